@@ -1,0 +1,195 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper of the plain C FP64 oracle.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+this package never imports the product library.
+
+The oracle evaluates the submatrix method with the sign function taken from
+a cyclic Jacobi eigendecomposition (see ``smx_oracle.c`` for the passages of
+the paper each step follows).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "smx_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP over groups)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class GroupInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nrow_blk", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("n_neg", ctypes.c_int32),
+                ("n_zero", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("min_abs_lambda", ctypes.c_double), ("max_abs_lambda", ctypes.c_double),
+                ("inf_norm", ctypes.c_double), ("eig_residual", ctypes.c_double),
+                ("orth_residual", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.oracle_jacobi.argtypes = [i32, P(f64), P(f64), P(f64), i32]
+        L.oracle_jacobi.restype = i32
+        L.oracle_dense_map.argtypes = [i32, P(f64), i32, f64, P(f64), P(f64), P(f64)]
+        L.oracle_dense_map.restype = i32
+        L.oracle_group_dims.argtypes = [i32, P(i32), P(i64), P(i32), i32, P(i32), P(i32), P(i32), P(i32)]
+        L.oracle_group_dims.restype = i32
+        L.oracle_submatrix.argtypes = [i32, P(i32), P(i64), P(i32), P(f64), i32, P(i32), P(i32),
+                                       f64, f64, P(i32), i32, i32, P(f64), P(f64), P(f64),
+                                       P(GroupInfo)]
+        L.oracle_submatrix.restype = i32
+        L.oracle_group_eig.argtypes = [i32, P(i32), P(i64), P(i32), P(f64), i32, P(i32), f64,
+                                       P(i32), P(f64), P(f64), P(GroupInfo)]
+        L.oracle_group_eig.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def jacobi(a: np.ndarray, max_sweeps: int = 60):
+    """Eigenpairs of a symmetric matrix: (lam ascending, Q, sweeps)."""
+    a = np.asfortranarray(a, dtype=np.float64).copy(order="F")
+    n = a.shape[0]
+    lam = np.zeros(n)
+    q = np.zeros((n, n), order="F")
+    sw = lib().oracle_jacobi(n, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             _p(lam, ctypes.c_double),
+                             q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), max_sweeps)
+    return lam, q, int(sw)
+
+
+def _dense_map(a, mode, kT):
+    a = np.asfortranarray(a, dtype=np.float64)
+    n = a.shape[0]
+    out = np.zeros((n, n), order="F")
+    st = lib().oracle_dense_map(n, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mode, kT,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None)
+    if st != 0:
+        raise RuntimeError(f"oracle_dense_map failed: {st}")
+    return np.array(out)
+
+
+def dense_sign(a: np.ndarray) -> np.ndarray:
+    """sign(A) of a symmetric matrix with the zero-eigenvalue extension."""
+    return _dense_map(a, 0, 0.0)
+
+
+def dense_density(a: np.ndarray, kT: float = 0.0) -> np.ndarray:
+    """D = Q occ(Lambda) Q^T of a symmetric (already shifted) matrix."""
+    return _dense_map(a, 1, kT)
+
+
+def _bsc_args(s):
+    blk = np.ascontiguousarray(s.blk_size, dtype=np.int32)
+    cp = np.ascontiguousarray(s.col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(s.row_idx, dtype=np.int32)
+    gp = np.ascontiguousarray(s.grp_ptr, dtype=np.int32)
+    gb = np.ascontiguousarray(s.grp_blocks, dtype=np.int32)
+    return blk, cp, ri, gp, gb
+
+
+def group_dims(s):
+    """(n_g, |R(g)|) for every group of a BlockSparse system."""
+    blk, cp, ri, gp, gb = _bsc_args(s)
+    ng = s.ngroups
+    n_out = np.zeros(ng, dtype=np.int32)
+    m_out = np.zeros(ng, dtype=np.int32)
+    st = lib().oracle_group_dims(s.nblk, _p(blk, ctypes.c_int32), _p(cp, ctypes.c_int64),
+                                 _p(ri, ctypes.c_int32), ng, _p(gp, ctypes.c_int32),
+                                 _p(gb, ctypes.c_int32), _p(n_out, ctypes.c_int32),
+                                 _p(m_out, ctypes.c_int32))
+    if st != 0:
+        raise RuntimeError(f"oracle_group_dims failed: {st}")
+    return n_out, m_out
+
+
+@dataclass
+class OracleResult:
+    d_values: np.ndarray      # K's layout; NaN outside the processed groups' columns
+    n_elec: float             # Tr D over the processed columns
+    energy: float             # Tr(DK) over the processed columns
+    info: list                # per processed group: dict of GroupInfo fields
+    groups: np.ndarray        # processed group ids
+
+
+def submatrix(s, mu: float | None = None, kT: float = 0.0, which=None,
+              nthreads: int | None = None, values: np.ndarray | None = None) -> OracleResult:
+    """Run the submatrix method (Jacobi sign) on a BlockSparse system."""
+    blk, cp, ri, gp, gb = _bsc_args(s)
+    vals = _f64(s.values if values is None else values)
+    mu = s.mu if mu is None else mu
+    if which is None:
+        which_arr = np.arange(s.ngroups, dtype=np.int32)
+        wptr = None
+    else:
+        which_arr = np.ascontiguousarray(which, dtype=np.int32)
+        wptr = _p(which_arr, ctypes.c_int32)
+    nj = len(which_arr)
+    d = np.full(vals.shape, np.nan)
+    info = (GroupInfo * max(nj, 1))()
+    n_e = ctypes.c_double()
+    e_e = ctypes.c_double()
+    nth = nthreads if nthreads else (os.cpu_count() or 1)
+    st = lib().oracle_submatrix(s.nblk, _p(blk, ctypes.c_int32), _p(cp, ctypes.c_int64),
+                                _p(ri, ctypes.c_int32), _p(vals, ctypes.c_double), s.ngroups,
+                                _p(gp, ctypes.c_int32), _p(gb, ctypes.c_int32), float(mu),
+                                float(kT), wptr, nj, int(nth), _p(d, ctypes.c_double),
+                                ctypes.byref(n_e), ctypes.byref(e_e), info)
+    if st != 0:
+        raise RuntimeError(f"oracle_submatrix failed: {st}")
+    recs = [{f: getattr(info[i], f) for f, _ in GroupInfo._fields_} for i in range(nj)]
+    return OracleResult(d, n_e.value, e_e.value, recs, which_arr)
+
+
+def group_eig(s, g: int, mu: float | None = None, values: np.ndarray | None = None):
+    """(R(g), lam, Q, info) for group g's shifted submatrix K[R, R] - mu I."""
+    blk, cp, ri, gp, gb = _bsc_args(s)
+    vals = _f64(s.values if values is None else values)
+    mu = s.mu if mu is None else mu
+    n_g, m_g = group_dims(s)
+    n, m = int(n_g[g]), int(m_g[g])
+    cols = np.ascontiguousarray(gb[gp[g]:gp[g + 1]], dtype=np.int32)
+    rows = np.zeros(max(s.nblk, 1), dtype=np.int32)
+    lam = np.zeros(n)
+    q = np.zeros(n * n)
+    gi = GroupInfo()
+    st = lib().oracle_group_eig(s.nblk, _p(blk, ctypes.c_int32), _p(cp, ctypes.c_int64),
+                                _p(ri, ctypes.c_int32), _p(vals, ctypes.c_double), len(cols),
+                                _p(cols, ctypes.c_int32), float(mu), _p(rows, ctypes.c_int32),
+                                _p(lam, ctypes.c_double), _p(q, ctypes.c_double), ctypes.byref(gi))
+    if st != 0:
+        raise RuntimeError(f"oracle_group_eig failed: {st}")
+    info = {f: getattr(gi, f) for f, _ in GroupInfo._fields_}
+    return rows[:m].copy(), lam, q.reshape(n, n, order="F"), info

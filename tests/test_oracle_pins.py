@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the property it checks.  None of them re-types the oracle's
+own formulas: they use closed forms (tight-binding chains and rings),
+algebraic identities of the sign function, structural identities of the
+submatrix method, and LAPACK (numpy.linalg.eigh) as an independent third
+route.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from waterbox import dense_to_bsc, tb_chain, random_block_system, water_system, block_offsets
+
+
+# ---------------------------------------------------------------- helpers
+
+def open_chain_eig(n, alpha, beta):
+    """Closed form: eps_k = alpha + 2 beta cos(k pi/(n+1)), v_k(j) = sqrt(2/(n+1)) sin(j k pi/(n+1))."""
+    k = np.arange(1, n + 1)
+    eps = alpha + 2.0 * beta * np.cos(k * math.pi / (n + 1))
+    j = np.arange(1, n + 1)
+    v = math.sqrt(2.0 / (n + 1)) * np.sin(np.outer(j, k) * math.pi / (n + 1))
+    return eps, v
+
+
+def open_chain_density(n, alpha, beta, mu, kT=0.0):
+    eps, v = open_chain_eig(n, alpha, beta)
+    if kT > 0:
+        w = 1.0 / (1.0 + np.exp((eps - mu) / kT))
+    else:
+        assert np.min(np.abs(eps - mu)) > 1e-9, "closed form needs mu off the spectrum"
+        w = (eps < mu).astype(float)
+    return (v * w) @ v.T, eps, w
+
+
+def chain_matrix(n, alpha, beta, periodic=False):
+    h = alpha * np.eye(n)
+    i = np.arange(n - 1)
+    h[i, i + 1] = beta
+    h[i + 1, i] = beta
+    if periodic:
+        h[0, n - 1] = h[n - 1, 0] = beta
+    return h
+
+
+def bsc_block(s, d_values, i, j):
+    """Block (i, j) of a result stored in s's layout, as a dense array."""
+    voff = s.val_off()
+    for p in range(s.col_ptr[j], s.col_ptr[j + 1]):
+        if s.row_idx[p] == i:
+            bi, bj = s.blk_size[i], s.blk_size[j]
+            return d_values[voff[p]:voff[p + 1]].reshape(bj, bi).T
+    raise KeyError((i, j))
+
+
+def scatter_dense(s, d_values):
+    """Dense n x n array holding the stored blocks of a result (0 elsewhere)."""
+    return s.with_values(d_values).to_dense()
+
+
+def lapack_submatrix_d(s, mu, kT=0.0):
+    """Independent route: dense index sets + numpy eigh, then keep the pattern."""
+    kd = s.to_dense()
+    boff = block_offsets(s.blk_size)
+    n = s.n
+    out = np.zeros((n, n))
+    stored = np.zeros((s.nblk, s.nblk), dtype=bool)
+    for j in range(s.nblk):
+        stored[s.row_idx[s.col_ptr[j]:s.col_ptr[j + 1]], j] = True
+    for g in range(s.ngroups):
+        cols = s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]
+        rows = np.nonzero(stored[:, cols].any(axis=1))[0]
+        idx = np.concatenate([np.arange(boff[r], boff[r + 1]) for r in rows])
+        a = kd[np.ix_(idx, idx)] - mu * np.eye(len(idx))
+        lam, q = np.linalg.eigh(a)
+        w = 1.0 / (1.0 + np.exp(lam / kT)) if kT > 0 else (lam < 0).astype(float)
+        dg = (q * w) @ q.T
+        where = {int(b): k for k, b in enumerate(np.repeat(rows, s.blk_size[rows]))}
+        pos = np.searchsorted(idx, np.arange(n))
+        for j in cols:
+            for i in rows:
+                if not stored[i, j]:
+                    continue
+                ri = np.arange(boff[i], boff[i + 1])
+                cj = np.arange(boff[j], boff[j + 1])
+                out[np.ix_(ri, cj)] = dg[np.ix_(pos[ri], pos[cj])]
+        del where
+    return out
+
+
+# ---------------------------------------------------------------- Jacobi
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40])
+def test_jacobi_open_chain_closed_form(oracle_lib, n):
+    h = chain_matrix(n, 0.3, -0.7)
+    lam, q, sw = oracle_lib.jacobi(h)
+    eps, v = open_chain_eig(n, 0.3, -0.7)
+    order = np.argsort(eps)
+    assert sw >= 0
+    np.testing.assert_allclose(lam, eps[order], atol=1e-13)
+    # eigenvectors up to sign (the chain spectrum is simple)
+    for k in range(n):
+        vk = v[:, order[k]]
+        assert abs(abs(vk @ q[:, k]) - 1.0) < 1e-12
+
+
+def test_jacobi_random_vs_lapack_and_residuals(oracle_lib):
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(60, 60))
+    a = a + a.T
+    lam, q, sw = oracle_lib.jacobi(a)
+    assert 0 <= sw < 60
+    np.testing.assert_allclose(lam, np.linalg.eigvalsh(a), atol=1e-12)
+    assert np.abs(a @ q - q * lam).max() <= 1e-12 * np.abs(a).sum(1).max()
+    assert np.abs(q.T @ q - np.eye(60)).max() <= 1e-12
+
+
+def test_jacobi_diagonal_and_degenerate(oracle_lib):
+    d = np.array([3.0, -1.0, 2.0, -1.0, 0.0])
+    lam, q, sw = oracle_lib.jacobi(np.diag(d))
+    np.testing.assert_array_equal(lam, np.sort(d))
+    assert sw == 0
+    # a matrix with a degenerate eigenvalue: I + u u^T has eigenvalues {1 (x n-1), 1 + |u|^2}
+    u = np.arange(1.0, 6.0)
+    lam, q, _ = oracle_lib.jacobi(np.eye(5) + np.outer(u, u))
+    np.testing.assert_allclose(lam, [1, 1, 1, 1, 1 + u @ u], atol=1e-12)
+
+
+# ---------------------------------------------------------------- sign function
+
+def test_sign_two_by_two_closed_form(oracle_lib):
+    # [[a, b], [b, -a]]^2 = (a^2 + b^2) I, so sign = A / sqrt(a^2 + b^2)
+    for a, b in [(0.3, 0.4), (-2.0, 0.1), (0.0, 1.0), (1e-3, -5.0)]:
+        m = np.array([[a, b], [b, -a]])
+        np.testing.assert_allclose(oracle_lib.dense_sign(m), m / math.hypot(a, b), atol=1e-15)
+
+
+def test_sign_involutory_reflection(oracle_lib):
+    # A = c * (I - 2 v v^T) with |v| = 1 satisfies A^2 = c^2 I, sign(A) = A / c for c > 0
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=9)
+    v /= np.linalg.norm(v)
+    refl = np.eye(9) - 2.0 * np.outer(v, v)
+    for c in (0.25, 3.0):
+        np.testing.assert_allclose(oracle_lib.dense_sign(c * refl), refl, atol=1e-13)
+
+
+def test_sign_diagonal_is_signum(oracle_lib):
+    d = np.array([-2.0, 0.5, 1e-3, -7.0, 0.0, 4.0])
+    s = oracle_lib.dense_sign(np.diag(d))
+    np.testing.assert_array_equal(s, np.diag(np.sign(d)))     # sign(0) = 0 extension
+
+
+def test_sign_square_identity_and_commutes(oracle_lib):
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(30, 30))
+    a = (a + a.T) / 2
+    s = oracle_lib.dense_sign(a)
+    assert np.abs(s @ s - np.eye(30)).max() < 1e-13
+    assert np.abs(s @ a - a @ s).max() < 1e-13
+    assert np.abs(s - s.T).max() < 1e-13
+
+
+def test_density_idempotent_and_trace(oracle_lib):
+    rng = np.random.default_rng(6)
+    a = rng.normal(size=(25, 25))
+    a = (a + a.T) / 2
+    d = oracle_lib.dense_density(a)
+    assert np.abs(d @ d - d).max() < 1e-13
+    nneg = int((np.linalg.eigvalsh(a) < 0).sum())
+    assert abs(np.trace(d) - nneg) < 1e-12
+
+
+def test_ring_zero_modes_extension(oracle_lib):
+    """Periodic ring, N = 0 mod 4, at mu = alpha: two exact zero modes get weight 1/2."""
+    n, beta = 16, -1.0
+    h = chain_matrix(n, 0.0, beta, periodic=True)
+    k = np.arange(n)
+    eps = 2.0 * beta * np.cos(2.0 * math.pi * k / n)
+    w = np.where(eps < 0, 1.0, 0.0)
+    w[[n // 4, 3 * n // 4]] = 0.5
+    ii = np.arange(n)
+    d_exact = np.zeros((n, n))
+    for kk in range(n):
+        d_exact += w[kk] * np.cos(2 * math.pi * kk * (ii[:, None] - ii[None, :]) / n) / n
+    d = oracle_lib.dense_density(h)
+    np.testing.assert_allclose(d, d_exact, atol=1e-13)
+    assert abs(np.trace(d) - n / 2) < 1e-12
+    # same through the block-sparse path: one group holding every block column
+    s = tb_chain(n, 4, 0.0, beta, periodic=True, pattern="dense").with_groups([list(range(4))])
+    r = oracle_lib.submatrix(s)
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), d_exact, atol=1e-13)
+    assert abs(r.n_elec - n / 2) < 1e-12
+    assert r.info[0]["n_zero"] == 2
+
+
+# ---------------------------------------------------------------- submatrix method
+
+@pytest.mark.parametrize("blk", [1, 3, 5])
+def test_dense_pattern_chain_closed_form(oracle_lib, blk):
+    """Dense pattern: every submatrix is the whole chain, so D is the exact closed form."""
+    n, alpha, beta, mu = 30, 0.1, -0.8, 0.05
+    s = tb_chain(n, blk, alpha, beta, pattern="dense", mu=mu)
+    r = oracle_lib.submatrix(s)
+    d_cf, eps, w = open_chain_density(n, alpha, beta, mu)
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), d_cf, atol=1e-13)
+    assert abs(r.n_elec - w.sum()) < 1e-12                       # integer electron count
+    assert abs(r.energy - (eps * w).sum()) < 1e-12                # E = sum of occupied eps
+
+
+def test_band_chain_submatrices_are_subchains(oracle_lib):
+    """Band pattern, one group per block column: the submatrix of column J is the
+    open chain spanning blocks J-1..J+1, so each stored D block is a closed form."""
+    n, blk, alpha, beta, mu = 24, 4, 0.0, -1.0, 0.1
+    s = tb_chain(n, blk, alpha, beta, pattern="band", mu=mu)
+    r = oracle_lib.submatrix(s)
+    nblk = n // blk
+    for j in range(nblk):
+        lo, hi = max(0, j - 1), min(nblk - 1, j + 1)
+        m = (hi - lo + 1) * blk
+        d_sub, _, _ = open_chain_density(m, alpha, beta, mu)
+        for i in range(lo, hi + 1):
+            got = bsc_block(s, r.d_values, i, j)
+            want = d_sub[(i - lo) * blk:(i - lo + 1) * blk, (j - lo) * blk:(j - lo + 1) * blk]
+            np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+def test_fermi_dense_chain_closed_form(oracle_lib):
+    n, alpha, beta, mu, kT = 20, 0.0, -1.0, 0.3, 0.05
+    s = tb_chain(n, 2, alpha, beta, pattern="dense", mu=mu)
+    r = oracle_lib.submatrix(s, kT=kT)
+    d_cf, eps, w = open_chain_density(n, alpha, beta, mu, kT)
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), d_cf, atol=1e-13)
+    assert abs(r.n_elec - w.sum()) < 1e-12
+
+
+def test_dense_pattern_water_identity(oracle_lib):
+    """Cutoff beyond half the box diagonal: every submatrix equals K, D equals the exact D."""
+    s = water_system(n_mol=4, box=5.0, r_cut=100.0, seed=21)
+    assert s.nnzb == s.nblk ** 2
+    r = oracle_lib.submatrix(s)
+    kd = s.to_dense()
+    lam, q = np.linalg.eigh(kd - s.mu * np.eye(s.n))
+    d_exact = (q * (lam < 0)) @ q.T
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), d_exact, atol=1e-12)
+    assert abs(r.n_elec - (lam < 0).sum()) < 1e-11
+    assert abs(r.energy - (lam[lam < 0] + s.mu).sum()) < 1e-11
+
+
+def test_block_diagonal_identity(oracle_lib):
+    """Only intramolecular blocks stored and groups = molecules: D is exact per molecule."""
+    s = water_system(n_mol=8, box=6.2, r_cut=0.0, seed=22, pattern="blockdiag")
+    r = oracle_lib.submatrix(s)
+    kd = s.to_dense()
+    lam, q = np.linalg.eigh(kd)
+    d_exact = (q * (lam < 0)) @ q.T
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), d_exact, atol=1e-12)
+
+
+def test_general_pattern_vs_lapack_route(oracle_lib):
+    """Ragged block sizes, sparse pattern, mixed group sizes vs dense indexing + LAPACK."""
+    sizes = [3, 1, 7, 2, 5, 4, 6, 1, 8, 3, 2, 5]
+    groups = [[0, 1], [2], [3, 4, 5], [6], [7, 8, 9], [10, 11]]
+    s = random_block_system(31, sizes, density=0.35, coupling=0.06, groups=groups, mu=0.02)
+    r = oracle_lib.submatrix(s)
+    want = lapack_submatrix_d(s, s.mu)
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), want, atol=1e-12)
+    # Fermi variant
+    r2 = oracle_lib.submatrix(s, kT=0.1)
+    want2 = lapack_submatrix_d(s, s.mu, kT=0.1)
+    np.testing.assert_allclose(scatter_dense(s, r2.d_values), want2, atol=1e-12)
+
+
+def test_water16_vs_lapack_route(oracle_lib):
+    s = water_system(n_mol=16, box=7.8, r_cut=4.0, seed=1)
+    r = oracle_lib.submatrix(s)
+    want = lapack_submatrix_d(s, s.mu)
+    np.testing.assert_allclose(scatter_dense(s, r.d_values), want, atol=1e-12)
+    for rec in r.info:
+        assert rec["sweeps"] >= 0
+        assert rec["eig_residual"] <= 1e-12 * rec["inf_norm"]
+        assert rec["orth_residual"] <= 1e-12
+
+
+def test_block_relabelling_invariance(oracle_lib):
+    """Permuting the block labels permutes D the same way (assembly/scatter indexing)."""
+    sizes = [4, 2, 6, 3, 5, 2, 4]
+    s = random_block_system(41, sizes, density=0.5, coupling=0.05, groups="column")
+    kd = s.to_dense()
+    stored = np.zeros((s.nblk, s.nblk), dtype=bool)
+    for j in range(s.nblk):
+        stored[s.row_idx[s.col_ptr[j]:s.col_ptr[j + 1]], j] = True
+    perm = np.array([3, 0, 6, 2, 5, 1, 4])                       # new block b = old perm[b]
+    boff = block_offsets(s.blk_size)
+    idx = np.concatenate([np.arange(boff[p], boff[p + 1]) for p in perm])
+    s2 = dense_to_bsc(kd[np.ix_(idx, idx)], np.asarray(sizes)[perm], stored[np.ix_(perm, perm)])
+    r1 = oracle_lib.submatrix(s)
+    r2 = oracle_lib.submatrix(s2)
+    d1 = scatter_dense(s, r1.d_values)
+    d2 = scatter_dense(s2, r2.d_values)
+    np.testing.assert_allclose(d2, d1[np.ix_(idx, idx)], atol=1e-13)
+
+
+def test_subset_matches_full(oracle_lib):
+    s = random_block_system(51, [3, 5, 2, 4, 6, 1], density=0.4, groups="pairs")
+    full = oracle_lib.submatrix(s)
+    part = oracle_lib.submatrix(s, which=[2, 0])
+    ok = ~np.isnan(part.d_values)
+    assert ok.any() and (~ok).any()
+    np.testing.assert_array_equal(part.d_values[ok], full.d_values[ok])
+
+
+def test_group_eig_matches_submatrix(oracle_lib):
+    s = water_system(n_mol=4, box=5.0, r_cut=3.0, seed=23)
+    rows, lam, q, info = oracle_lib.group_eig(s, 1)
+    n_g, m_g = oracle_lib.group_dims(s)
+    assert len(rows) == m_g[1] and len(lam) == n_g[1] == info["n"]
+    assert np.all(np.diff(rows) > 0)
+    assert np.abs(q.T @ q - np.eye(len(lam))).max() < 1e-12
