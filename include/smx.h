@@ -1,0 +1,223 @@
+/*
+ * smx.h - C ABI of libsmx: density matrices of a block-sparse, symmetric,
+ * orthogonalised Kohn-Sham matrix by the submatrix method with a
+ * Newton-Schulz matrix-sign iteration, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Lass, Schade, Kuehne, Plessl, "A Submatrix-Based Method for
+ * Approximate Matrix Function Evaluation in the Quantum Chemistry Code
+ * CP2K"):
+ *
+ *   For every group g of block columns of K (Sec. III-A overview applied per
+ *   block column, Sec. IV-C; several block columns may be combined into one
+ *   submatrix, Sec. IV-C "Generating Submatrices From Multiple Block
+ *   Columns"):
+ *     1. R(g) = the block rows stored in any column of g (ascending);
+ *        A_g = K[R(g), R(g)] - mu I, unstored blocks taken as zero.
+ *     2. S_g = sign(A_g) (Eq. sign / signev), evaluated by the second-order
+ *        Newton-Schulz iteration X_{k+1} = X_k (3I - X_k^2) / 2 (Sec. II-B)
+ *        from X_0 = A_g / s_g, where s_g = ||A_g||_inf is a Gershgorin bound
+ *        on the spectral radius; stopped when max|X_k^2 - I| <= tol.
+ *     3. The group's own block columns of D_g = (I - S_g) / 2 (Eq. DsignSym
+ *        with S = I) are written into D, only at the block positions stored
+ *        in K (the result keeps K's sparsity pattern).
+ *   Then N = Tr D (Sec. IV-H, no spin factor) and E = Tr(D K) (Eq.
+ *   bandenergy), reduced in FP64.
+ *
+ * Conventions
+ *   - Every function returns an int32_t status: SMX_OK (0) or a negative
+ *     SMX_E_* code.  Nothing throws across the ABI.  smx_last_error() gives a
+ *     message for the last failing call on a context.
+ *   - A context is not thread-safe; use one per host thread.
+ *   - Input arrays are borrowed for the duration of the call only and are
+ *     copied.  Outputs go to caller-owned buffers.  The context owns its
+ *     device memory and frees it in smx_destroy().
+ *   - Device work is enqueued on the stream given to smx_set_stream() (the
+ *     null stream by default), e.g. the current PyTorch stream.  Functions
+ *     that return host scalars synchronise that stream.
+ *
+ * Block-sparse layout (BSC, "block compressed sparse column"):
+ *   nblk block rows/columns with sizes blk_size[0..nblk-1] (1..1024);
+ *   block column J holds storage positions col_ptr[J] .. col_ptr[J+1]-1
+ *   (col_ptr int64, col_ptr[0] = 0), whose block rows row_idx[p] ascend
+ *   strictly.  BOTH triangles are stored and every diagonal block must be
+ *   present.  Block (I, J) is a dense column-major blk_size[I] x
+ *   blk_size[J] array at the running offset of all preceding blocks in
+ *   storage order, so values has sum_p blk_size[row_idx[p]] *
+ *   blk_size[col(p)] doubles.  D is returned in exactly the same layout.
+ */
+#ifndef SMX_H
+#define SMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SMX_OK                 0
+#define SMX_E_INVALID         -1   /* bad argument, size or layout            */
+#define SMX_E_STATE           -2   /* call order (e.g. evaluate before load)  */
+#define SMX_E_NOT_SYMMETRIC   -3   /* |K_IJ - K_JI^T| > 1e-12 max|K|          */
+#define SMX_E_NONFINITE       -4   /* NaN/Inf in K or in an iterate           */
+#define SMX_E_UNSUPPORTED     -5   /* option not implemented on this path     */
+#define SMX_E_NOMEM           -6   /* device or host allocation failed        */
+#define SMX_E_HIP             -7   /* HIP runtime error                        */
+#define SMX_E_NOT_CONVERGED   -8   /* a group reached max_iter; D is written  */
+
+/* ---- precision modes (smx_set_precision) ------------------------------- */
+#define SMX_FP64      0   /* every Newton-Schulz product in FP64 (MFMA f64)      */
+#define SMX_BF16_3W   1   /* bulk products as 3-word BF16 splits (6 MFMA bf16
+                             products, FP32 accumulation), then FP64 polish     */
+#define SMX_BF16_1W   2   /* bulk products in plain BF16 (FP32 accumulation),
+                             then FP64 polish                                    */
+#define SMX_FP32      3   /* bulk products in FP32 (MFMA f32), then FP64 polish  */
+
+typedef struct smx_context *smx_ctx;
+
+typedef struct {
+    int32_t ngroups;          /* number of submatrices                            */
+    int32_t n_min, n_max;     /* min / max submatrix dimension n_g                */
+    int32_t iters_min, iters_max;  /* Newton-Schulz iterations per group (bulk +
+                                      polish), i.e. the k at which X_k was taken   */
+    int32_t n_not_converged;  /* groups that hit max_iter                         */
+    int32_t precision;        /* precision mode of the last evaluation            */
+    int32_t pad0;
+    double  n_mean;           /* mean n_g                                         */
+    double  iters_mean;
+    double  resid_max;        /* max over groups of the last computed max|X^2 - I| */
+    double  algo_flops;       /* sum_g 4 n_g^3 k_g (two dense products per step)  */
+    double  exec_flops;       /* flops issued to the matrix cores (padding, half
+                                 tiles and multi-word products included)           */
+    double  time_gather_ms;   /* device time of the last evaluation, per phase    */
+    double  time_iterate_ms;
+    double  time_scatter_ms;
+    double  time_total_ms;
+    double  workspace_bytes;  /* device memory held by the context                */
+} smx_stats;
+
+/* Lifetime.  `device` is a HIP device ordinal; the context makes it current
+ * in every call. */
+int32_t smx_create(int32_t device, smx_ctx *out);
+int32_t smx_destroy(smx_ctx ctx);
+
+/* Message for the last failing call on ctx (never NULL; valid until the next
+ * call on ctx).  smx_last_error(NULL) describes the last smx_create failure. */
+const char *smx_last_error(smx_ctx ctx);
+
+/* Enqueue all device work on `hip_stream` (a hipStream_t; NULL = null stream). */
+int32_t smx_set_stream(smx_ctx ctx, void *hip_stream);
+
+/*
+ * Load K (Sec. II-C: DBCSR-style dense blocks with a sparse block index).
+ * blk_size, col_ptr and row_idx are host arrays; `values` is a host pointer,
+ * or a device pointer when values_on_device != 0.  Validates the layout
+ * (SMX_E_INVALID), finiteness (SMX_E_NONFINITE) and symmetry
+ * max|K_IJ - K_JI^T| <= 1e-12 max|K| (SMX_E_NOT_SYMMETRIC).  Resets the
+ * groups to one group per block column and invalidates any result.
+ */
+int32_t smx_load_k(smx_ctx ctx, int32_t nblk, const int32_t *blk_size,
+                   const int64_t *col_ptr, const int32_t *row_idx,
+                   const double *values, int32_t values_on_device);
+
+/*
+ * Replace K's values, keeping the pattern of the last smx_load_k (the plan
+ * is reused).  Same validation of values as smx_load_k.
+ */
+int32_t smx_update_values(smx_ctx ctx, const double *values, int32_t values_on_device);
+
+/*
+ * Partition the block columns into submatrix groups (Sec. IV-C): group g
+ * owns block columns grp_blocks[grp_ptr[g] .. grp_ptr[g+1]-1].  Every block
+ * column must appear in exactly one group (else SMX_E_INVALID).  Host arrays.
+ */
+int32_t smx_set_groups(smx_ctx ctx, int32_t ngroups, const int32_t *grp_ptr,
+                       const int32_t *grp_blocks);
+
+/* Chemical potential mu (Hartree) of D = (I - sign(K - mu I)) / 2. */
+int32_t smx_set_mu(smx_ctx ctx, double mu);
+
+/* Electronic temperature kT in Hartree.  Only kT == 0 (the sign function) is
+ * implemented on the GPU; kT > 0 makes smx_evaluate return SMX_E_UNSUPPORTED. */
+int32_t smx_set_temperature(smx_ctx ctx, double kT);
+
+/* One of SMX_FP64, SMX_BF16_3W, SMX_BF16_1W, SMX_FP32. */
+int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
+
+/*
+ * Stopping rule of the iteration: stop at the first k with
+ * max|X_k^2 - I| <= tol (FP64 products), at most max_iter steps.  In the
+ * reduced-precision modes the bulk runs until max|X_k^2 - I| <= switch_tol
+ * (or stops improving) and is followed by n_polish FP64 steps (>= 1).
+ * Defaults: tol 1e-12, max_iter 100, n_polish 2, switch_tol 1e-3.
+ */
+int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
+                            int32_t n_polish, double switch_tol);
+
+/*
+ * Evaluate D, N and E for the current K, groups and mu.  The work is
+ * enqueued on the context's stream; the call returns after enqueueing it
+ * (the host only polls a small counter to stop the iteration when every
+ * group has converged).  D stays resident on the device.
+ */
+int32_t smx_evaluate(smx_ctx ctx);
+
+/* Wait for the last evaluation; SMX_E_NOT_CONVERGED if any group reached
+ * max_iter (D is still written), SMX_E_NONFINITE if an iterate was not finite. */
+int32_t smx_wait(smx_ctx ctx);
+
+/* Copy D (K's layout, same number of doubles as K's values) into `out`
+ * (host, or device when out_on_device != 0).  Synchronises. */
+int32_t smx_get_d(smx_ctx ctx, double *out, int32_t out_on_device);
+
+/* N = Tr D and E = Tr(D K) of the last evaluation, FP64, reduced in a fixed
+ * order (bitwise reproducible).  Synchronise. */
+int32_t smx_trace(smx_ctx ctx, double *n_out);
+int32_t smx_energy(smx_ctx ctx, double *e_out);
+
+/* Summary of the last evaluation.  Synchronises. */
+int32_t smx_get_stats(smx_ctx ctx, smx_stats *out);
+
+/*
+ * Per-group details of the last evaluation (host arrays of ngroups entries,
+ * any may be NULL): submatrix dimension n_g, iterations k_g, Gershgorin
+ * scale s_g, and the last computed max|X^2 - I|.  Synchronises.
+ */
+int32_t smx_get_group_info(smx_ctx ctx, int32_t *n_g, int32_t *iters,
+                           double *scale, double *resid);
+
+/*
+ * Dense submatrix of group g (Sec. III-A: the submatrix a_i and its result
+ * f(a_i)), column-major n_g x n_g into host array `out` with leading
+ * dimension ld >= n_g:
+ *   what = 0: A_g = K[R(g), R(g)] - mu I as gathered on the device
+ *             (needs a loaded K; uses the current groups and mu);
+ *   what = 1: the sign S_g of the last evaluation (the whole submatrix,
+ *             not only the group's own columns).
+ * n_out (nullable) receives n_g.  With out == NULL only n_g is returned.
+ * Synchronises.  what = 0 overwrites scratch that what = 1 does not read.
+ */
+int32_t smx_get_submatrix(smx_ctx ctx, int32_t g, int32_t what, double *out, int32_t ld,
+                          int32_t *n_out);
+
+/* Number of groups and stored values of the loaded problem. */
+int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
+
+/*
+ * Per-launch profile of the matrix-core product kernels of the last
+ * evaluation, in launch order (square, update, square, update, ...):
+ * device time in ms measured with HIP events on the context's stream, and
+ * the algorithmic flops of the launch (2 n_g^3 for every group the launch
+ * works on, i.e. one dense n_g x n_g product).  Writes min(cap, count)
+ * entries to the host arrays (either may be NULL) and the launch count to
+ * *count.  Synchronises.
+ */
+int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,
+                               int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMX_H */

@@ -1,0 +1,342 @@
+"""Python binding of libsmx (the C ABI in include/smx.h).
+
+Argument marshalling only: every step of the path (gather, Newton-Schulz
+products, scatter, reductions) runs in the HIP kernels of libsmx.so.  The
+library must have been built (``python paper_2004_10811_amd/build.py`` or
+``__graft_entry__.build()``); importing this package without it raises.
+
+PyTorch is optional here and only provides device memory and streams:
+arrays may be numpy (host) or torch tensors (host or device).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsmx.so")
+
+SMX_OK = 0
+SMX_E_INVALID = -1
+SMX_E_STATE = -2
+SMX_E_NOT_SYMMETRIC = -3
+SMX_E_NONFINITE = -4
+SMX_E_UNSUPPORTED = -5
+SMX_E_NOMEM = -6
+SMX_E_HIP = -7
+SMX_E_NOT_CONVERGED = -8
+
+SMX_FP64 = 0
+SMX_BF16_3W = 1
+SMX_BF16_1W = 2
+SMX_FP32 = 3
+
+PRECISIONS = {"fp64": SMX_FP64, "bf16x3": SMX_BF16_3W, "bf16": SMX_BF16_1W, "fp32": SMX_FP32}
+
+# Every function the header declares, with (restype, argtypes).
+_P = ctypes.POINTER
+_i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class SmxStats(ctypes.Structure):
+    _fields_ = [("ngroups", _i32), ("n_min", _i32), ("n_max", _i32), ("iters_min", _i32),
+                ("iters_max", _i32), ("n_not_converged", _i32), ("precision", _i32), ("pad0", _i32),
+                ("n_mean", _f64), ("iters_mean", _f64), ("resid_max", _f64), ("algo_flops", _f64),
+                ("exec_flops", _f64), ("time_gather_ms", _f64), ("time_iterate_ms", _f64),
+                ("time_scatter_ms", _f64), ("time_total_ms", _f64), ("workspace_bytes", _f64)]
+
+
+SIGNATURES = {
+    "smx_create": (_i32, [_i32, _P(_vp)]),
+    "smx_destroy": (_i32, [_vp]),
+    "smx_last_error": (ctypes.c_char_p, [_vp]),
+    "smx_set_stream": (_i32, [_vp, _vp]),
+    "smx_load_k": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32]),
+    "smx_update_values": (_i32, [_vp, _vp, _i32]),
+    "smx_set_groups": (_i32, [_vp, _i32, _vp, _vp]),
+    "smx_set_mu": (_i32, [_vp, _f64]),
+    "smx_set_temperature": (_i32, [_vp, _f64]),
+    "smx_set_precision": (_i32, [_vp, _i32]),
+    "smx_set_convergence": (_i32, [_vp, _f64, _i32, _i32, _f64]),
+    "smx_evaluate": (_i32, [_vp]),
+    "smx_wait": (_i32, [_vp]),
+    "smx_get_d": (_i32, [_vp, _vp, _i32]),
+    "smx_trace": (_i32, [_vp, _P(_f64)]),
+    "smx_energy": (_i32, [_vp, _P(_f64)]),
+    "smx_get_stats": (_i32, [_vp, _P(SmxStats)]),
+    "smx_get_group_info": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "smx_get_sizes": (_i32, [_vp, _P(_i32), _P(_i64)]),
+    "smx_get_launch_profile": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
+    "smx_get_submatrix": (_i32, [_vp, _i32, _i32, _vp, _i32, _P(_i32)]),
+}
+
+_lib = None
+
+
+def _share_torch_hip_runtime():
+    """Make libsmx bind to PyTorch's HIP runtime when PyTorch is installed.
+
+    PyTorch ships its own libamdhip64 (same soname as the system one).  If the
+    system copy were loaded first, a later ``import torch`` would bring in a
+    second HIP runtime in the same process, and torch's streams and device
+    pointers would not be valid for libsmx.  Loading torch's copy first (by
+    path, without importing torch) makes every later load resolve to it.
+    """
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec is None or not spec.submodule_search_locations:
+            return
+        for loc in spec.submodule_search_locations:
+            p = os.path.join(loc, "lib", "libamdhip64.so")
+            if os.path.exists(p):
+                ctypes.CDLL(p, mode=ctypes.RTLD_GLOBAL)
+                return
+    except OSError:
+        pass
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsmx.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"libsmx.so is not built ({path}); run __graft_entry__.build()")
+        _share_torch_hip_runtime()
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class SmxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    """Raw address of a numpy array or torch tensor (host or device)."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def _on_device(a) -> int:
+    return 0 if isinstance(a, np.ndarray) else int(getattr(a, "is_cuda", False))
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+
+def _check(ctx, code):
+    if code != SMX_OK:
+        msg = load_library().smx_last_error(ctx).decode()
+        raise SmxError(code, msg)
+    return code
+
+
+def smx_create(device: int = 0):
+    lib = load_library()
+    h = _vp()
+    st = lib.smx_create(device, ctypes.byref(h))
+    if st != SMX_OK:
+        raise SmxError(st, lib.smx_last_error(None).decode())
+    return h
+
+
+def smx_destroy(ctx):
+    return _check(ctx, load_library().smx_destroy(ctx))
+
+
+def smx_set_stream(ctx, stream_handle: int):
+    return _check(ctx, load_library().smx_set_stream(ctx, _vp(stream_handle)))
+
+
+def smx_load_k(ctx, blk_size, col_ptr, row_idx, values):
+    blk = np.ascontiguousarray(blk_size, dtype=np.int32)
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+    if isinstance(values, np.ndarray):
+        values = np.ascontiguousarray(values, dtype=np.float64)
+    return _check(ctx, load_library().smx_load_k(ctx, len(blk), blk.ctypes.data, cp.ctypes.data,
+                                                  ri.ctypes.data, _ptr(values), _on_device(values)))
+
+
+def smx_update_values(ctx, values):
+    if isinstance(values, np.ndarray):
+        values = np.ascontiguousarray(values, dtype=np.float64)
+    return _check(ctx, load_library().smx_update_values(ctx, _ptr(values), _on_device(values)))
+
+
+def smx_set_groups(ctx, grp_ptr, grp_blocks):
+    gp = np.ascontiguousarray(grp_ptr, dtype=np.int32)
+    gb = np.ascontiguousarray(grp_blocks, dtype=np.int32)
+    return _check(ctx, load_library().smx_set_groups(ctx, len(gp) - 1, gp.ctypes.data, gb.ctypes.data))
+
+
+def smx_set_mu(ctx, mu: float):
+    return _check(ctx, load_library().smx_set_mu(ctx, float(mu)))
+
+
+def smx_set_temperature(ctx, kT: float):
+    return _check(ctx, load_library().smx_set_temperature(ctx, float(kT)))
+
+
+def smx_set_precision(ctx, mode):
+    if isinstance(mode, str):
+        mode = PRECISIONS[mode]
+    return _check(ctx, load_library().smx_set_precision(ctx, int(mode)))
+
+
+def smx_set_convergence(ctx, tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3):
+    return _check(ctx, load_library().smx_set_convergence(ctx, float(tol), int(max_iter),
+                                                           int(n_polish), float(switch_tol)))
+
+
+def smx_evaluate(ctx):
+    return _check(ctx, load_library().smx_evaluate(ctx))
+
+
+def smx_wait(ctx, allow_not_converged: bool = False):
+    st = load_library().smx_wait(ctx)
+    if allow_not_converged and st == SMX_E_NOT_CONVERGED:
+        return st
+    return _check(ctx, st)
+
+
+def smx_get_d(ctx, out):
+    return _check(ctx, load_library().smx_get_d(ctx, _ptr(out), _on_device(out)))
+
+
+def smx_trace(ctx) -> float:
+    v = _f64()
+    _check(ctx, load_library().smx_trace(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def smx_energy(ctx) -> float:
+    v = _f64()
+    _check(ctx, load_library().smx_energy(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def smx_get_stats(ctx) -> dict:
+    s = SmxStats()
+    _check(ctx, load_library().smx_get_stats(ctx, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in SmxStats._fields_ if f != "pad0"}
+
+
+def smx_get_sizes(ctx):
+    ng, nv = _i32(), _i64()
+    _check(ctx, load_library().smx_get_sizes(ctx, ctypes.byref(ng), ctypes.byref(nv)))
+    return ng.value, nv.value
+
+
+def smx_get_group_info(ctx):
+    ng, _ = smx_get_sizes(ctx)
+    n = np.zeros(ng, np.int32)
+    it = np.zeros(ng, np.int32)
+    sc = np.zeros(ng)
+    rs = np.zeros(ng)
+    _check(ctx, load_library().smx_get_group_info(ctx, n.ctypes.data, it.ctypes.data,
+                                                   sc.ctypes.data, rs.ctypes.data))
+    return dict(n=n, iters=it, scale=sc, resid=rs)
+
+
+def smx_get_launch_profile(ctx):
+    """(ms per launch, algorithmic flops per launch) of the product kernels."""
+    cnt = _i32()
+    _check(ctx, load_library().smx_get_launch_profile(ctx, 0, None, None, ctypes.byref(cnt)))
+    n = cnt.value
+    ms = np.zeros(n, np.float32)
+    fl = np.zeros(n)
+    _check(ctx, load_library().smx_get_launch_profile(ctx, n, ms.ctypes.data, fl.ctypes.data,
+                                                       ctypes.byref(cnt)))
+    return ms.astype(np.float64), fl
+
+
+def smx_get_submatrix(ctx, g: int, what: int = 1) -> np.ndarray:
+    """Group g's dense submatrix: what=0 the gathered A_g, what=1 its sign S_g."""
+    n = _i32()
+    _check(ctx, load_library().smx_get_submatrix(ctx, g, what, None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, n.value), order="F")
+    _check(ctx, load_library().smx_get_submatrix(ctx, g, what, out.ctypes.data, max(n.value, 1),
+                                                  ctypes.byref(n)))
+    return np.ascontiguousarray(out)
+
+
+# ---- convenience object -----------------------------------------------------
+
+@dataclass
+class Result:
+    d_values: object
+    n_elec: float
+    energy: float
+    status: int
+
+
+class Context:
+    """Owns one smx context; `system` is any object with the BSC fields
+    (blk_size, col_ptr, row_idx, values, grp_ptr, grp_blocks, mu)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.handle = smx_create(device)
+        if stream is not None:
+            smx_set_stream(self.handle, stream)
+        self.nvalues = 0
+
+    def close(self):
+        if self.handle is not None:
+            smx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, system, values=None):
+        vals = system.values if values is None else values
+        smx_load_k(self.handle, system.blk_size, system.col_ptr, system.row_idx, vals)
+        smx_set_groups(self.handle, system.grp_ptr, system.grp_blocks)
+        smx_set_mu(self.handle, getattr(system, "mu", 0.0))
+        _, self.nvalues = smx_get_sizes(self.handle)
+        return self
+
+    def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
+                  mu=None, kT=None):
+        smx_set_precision(self.handle, precision)
+        smx_set_convergence(self.handle, tol, max_iter, n_polish, switch_tol)
+        if mu is not None:
+            smx_set_mu(self.handle, mu)
+        if kT is not None:
+            smx_set_temperature(self.handle, kT)
+        return self
+
+    def evaluate(self, out=None, allow_not_converged=False) -> Result:
+        smx_evaluate(self.handle)
+        st = smx_wait(self.handle, allow_not_converged)
+        if out is None:
+            out = np.empty(self.nvalues)
+        smx_get_d(self.handle, out)
+        return Result(out, smx_trace(self.handle), smx_energy(self.handle), st)
+
+    def stats(self) -> dict:
+        return smx_get_stats(self.handle)
+
+    def group_info(self) -> dict:
+        return smx_get_group_info(self.handle)
+
+    def submatrix(self, g: int, what: int = 1) -> np.ndarray:
+        return smx_get_submatrix(self.handle, g, what)
+
+    def launch_profile(self):
+        return smx_get_launch_profile(self.handle)

@@ -1,0 +1,902 @@
+// Host side of libsmx: the C ABI declared in include/smx.h.
+//
+// Responsibilities: argument and layout validation, the per-pattern plan
+// (row sets R(g), gather/scatter tables, product tiles), device memory, and
+// the stream-ordered driver of one evaluation:
+//   gather + shift + Gershgorin bound -> Newton-Schulz steps (two batched
+//   matrix-core products per step, converged groups skip on the device) ->
+//   scatter of the own columns of D with energy/trace partials -> fixed-order
+//   reduction.
+#include "smx.h"
+#include "smx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace smx;
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), bytes);
+        if (e == hipSuccess) cap = std::max<size_t>(n, 1);
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    size_t bytes() const { return cap * sizeof(T); }
+};
+
+struct Plan {
+    int32_t ngroups = 0;
+    std::vector<GroupDesc> gd;
+    std::vector<TileDesc> tiles;
+    std::vector<int2> chunks;
+    std::vector<RowInfo> rinfo;
+    std::vector<int32_t> bmap;
+    std::vector<int32_t> boffs;
+    std::vector<ScatterDesc> scat;
+    int64_t work_elems = 0;
+    double exec_flops_per_step = 0;   // issued FP64 MFMA flops of one full product over all groups
+};
+
+}  // namespace
+
+struct smx_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // problem
+    bool loaded = false;
+    int32_t nblk = 0;
+    int64_t nnzb = 0, nvals = 0;
+    std::vector<int32_t> blk_size;
+    std::vector<int64_t> col_ptr;
+    std::vector<int32_t> row_idx;
+    std::vector<int64_t> val_off;
+    std::vector<int32_t> grp_ptr, grp_blocks;
+    bool plan_dirty = true;
+    Plan plan;
+
+    // options
+    double mu = 0.0, kT = 0.0;
+    int32_t precision = SMX_FP64;
+    double tol = 1e-12, switch_tol = 1e-3;
+    int32_t max_iter = 100, n_polish = 2;
+
+    // device: problem
+    DevBuf<double> d_k, d_d;
+    DevBuf<int64_t> d_valoff, d_mirror;
+    DevBuf<int32_t> d_brow, d_bcol;
+    // device: plan
+    DevBuf<GroupDesc> d_gd;
+    DevBuf<TileDesc> d_tiles;
+    DevBuf<int2> d_chunks;
+    DevBuf<RowInfo> d_rinfo;
+    DevBuf<int32_t> d_bmap, d_boffs;
+    DevBuf<ScatterDesc> d_scat;
+    // device: work
+    DevBuf<double> d_x0, d_x1, d_w;
+    DevBuf<unsigned long long> d_scale, d_resid;
+    DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
+    DevBuf<double> d_pe, d_pn, d_ne, d_check;
+
+    // host polling / timing
+    int32_t *h_ndone = nullptr;
+    int32_t h_ndone_cap = 0;
+    std::vector<hipEvent_t> ev_poll;
+    std::vector<hipEvent_t> ev_launch;   // two per product launch (before, after)
+    std::vector<int32_t> launch_step;    // step k of each product launch
+    std::vector<int32_t> launch_mode;    // 0 square, 1 update
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
+
+    // results of the last evaluation
+    bool evaluated = false;
+    int32_t steps_launched = 0;
+    int32_t last_precision = SMX_FP64;
+    int32_t last_stride = 0;
+};
+
+namespace {
+
+int32_t fail(smx_ctx c, int32_t code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+std::string g_create_err;
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return fail((ctx), _e == hipErrorOutOfMemory ? SMX_E_NOMEM : SMX_E_HIP,          \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                  \
+    } while (0)
+
+template <typename T>
+hipError_t upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
+{
+    hipError_t e = b.ensure(v.size());
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+int32_t build_plan(smx_ctx c)
+{
+    Plan &P = c->plan;
+    P = Plan();
+    const int32_t nblk = c->nblk;
+    const int32_t ng = (int32_t)c->grp_ptr.size() - 1;
+    P.ngroups = ng;
+    std::vector<int32_t> pos(nblk, -1);
+    std::vector<char> mark(nblk, 0);
+    P.scat.assign((size_t)c->nnzb, ScatterDesc{-1, 0, 0, 0});
+    std::vector<int32_t> rows;
+    rows.reserve(1024);
+    for (int32_t g = 0; g < ng; g++) {
+        rows.clear();
+        for (int32_t q = c->grp_ptr[g]; q < c->grp_ptr[g + 1]; q++) {
+            const int32_t j = c->grp_blocks[q];
+            for (int64_t p = c->col_ptr[j]; p < c->col_ptr[j + 1]; p++) {
+                const int32_t i = c->row_idx[p];
+                if (!mark[i]) {
+                    mark[i] = 1;
+                    rows.push_back(i);
+                }
+            }
+        }
+        std::sort(rows.begin(), rows.end());
+        const int32_t m = (int32_t)rows.size();
+        GroupDesc d{};
+        d.m = m;
+        d.boff_off = (int32_t)P.boffs.size();
+        int64_t n = 0;
+        for (int32_t t = 0; t < m; t++) {
+            mark[rows[t]] = 0;
+            pos[rows[t]] = t;
+            P.boffs.push_back((int32_t)n);
+            n += c->blk_size[rows[t]];
+        }
+        P.boffs.push_back((int32_t)n);
+        if (n > 60000) return fail(c, SMX_E_INVALID, "submatrix dimension above 60000 in group " + std::to_string(g));
+        d.n = (int32_t)n;
+        d.npad = (int32_t)(((std::max<int64_t>(n, 1) + kPad - 1) / kPad) * kPad);
+        d.off = P.work_elems;
+        P.work_elems += (int64_t)d.npad * d.npad;
+        d.rinfo_off = (int64_t)P.rinfo.size();
+        for (int32_t t = 0; t < m; t++) {
+            const int32_t b = c->blk_size[rows[t]];
+            for (int32_t rr = 0; rr < b; rr++) P.rinfo.push_back(RowInfo{t, rr | (b << 16)});
+        }
+        for (int32_t r = d.n; r < d.npad; r++) P.rinfo.push_back(RowInfo{0, 0});
+        d.map_off = (int64_t)P.bmap.size();
+        P.bmap.resize(P.bmap.size() + (size_t)m * m, -1);
+        for (int32_t tb = 0; tb < m; tb++) {
+            const int32_t j = rows[tb];
+            for (int64_t p = c->col_ptr[j]; p < c->col_ptr[j + 1]; p++) {
+                const int32_t a = pos[c->row_idx[p]];
+                if (a >= 0) P.bmap[(size_t)d.map_off + a + (size_t)m * tb] = (int32_t)p;
+            }
+        }
+        for (int32_t q = c->grp_ptr[g]; q < c->grp_ptr[g + 1]; q++) {
+            const int32_t j = c->grp_blocks[q];
+            const int32_t oj = P.boffs[d.boff_off + pos[j]];
+            for (int64_t p = c->col_ptr[j]; p < c->col_ptr[j + 1]; p++) {
+                const int32_t i = c->row_idx[p];
+                const int32_t oi = P.boffs[d.boff_off + pos[i]];
+                P.scat[p] = ScatterDesc{g, oi, oj, c->blk_size[i] | (c->blk_size[j] << 16)};
+            }
+        }
+        for (int32_t t = 0; t < m; t++) pos[rows[t]] = -1;
+        const int32_t nt = (d.npad + kTile - 1) / kTile;
+        for (int32_t ti = 0; ti < nt; ti++)
+            for (int32_t tj = 0; tj <= ti; tj++) P.tiles.push_back(TileDesc{g, (ti << 16) | tj});
+        for (int32_t r0 = 0; r0 < d.npad; r0 += 256) P.chunks.push_back(int2{g, r0});
+        // issued flops of one product: live 64 x 64 wave tiles x K
+        double wt = 0;
+        for (int32_t ti = 0; ti < nt; ti++)
+            for (int32_t tj = 0; tj <= ti; tj++)
+                for (int wr = 0; wr < 2; wr++)
+                    for (int wc = 0; wc < 2; wc++) {
+                        if (ti * kTile + wr * 64 >= d.npad || tj * kTile + wc * 64 >= d.npad) continue;
+                        if (ti == tj && wr < wc) continue;
+                        wt += 1;
+                    }
+        P.exec_flops_per_step += wt * 2.0 * 64 * 64 * d.npad;
+        P.gd.push_back(d);
+    }
+    // larger submatrices first: their tiles are the longest, so they should not form the tail
+    std::stable_sort(P.tiles.begin(), P.tiles.end(), [&](const TileDesc &x, const TileDesc &y) {
+        return P.gd[x.x].npad > P.gd[y.x].npad;
+    });
+    for (int64_t p = 0; p < c->nnzb; p++)
+        if (P.scat[p].g < 0) return fail(c, SMX_E_INVALID, "internal: stored block without a group");
+    return SMX_OK;
+}
+
+// Host-side consistency check of everything the kernels will index with.
+int32_t check_plan(smx_ctx c)
+{
+    const Plan &P = c->plan;
+    for (const TileDesc &t : P.tiles) {
+        if (t.x < 0 || t.x >= P.ngroups) return fail(c, SMX_E_INVALID, "internal: tile group");
+        const GroupDesc &d = P.gd[t.x];
+        const int ti = t.y >> 16, tj = t.y & 0xffff;
+        if (tj > ti || ti * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
+    }
+    for (const GroupDesc &d : P.gd) {
+        if (d.npad % 16 || d.npad < d.n || d.off + (int64_t)d.npad * d.npad > P.work_elems)
+            return fail(c, SMX_E_INVALID, "internal: group extent");
+        if (d.rinfo_off + d.npad > (int64_t)P.rinfo.size() ||
+            d.map_off + (int64_t)d.m * d.m > (int64_t)P.bmap.size() ||
+            d.boff_off + d.m + 1 > (int64_t)P.boffs.size() || P.boffs[d.boff_off + d.m] != d.n)
+            return fail(c, SMX_E_INVALID, "internal: group tables");
+    }
+    for (size_t q = 0; q < P.bmap.size(); q++)
+        if (P.bmap[q] < -1 || P.bmap[q] >= c->nnzb) return fail(c, SMX_E_INVALID, "internal: block map");
+    for (const RowInfo &r : P.rinfo)
+        if (r.x < 0 || (r.y & 0xffff) >= (r.y >> 16 ? (r.y >> 16) : 1)) return fail(c, SMX_E_INVALID, "internal: row table");
+    for (int64_t p = 0; p < c->nnzb; p++) {
+        const ScatterDesc &s = P.scat[p];
+        const GroupDesc &d = P.gd[s.g];
+        if (s.oi + (s.bij & 0xffff) > d.n || s.oj + (s.bij >> 16) > d.n)
+            return fail(c, SMX_E_INVALID, "internal: scatter extent");
+    }
+    return SMX_OK;
+}
+
+int32_t ensure_plan(smx_ctx c)
+{
+    if (!c->plan_dirty) return SMX_OK;
+    int32_t st = build_plan(c);
+    if (st) return st;
+    st = check_plan(c);
+    if (st) return st;
+    const Plan &P = c->plan;
+    // device memory: three group buffers + tables
+    size_t need = 3 * (size_t)P.work_elems * sizeof(double);
+    size_t fr = 0, tot = 0;
+    HIP_TRY(c, hipMemGetInfo(&fr, &tot));
+    const size_t have = fr + c->d_x0.bytes() + c->d_x1.bytes() + c->d_w.bytes();
+    if (need + (64u << 20) > have)
+        return fail(c, SMX_E_NOMEM, "submatrix buffers need " + std::to_string(need >> 20) +
+                                        " MiB, device has " + std::to_string(have >> 20) + " MiB free");
+    HIP_TRY(c, c->d_x0.ensure((size_t)P.work_elems));
+    HIP_TRY(c, c->d_x1.ensure((size_t)P.work_elems));
+    HIP_TRY(c, c->d_w.ensure((size_t)P.work_elems));
+    HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
+    HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
+    HIP_TRY(c, upload(c->d_chunks, P.chunks, c->stream));
+    HIP_TRY(c, upload(c->d_rinfo, P.rinfo, c->stream));
+    HIP_TRY(c, upload(c->d_bmap, P.bmap, c->stream));
+    HIP_TRY(c, upload(c->d_boffs, P.boffs, c->stream));
+    HIP_TRY(c, upload(c->d_scat, P.scat, c->stream));
+    const size_t ng = (size_t)std::max(P.ngroups, 1);
+    HIP_TRY(c, c->d_scale.ensure(ng));
+    HIP_TRY(c, c->d_done.ensure(ng));
+    HIP_TRY(c, c->d_kfinal.ensure(ng));
+    HIP_TRY(c, c->d_flags.ensure(ng));
+    HIP_TRY(c, c->d_ndone.ensure(1));
+    HIP_TRY(c, c->d_pe.ensure((size_t)std::max<int64_t>(c->nnzb, 1)));
+    HIP_TRY(c, c->d_pn.ensure((size_t)std::max<int64_t>(c->nnzb, 1)));
+    HIP_TRY(c, c->d_ne.ensure(2));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));   // host vectors may change after return
+    c->plan_dirty = false;
+    return SMX_OK;
+}
+
+int32_t validate_values(smx_ctx c)
+{
+    HIP_TRY(c, c->d_check.ensure(2));
+    HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, 2 * sizeof(double), c->stream));
+    HIP_TRY(c, launch_check_values(c->stream, c->nnzb, c->d_valoff.p, c->d_brow.p, c->d_bcol.p,
+                                   c->d_mirror.p, c->d_k.p, c->d_check.p));
+    double h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(h, c->d_check.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!std::isfinite(h[1])) return fail(c, SMX_E_NONFINITE, "K holds NaN or Inf values");
+    if (h[0] > 1e-12 * h[1]) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "K is not symmetric: max|K_IJ - K_JI^T| = %.3e > 1e-12 * max|K| = %.3e",
+                      h[0], 1e-12 * h[1]);
+        return fail(c, SMX_E_NOT_SYMMETRIC, buf);
+    }
+    return SMX_OK;
+}
+
+int32_t copy_values_in(smx_ctx c, const double *values, int32_t on_device)
+{
+    HIP_TRY(c, c->d_k.ensure((size_t)std::max<int64_t>(c->nvals, 1)));
+    HIP_TRY(c, c->d_d.ensure((size_t)std::max<int64_t>(c->nvals, 1)));
+    if (c->nvals > 0)
+        HIP_TRY(c, hipMemcpyAsync(c->d_k.p, values, (size_t)c->nvals * sizeof(double),
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    return SMX_OK;
+}
+
+int32_t set_device(smx_ctx c)
+{
+    HIP_TRY(c, hipSetDevice(c->device));
+    return SMX_OK;
+}
+
+int32_t need_sync_results(smx_ctx c)
+{
+    if (!c->evaluated) return fail(c, SMX_E_STATE, "no evaluation has been run");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t smx_create(int32_t device, smx_ctx *out)
+{
+    if (!out) {
+        g_create_err = "out is NULL";
+        return SMX_E_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_create_err = "no HIP device " + std::to_string(device) + " (" + hipGetErrorString(e) + ")";
+        return SMX_E_HIP;
+    }
+    smx_ctx c = new (std::nothrow) smx_context();
+    if (!c) {
+        g_create_err = "host allocation failed";
+        return SMX_E_NOMEM;
+    }
+    c->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_t0);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_t1);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_t2);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_t3);
+    if (e != hipSuccess) {
+        g_create_err = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
+        delete c;
+        return SMX_E_HIP;
+    }
+    *out = c;
+    return SMX_OK;
+}
+
+int32_t smx_destroy(smx_ctx c)
+{
+    if (!c) return SMX_E_INVALID;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto *b : {&c->d_k, &c->d_d, &c->d_x0, &c->d_x1, &c->d_w, &c->d_pe, &c->d_pn, &c->d_ne, &c->d_check})
+        b->release();
+    c->d_valoff.release();
+    c->d_mirror.release();
+    c->d_brow.release();
+    c->d_bcol.release();
+    c->d_gd.release();
+    c->d_tiles.release();
+    c->d_chunks.release();
+    c->d_rinfo.release();
+    c->d_bmap.release();
+    c->d_boffs.release();
+    c->d_scat.release();
+    c->d_scale.release();
+    c->d_resid.release();
+    c->d_done.release();
+    c->d_kfinal.release();
+    c->d_flags.release();
+    c->d_ndone.release();
+    if (c->h_ndone) (void)hipHostFree(c->h_ndone);
+    for (hipEvent_t ev : c->ev_poll) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : c->ev_launch) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : {c->ev_t0, c->ev_t1, c->ev_t2, c->ev_t3})
+        if (ev) (void)hipEventDestroy(ev);
+    delete c;
+    return SMX_OK;
+}
+
+const char *smx_last_error(smx_ctx c)
+{
+    if (!c) return g_create_err.c_str();
+    return c->err.c_str();
+}
+
+int32_t smx_set_stream(smx_ctx c, void *hip_stream)
+{
+    if (!c) return SMX_E_INVALID;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return SMX_OK;
+}
+
+int32_t smx_load_k(smx_ctx c, int32_t nblk, const int32_t *blk_size, const int64_t *col_ptr,
+                   const int32_t *row_idx, const double *values, int32_t values_on_device)
+{
+    if (!c) return SMX_E_INVALID;
+    c->loaded = false;
+    c->evaluated = false;
+    c->plan_dirty = true;
+    if (nblk <= 0 || !blk_size || !col_ptr || !row_idx || !values)
+        return fail(c, SMX_E_INVALID, "nblk must be positive and all arrays non-NULL");
+    if (int32_t st = set_device(c)) return st;
+    for (int32_t j = 0; j < nblk; j++)
+        if (blk_size[j] < 1 || blk_size[j] > 1024)
+            return fail(c, SMX_E_INVALID, "block size out of range 1..1024 at block " + std::to_string(j));
+    if (col_ptr[0] != 0) return fail(c, SMX_E_INVALID, "col_ptr[0] must be 0");
+    for (int32_t j = 0; j < nblk; j++)
+        if (col_ptr[j + 1] < col_ptr[j]) return fail(c, SMX_E_INVALID, "col_ptr must be non-decreasing");
+    const int64_t nnzb = col_ptr[nblk];
+    if (nnzb > (int64_t)INT32_MAX) return fail(c, SMX_E_INVALID, "more than 2^31-1 stored blocks");
+    c->nblk = nblk;
+    c->nnzb = nnzb;
+    c->blk_size.assign(blk_size, blk_size + nblk);
+    c->col_ptr.assign(col_ptr, col_ptr + nblk + 1);
+    c->row_idx.assign(row_idx, row_idx + nnzb);
+    c->val_off.assign((size_t)nnzb + 1, 0);
+    std::vector<int32_t> brow((size_t)nnzb), bcol((size_t)nnzb);
+    std::vector<int64_t> mirror((size_t)nnzb);
+    for (int32_t j = 0; j < nblk; j++) {
+        bool has_diag = false;
+        for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; p++) {
+            const int32_t i = row_idx[p];
+            if (i < 0 || i >= nblk) return fail(c, SMX_E_INVALID, "row index out of range in column " + std::to_string(j));
+            if (p > col_ptr[j] && row_idx[p - 1] >= i)
+                return fail(c, SMX_E_INVALID, "row indices must ascend strictly in column " + std::to_string(j));
+            if (i == j) has_diag = true;
+            c->val_off[p + 1] = c->val_off[p] + (int64_t)blk_size[i] * blk_size[j];
+            brow[p] = blk_size[i];
+            bcol[p] = blk_size[j];
+        }
+        if (!has_diag) return fail(c, SMX_E_INVALID, "diagonal block missing in column " + std::to_string(j));
+    }
+    // mirror positions: block (J, I) for every stored (I, J); the pattern must be symmetric
+    for (int32_t j = 0; j < nblk; j++)
+        for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; p++) {
+            const int32_t i = row_idx[p];
+            const int32_t *lo = row_idx + col_ptr[i], *hi = row_idx + col_ptr[i + 1];
+            const int32_t *f = std::lower_bound(lo, hi, j);
+            if (f == hi || *f != j)
+                return fail(c, SMX_E_NOT_SYMMETRIC, "pattern is not symmetric: block (" + std::to_string(i) + "," +
+                                                        std::to_string(j) + ") stored without its mirror");
+            mirror[p] = col_ptr[i] + (f - lo);
+        }
+    c->nvals = c->val_off[nnzb];
+    HIP_TRY(c, upload(c->d_valoff, c->val_off, c->stream));
+    HIP_TRY(c, upload(c->d_mirror, mirror, c->stream));
+    HIP_TRY(c, upload(c->d_brow, brow, c->stream));
+    HIP_TRY(c, upload(c->d_bcol, bcol, c->stream));
+    if (int32_t st = copy_values_in(c, values, values_on_device)) return st;
+    if (int32_t st = validate_values(c)) return st;
+    // default grouping: one group per block column
+    c->grp_ptr.resize((size_t)nblk + 1);
+    c->grp_blocks.resize((size_t)nblk);
+    for (int32_t j = 0; j <= nblk; j++) c->grp_ptr[j] = j;
+    for (int32_t j = 0; j < nblk; j++) c->grp_blocks[j] = j;
+    c->loaded = true;
+    return SMX_OK;
+}
+
+int32_t smx_update_values(smx_ctx c, const double *values, int32_t values_on_device)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (!values) return fail(c, SMX_E_INVALID, "values is NULL");
+    if (int32_t st = set_device(c)) return st;
+    c->evaluated = false;
+    if (int32_t st = copy_values_in(c, values, values_on_device)) return st;
+    if (int32_t st = validate_values(c)) {
+        c->loaded = false;
+        return st;
+    }
+    return SMX_OK;
+}
+
+int32_t smx_set_groups(smx_ctx c, int32_t ngroups, const int32_t *grp_ptr, const int32_t *grp_blocks)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (ngroups <= 0 || !grp_ptr || !grp_blocks) return fail(c, SMX_E_INVALID, "need ngroups > 0 and arrays");
+    if (grp_ptr[0] != 0 || grp_ptr[ngroups] != c->nblk)
+        return fail(c, SMX_E_INVALID, "groups must cover every block column exactly once");
+    std::vector<char> seen((size_t)c->nblk, 0);
+    for (int32_t g = 0; g < ngroups; g++) {
+        if (grp_ptr[g + 1] <= grp_ptr[g]) return fail(c, SMX_E_INVALID, "empty group " + std::to_string(g));
+        for (int32_t q = grp_ptr[g]; q < grp_ptr[g + 1]; q++) {
+            const int32_t j = grp_blocks[q];
+            if (j < 0 || j >= c->nblk || seen[j])
+                return fail(c, SMX_E_INVALID, "block column listed twice or out of range in group " + std::to_string(g));
+            seen[j] = 1;
+        }
+    }
+    c->grp_ptr.assign(grp_ptr, grp_ptr + ngroups + 1);
+    c->grp_blocks.assign(grp_blocks, grp_blocks + c->nblk);
+    c->plan_dirty = true;
+    c->evaluated = false;
+    return SMX_OK;
+}
+
+int32_t smx_set_mu(smx_ctx c, double mu)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!std::isfinite(mu)) return fail(c, SMX_E_INVALID, "mu must be finite");
+    c->mu = mu;
+    return SMX_OK;
+}
+
+int32_t smx_set_temperature(smx_ctx c, double kT)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!(kT >= 0.0) || !std::isfinite(kT)) return fail(c, SMX_E_INVALID, "kT must be finite and >= 0");
+    c->kT = kT;
+    return SMX_OK;
+}
+
+int32_t smx_set_precision(smx_ctx c, int32_t mode)
+{
+    if (!c) return SMX_E_INVALID;
+    if (mode < SMX_FP64 || mode > SMX_FP32) return fail(c, SMX_E_INVALID, "unknown precision mode");
+    c->precision = mode;
+    return SMX_OK;
+}
+
+int32_t smx_set_convergence(smx_ctx c, double tol, int32_t max_iter, int32_t n_polish, double switch_tol)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!(tol > 0.0) || max_iter < 1 || max_iter > 1000 || n_polish < 1 || n_polish > 10 || !(switch_tol > 0.0))
+        return fail(c, SMX_E_INVALID, "need tol > 0, 1 <= max_iter <= 1000, 1 <= n_polish <= 10, switch_tol > 0");
+    c->tol = tol;
+    c->max_iter = max_iter;
+    c->n_polish = n_polish;
+    c->switch_tol = switch_tol;
+    return SMX_OK;
+}
+
+int32_t smx_evaluate(smx_ctx c)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (c->kT > 0.0) return fail(c, SMX_E_UNSUPPORTED, "finite temperature (kT > 0) is not implemented on the GPU path");
+    if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented yet");
+    if (int32_t st = set_device(c)) return st;
+    c->evaluated = false;
+    if (int32_t st = ensure_plan(c)) return st;
+    const Plan &P = c->plan;
+    const int32_t ng = P.ngroups;
+    const int32_t stride = c->max_iter + 2;
+    HIP_TRY(c, c->d_resid.ensure((size_t)ng * stride));
+    if (c->h_ndone_cap < stride) {
+        if (c->h_ndone) (void)hipHostFree(c->h_ndone);
+        c->h_ndone = nullptr;
+        HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_ndone), sizeof(int32_t) * stride));
+        c->h_ndone_cap = stride;
+    }
+    while ((int32_t)c->ev_poll.size() < stride) {
+        hipEvent_t ev;
+        HIP_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->ev_poll.push_back(ev);
+    }
+    hipStream_t st = c->stream;
+    IterState it;
+    it.scale_bits = c->d_scale.p;
+    it.resid_bits = c->d_resid.p;
+    it.done = c->d_done.p;
+    it.kfinal = c->d_kfinal.p;
+    it.flags = c->d_flags.p;
+    it.ndone = c->d_ndone.p;
+    it.resid_stride = stride;
+
+    HIP_TRY(c, hipEventRecord(c->ev_t0, st));
+    HIP_TRY(c, hipMemsetAsync(it.scale_bits, 0, sizeof(unsigned long long) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(it.resid_bits, 0, sizeof(unsigned long long) * (size_t)ng * stride, st));
+    HIP_TRY(c, hipMemsetAsync(it.done, 0, sizeof(int32_t) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(it.kfinal, 0, sizeof(int32_t) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(it.flags, 0, sizeof(int32_t) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
+    HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
+                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_x0.p, it.scale_bits));
+    HIP_TRY(c, hipEventRecord(c->ev_t1, st));
+
+    double *xb[2] = {c->d_x0.p, c->d_x1.p};
+    int32_t launched = 0;
+    c->launch_step.clear();
+    c->launch_mode.clear();
+    auto timed = [&](int mode, int k, const double *x, const double *b, double *o) -> hipError_t {
+        const size_t idx = c->launch_step.size();
+        while (c->ev_launch.size() < 2 * (idx + 1)) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            c->ev_launch.push_back(ev);
+        }
+        hipError_t e = hipEventRecord(c->ev_launch[2 * idx], st);
+        if (e == hipSuccess)
+            e = launch_ns_f64(st, mode, (int)P.tiles.size(), c->d_tiles.p, c->d_gd.p, x, b, o, it, k, c->tol,
+                              c->max_iter);
+        if (e == hipSuccess) e = hipEventRecord(c->ev_launch[2 * idx + 1], st);
+        c->launch_step.push_back(k);
+        c->launch_mode.push_back(mode);
+        return e;
+    };
+    for (int32_t k = 0; k <= c->max_iter; k++) {
+        HIP_TRY(c, timed(0, k, xb[k & 1], xb[k & 1], c->d_w.p));
+        HIP_TRY(c, timed(1, k, xb[k & 1], c->d_w.p, xb[(k + 1) & 1]));
+        launched = k + 1;
+        HIP_TRY(c, hipMemcpyAsync(c->h_ndone + k, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipEventRecord(c->ev_poll[k], st));
+        if (k >= 1) {
+            HIP_TRY(c, hipEventSynchronize(c->ev_poll[k - 1]));
+            if (c->h_ndone[k - 1] >= ng) break;
+        }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_t2, st));
+    HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_x0.p, c->d_x1.p, it, c->d_k.p,
+                              c->d_d.p, c->d_pe.p, c->d_pn.p));
+    HIP_TRY(c, launch_reduce(st, c->nnzb, c->d_pe.p, c->d_pn.p, c->d_ne.p));
+    HIP_TRY(c, hipEventRecord(c->ev_t3, st));
+    c->steps_launched = launched;
+    c->last_precision = c->precision;
+    c->last_stride = stride;
+    c->evaluated = true;
+    return SMX_OK;
+}
+
+int32_t smx_wait(smx_ctx c)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = need_sync_results(c)) return st;
+    std::vector<int32_t> fl((size_t)c->plan.ngroups);
+    HIP_TRY(c, hipMemcpy(fl.data(), c->d_flags.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int nc = 0, nf = 0;
+    for (int32_t f : fl) {
+        nc += (f & 1) != 0;
+        nf += (f & 2) != 0;
+    }
+    if (nf) return fail(c, SMX_E_NONFINITE, std::to_string(nf) + " group(s) produced non-finite iterates");
+    if (nc) return fail(c, SMX_E_NOT_CONVERGED, std::to_string(nc) + " group(s) reached max_iter");
+    return SMX_OK;
+}
+
+int32_t smx_get_d(smx_ctx c, double *out, int32_t out_on_device)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!out) return fail(c, SMX_E_INVALID, "out is NULL");
+    if (int32_t st = need_sync_results(c)) return st;
+    if (c->nvals > 0)
+        HIP_TRY(c, hipMemcpyAsync(out, c->d_d.p, (size_t)c->nvals * sizeof(double),
+                                  out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMX_OK;
+}
+
+static int32_t read_ne(smx_ctx c, double *ne)
+{
+    if (int32_t st = need_sync_results(c)) return st;
+    HIP_TRY(c, hipMemcpy(ne, c->d_ne.p, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    return SMX_OK;
+}
+
+int32_t smx_trace(smx_ctx c, double *n_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!n_out) return fail(c, SMX_E_INVALID, "n_out is NULL");
+    double ne[2];
+    if (int32_t st = read_ne(c, ne)) return st;
+    *n_out = ne[0];
+    return SMX_OK;
+}
+
+int32_t smx_energy(smx_ctx c, double *e_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!e_out) return fail(c, SMX_E_INVALID, "e_out is NULL");
+    double ne[2];
+    if (int32_t st = read_ne(c, ne)) return st;
+    *e_out = ne[1];
+    return SMX_OK;
+}
+
+int32_t smx_get_group_info(smx_ctx c, int32_t *n_g, int32_t *iters, double *scale, double *resid)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = need_sync_results(c)) return st;
+    const int32_t ng = c->plan.ngroups;
+    std::vector<int32_t> kf((size_t)ng);
+    std::vector<unsigned long long> sb((size_t)ng), rb((size_t)ng * c->last_stride);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(sb.data(), c->d_scale.p, sb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(rb.data(), c->d_resid.p, rb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int32_t g = 0; g < ng; g++) {
+        if (n_g) n_g[g] = c->plan.gd[g].n;
+        if (iters) iters[g] = kf[g];
+        double s, r;
+        std::memcpy(&s, &sb[g], sizeof s);
+        std::memcpy(&r, &rb[(size_t)g * c->last_stride + kf[g]], sizeof r);
+        if (scale) scale[g] = s;
+        if (resid) resid[g] = r;
+    }
+    return SMX_OK;
+}
+
+int32_t smx_get_stats(smx_ctx c, smx_stats *out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!out) return fail(c, SMX_E_INVALID, "out is NULL");
+    if (int32_t st = need_sync_results(c)) return st;
+    const int32_t ng = c->plan.ngroups;
+    std::vector<int32_t> n((size_t)ng), it((size_t)ng), fl((size_t)ng);
+    std::vector<double> sc((size_t)ng), rs((size_t)ng);
+    if (int32_t st = smx_get_group_info(c, n.data(), it.data(), sc.data(), rs.data())) return st;
+    HIP_TRY(c, hipMemcpy(fl.data(), c->d_flags.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    smx_stats s;
+    std::memset(&s, 0, sizeof s);
+    s.ngroups = ng;
+    s.precision = c->last_precision;
+    s.n_min = INT32_MAX;
+    s.iters_min = INT32_MAX;
+    double nsum = 0, isum = 0;
+    for (int32_t g = 0; g < ng; g++) {
+        s.n_min = std::min(s.n_min, n[g]);
+        s.n_max = std::max(s.n_max, n[g]);
+        s.iters_min = std::min(s.iters_min, it[g]);
+        s.iters_max = std::max(s.iters_max, it[g]);
+        s.n_not_converged += (fl[g] & 1) != 0;
+        nsum += n[g];
+        isum += it[g];
+        s.resid_max = std::max(s.resid_max, rs[g]);
+        const double nd = n[g];
+        s.algo_flops += 4.0 * nd * nd * nd * it[g];
+    }
+    s.n_mean = ng ? nsum / ng : 0;
+    s.iters_mean = ng ? isum / ng : 0;
+    // issued matrix-core flops: every step runs the square product; all but the last the update
+    double exec = 0;
+    {
+        // per group: (2 k_g + 1) products of its live wave tiles
+        const Plan &P = c->plan;
+        for (int32_t g = 0; g < ng; g++) {
+            const GroupDesc &d = P.gd[g];
+            const int32_t nt = (d.npad + kTile - 1) / kTile;
+            double wt = 0;
+            for (int32_t ti = 0; ti < nt; ti++)
+                for (int32_t tj = 0; tj <= ti; tj++)
+                    for (int wr = 0; wr < 2; wr++)
+                        for (int wc = 0; wc < 2; wc++) {
+                            if (ti * kTile + wr * 64 >= d.npad || tj * kTile + wc * 64 >= d.npad) continue;
+                            if (ti == tj && wr < wc) continue;
+                            wt += 1;
+                        }
+            exec += wt * 2.0 * 64 * 64 * d.npad * (2.0 * it[g] + 1.0);
+        }
+    }
+    s.exec_flops = exec;
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
+    s.time_gather_ms = ms;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t1, c->ev_t2));
+    s.time_iterate_ms = ms;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t2, c->ev_t3));
+    s.time_scatter_ms = ms;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t0, c->ev_t3));
+    s.time_total_ms = ms;
+    double ws = 0;
+    for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_x0.bytes(), c->d_x1.bytes(), c->d_w.bytes(),
+                     c->d_bmap.bytes(), c->d_rinfo.bytes(), c->d_scat.bytes(), c->d_resid.bytes()})
+        ws += (double)b;
+    s.workspace_bytes = ws;
+    *out = s;
+    return SMX_OK;
+}
+
+int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_flops, int32_t *count)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = need_sync_results(c)) return st;
+    const int32_t nl = (int32_t)c->launch_step.size();
+    if (count) *count = nl;
+    std::vector<int32_t> kf((size_t)c->plan.ngroups);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t l = 0; l < nl && l < cap; l++) {
+        if (ms) {
+            float t = 0;
+            HIP_TRY(c, hipEventElapsedTime(&t, c->ev_launch[2 * l], c->ev_launch[2 * l + 1]));
+            ms[l] = t;
+        }
+        if (algo_flops) {
+            const int32_t k = c->launch_step[l];
+            double f = 0;
+            for (int32_t g = 0; g < c->plan.ngroups; g++) {
+                const bool active = c->launch_mode[l] == 0 ? (k <= kf[g]) : (k < kf[g]);
+                const double n = c->plan.gd[g].n;
+                if (active) f += 2.0 * n * n * n;
+            }
+            algo_flops[l] = f;
+        }
+    }
+    return SMX_OK;
+}
+
+int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32_t ld, int32_t *n_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (what != 0 && what != 1) return fail(c, SMX_E_INVALID, "what must be 0 or 1");
+    if (int32_t st = set_device(c)) return st;
+    if (what == 1 && !c->evaluated) return fail(c, SMX_E_STATE, "no evaluation has been run");
+    if (int32_t st = ensure_plan(c)) return st;
+    const Plan &P = c->plan;
+    if (g < 0 || g >= P.ngroups) return fail(c, SMX_E_INVALID, "group index out of range");
+    const GroupDesc d = P.gd[g];
+    if (n_out) *n_out = d.n;
+    if (!out) return SMX_OK;
+    if (ld < d.n) return fail(c, SMX_E_INVALID, "ld < n_g");
+    const double *src = nullptr;
+    double a = 1.0;
+    if (what == 0) {
+        // re-gather this group's chunks into the scratch product buffer
+        std::vector<int2> ch;
+        for (const int2 &x : P.chunks)
+            if (x.x == g) ch.push_back(x);
+        DevBuf<int2> dch;
+        HIP_TRY(c, upload(dch, ch, c->stream));
+        HIP_TRY(c, c->d_check.ensure((size_t)std::max(P.ngroups, 2)));
+        HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, sizeof(double) * std::max(P.ngroups, 2), c->stream));
+        HIP_TRY(c, launch_gather(c->stream, (int)ch.size(), dch.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
+                                 c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_w.p,
+                                 reinterpret_cast<unsigned long long *>(c->d_check.p)));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dch.release();
+        src = c->d_w.p + d.off;
+    } else {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        int32_t kf = 0;
+        unsigned long long sb = 0;
+        HIP_TRY(c, hipMemcpy(&kf, c->d_kfinal.p + g, sizeof kf, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(&sb, c->d_scale.p + g, sizeof sb, hipMemcpyDeviceToHost));
+        if (kf == 0) {
+            double s;
+            std::memcpy(&s, &sb, sizeof s);
+            a = s > 0 ? 1.0 / s : 0.0;
+        }
+        src = ((kf & 1) ? c->d_x1.p : c->d_x0.p) + d.off;
+    }
+    std::vector<double> tmp((size_t)d.npad * d.npad);
+    HIP_TRY(c, hipMemcpy(tmp.data(), src, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int32_t j = 0; j < d.n; j++)
+        for (int32_t i = 0; i < d.n; i++) out[i + (size_t)j * ld] = a * tmp[i + (size_t)j * d.npad];
+    return SMX_OK;
+}
+
+int32_t smx_get_sizes(smx_ctx c, int32_t *ngroups, int64_t *nvalues)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (ngroups) *ngroups = (int32_t)c->grp_ptr.size() - 1;
+    if (nvalues) *nvalues = c->nvals;
+    return SMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+// Memory-bound kernels of the submatrix path: gather + shift + Gershgorin
+// bound, scatter of the own columns of D with the energy/trace partials, the
+// fixed-order final reduction, and validation of K's values.
+#include "smx_internal.h"
+
+namespace smx {
+
+namespace {
+
+__device__ inline void atomic_max_nonneg(unsigned long long *addr, double v)
+{
+    // For non-negative doubles the IEEE bit patterns order like the values;
+    // NaN is mapped to +Inf so that it is never lost.
+    if (!(v == v)) v = __builtin_huge_val();
+    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Gather (submatrix assembly, Sec. III-A step 1): one thread per row r of the
+// padded submatrix, looping over its columns block by block.  Consecutive
+// threads write consecutive rows of one column (coalesced), and the row sum
+// of |A_g| feeds the Gershgorin bound s_g = ||A_g||_inf.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256)
+void gather_shift_kernel(const int2 *__restrict__ chunks, const GroupDesc *__restrict__ groups,
+                         const RowInfo *__restrict__ rinfo, const int32_t *__restrict__ bmap,
+                         const int32_t *__restrict__ boffs, const int64_t *__restrict__ valoff,
+                         const double *__restrict__ kvals, double mu, double *__restrict__ x0,
+                         unsigned long long *__restrict__ scale_bits)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const GroupDesc gd = groups[ch.x];
+    const int r = ch.y + (int)threadIdx.x;
+    const int npad = gd.npad;
+    const bool live = r < npad;
+    const bool real = r < gd.n;
+    int lb = 0, rr = 0, br = 0;
+    if (real) {
+        const RowInfo ri = rinfo[gd.rinfo_off + r];
+        lb = ri.x;
+        rr = ri.y & 0xffff;
+        br = ri.y >> 16;
+    }
+    double *xg = x0 + gd.off;
+    const int32_t *map_row = bmap + gd.map_off + lb;     // + m * column block
+    const int32_t *bo = boffs + gd.boff_off;
+    double rowsum = 0.0;
+    for (int cb = 0; cb < gd.m; cb++) {
+        const int c0 = bo[cb];
+        const int bc = bo[cb + 1] - c0;
+        const int32_t p = real ? map_row[(int64_t)gd.m * cb] : -1;
+        const double *src = (p >= 0) ? kvals + valoff[p] + rr : nullptr;
+        for (int cc = 0; cc < bc; cc++) {
+            const int c = c0 + cc;
+            double v = (p >= 0) ? src[(int64_t)cc * br] : 0.0;
+            if (r == c) v -= mu;
+            rowsum += fabs(v);
+            if (live) xg[r + (int64_t)c * npad] = v;
+        }
+    }
+    // padding columns: identity on the padded diagonal
+    for (int c = gd.n; c < npad; c++)
+        if (live) xg[r + (int64_t)c * npad] = (r == c) ? 1.0 : 0.0;
+
+    double m = real ? rowsum : 0.0;
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(scale_bits + ch.x, m);
+}
+
+// ---------------------------------------------------------------------------
+// Scatter (Sec. III-A step 3): for every stored block (I, J) of an own
+// column J of group g, D_IJ = (delta_IJ I - S_g[I rows, J cols]) / 2 with
+// S_g = a X_k (a = 1/s_g only when the result is X_0).  Also writes the
+// block's <D_IJ, K_IJ> and, for diagonal blocks, tr D_JJ.  One wave per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256)
+void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
+                    const int64_t *__restrict__ valoff, const GroupDesc *__restrict__ groups,
+                    const double *__restrict__ x0, const double *__restrict__ x1,
+                    const int32_t *__restrict__ kfinal, const unsigned long long *__restrict__ scale_bits,
+                    const double *__restrict__ kvals, double *__restrict__ dvals,
+                    double *__restrict__ part_e, double *__restrict__ part_n)
+{
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= nblocks) return;
+    const ScatterDesc d = sd[p];
+    const GroupDesc gd = groups[d.g];
+    const int kf = kfinal[d.g];
+    const double *xs = ((kf & 1) ? x1 : x0) + gd.off;
+    double a = 1.0;
+    if (kf == 0) {
+        const double s = __longlong_as_double((long long)scale_bits[d.g]);
+        a = s > 0.0 ? 1.0 / s : 0.0;
+    }
+    const int bi = d.bij & 0xffff, bj = d.bij >> 16;
+    const bool diag = (d.oi == d.oj);
+    const int64_t vo = valoff[p];
+    const int nel = bi * bj;
+    double e = 0.0, tr = 0.0;
+    for (int t = lane; t < nel; t += 64) {
+        const int rr = t % bi, cc = t / bi;
+        const double s = a * xs[(int64_t)(d.oi + rr) + (int64_t)(d.oj + cc) * gd.npad];
+        const double dv = 0.5 * ((diag && rr == cc) ? 1.0 : 0.0) - 0.5 * s;
+        dvals[vo + t] = dv;
+        e += dv * kvals[vo + t];
+        if (diag && rr == cc) tr += dv;
+    }
+    e = wave_sum(e);
+    tr = wave_sum(tr);
+    if (lane == 0) {
+        part_e[p] = e;
+        part_n[p] = tr;
+    }
+}
+
+// Fixed-order sum of the per-block partials (one workgroup): deterministic.
+__global__ __launch_bounds__(1024)
+void reduce_kernel(int64_t n, const double *__restrict__ pe, const double *__restrict__ pn,
+                   double *__restrict__ out2)
+{
+    __shared__ double se[16], sn[16];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = t * per;
+    const int64_t hi = (lo + per < n) ? lo + per : n;
+    double e = 0.0, tr = 0.0;
+    for (int64_t i = lo; i < hi; i++) {
+        e += pe[i];
+        tr += pn[i];
+    }
+    // fixed tree: within waves by xor shuffles, then across the 16 waves in order
+    e = wave_sum(e);
+    tr = wave_sum(tr);
+    if ((t & 63) == 0) {
+        se[t >> 6] = e;
+        sn[t >> 6] = tr;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double ae = 0.0, an = 0.0;
+        for (int w = 0; w < 16; w++) {
+            ae += se[w];
+            an += sn[w];
+        }
+        out2[0] = an;
+        out2[1] = ae;
+    }
+}
+
+// Validation of K's values: max|K_IJ - K_JI^T| and max|K| (NaN/Inf -> +Inf).
+__global__ __launch_bounds__(256)
+void check_values_kernel(int64_t nblocks, const int64_t *__restrict__ valoff,
+                         const int32_t *__restrict__ brow, const int32_t *__restrict__ bcol,
+                         const int64_t *__restrict__ mirror, const double *__restrict__ kv,
+                         unsigned long long *__restrict__ out2)
+{
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double asym = 0.0, amax = 0.0;
+    if (p < nblocks) {
+        const int bi = brow[p], bj = bcol[p];
+        const int64_t q = mirror[p];
+        const double *a = kv + valoff[p];
+        const double *b = kv + valoff[q];          // block (J, I): bj x bi
+        for (int t = lane; t < bi * bj; t += 64) {
+            const int rr = t % bi, cc = t / bi;
+            const double x = a[t];
+            const double y = b[cc + (int64_t)rr * bj];
+            double dz = fabs(x - y);
+            double ax = fabs(x);
+            if (!(ax <= 1.7976931348623157e308)) { ax = __builtin_huge_val(); dz = ax; }
+            asym = fmax(asym, dz);
+            amax = fmax(amax, ax);
+        }
+    }
+    asym = wave_max(asym);
+    amax = wave_max(amax);
+    if (lane == 0 && p < nblocks) {
+        atomic_max_nonneg(out2 + 0, asym);
+        atomic_max_nonneg(out2 + 1, amax);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const GroupDesc *groups,
+                         const RowInfo *rinfo, const int32_t *bmap, const int32_t *boffs,
+                         const int64_t *valoff, const double *kvals, double mu, double *x0,
+                         unsigned long long *scale_bits)
+{
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_shift_kernel, dim3(nchunks), dim3(256), 0, st, chunks, groups,
+                       rinfo, bmap, boffs, valoff, kvals, mu, x0, scale_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd,
+                          const int64_t *valoff, const GroupDesc *groups, const double *x0,
+                          const double *x1, const IterState &it, const double *kvals,
+                          double *dvals, double *part_e, double *part_n)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const int64_t grid = (nblocks + 3) / 4;
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
+                       groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const double *part_n,
+                         double *out2)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, n, part_e, part_n, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_values(hipStream_t st, int64_t nblocks, const int64_t *valoff,
+                               const int32_t *blk_rows, const int32_t *blk_cols,
+                               const int64_t *mirror, const double *kvals, double *out2)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const int64_t grid = (nblocks + 3) / 4;
+    hipLaunchKernelGGL(check_values_kernel, dim3((unsigned)grid), dim3(256), 0, st, nblocks, valoff,
+                       blk_rows, blk_cols, mirror, kvals,
+                       reinterpret_cast<unsigned long long *>(out2));
+    return hipGetLastError();
+}
+
+}  // namespace smx
