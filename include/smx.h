@@ -72,7 +72,10 @@ extern "C" {
                              products, FP32 accumulation), then FP64 polish     */
 #define SMX_BF16_1W   2   /* bulk products in plain BF16 (FP32 accumulation),
                              then FP64 polish                                    */
-#define SMX_FP32      3   /* bulk products in FP32 (MFMA f32), then FP64 polish  */
+#define SMX_FP32      3   /* bulk products in FP32 (MFMA f32), then FP64 polish
+                             (not implemented on the GPU path: SMX_E_UNSUPPORTED) */
+#define SMX_FP16_2W   4   /* bulk products as 2-word FP16 splits (3 MFMA f16
+                             products, FP32 accumulation), then FP64 polish     */
 
 typedef struct smx_context *smx_ctx;
 
@@ -148,8 +151,12 @@ int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
 /*
  * Stopping rule of the iteration: stop at the first k with
  * max|X_k^2 - I| <= tol (FP64 products), at most max_iter steps.  In the
- * reduced-precision modes the bulk runs until max|X_k^2 - I| <= switch_tol
- * (or stops improving) and is followed by n_polish FP64 steps (>= 1).
+ * reduced-precision modes the bulk runs until tau_k = Tr(I - X_k^2) <=
+ * switch_tol (tau_k bounds the largest 1 - x_i^2 over the eigenvalues x_i
+ * of X_k, all of which lie in [-1, 1]), or until tau_k stops falling
+ * (tau_k < 0.1 and tau_k > tau_{k-1}/2), or for at most max_iter - n_polish
+ * steps, and is followed by n_polish FP64 steps (>= 1); the last of them is
+ * computed on the group's own columns only, since only those enter D.
  * Defaults: tol 1e-12, max_iter 100, n_polish 2, switch_tol 1e-3.
  */
 int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
@@ -194,7 +201,9 @@ int32_t smx_get_group_info(smx_ctx ctx, int32_t *n_g, int32_t *iters,
  *   what = 0: A_g = K[R(g), R(g)] - mu I as gathered on the device
  *             (needs a loaded K; uses the current groups and mu);
  *   what = 1: the sign S_g of the last evaluation (the whole submatrix,
- *             not only the group's own columns).
+ *             not only the group's own columns); in the reduced-precision
+ *             modes the last full FP64 iterate, one step before the final
+ *             (own-column) step.
  * n_out (nullable) receives n_g.  With out == NULL only n_g is returned.
  * Synchronises.  what = 0 overwrites scratch that what = 1 does not read.
  */
@@ -206,15 +215,15 @@ int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
 
 /*
  * Per-launch profile of the matrix-core product kernels of the last
- * evaluation, in launch order (square, update, square, update, ...):
- * device time in ms measured with HIP events on the context's stream, and
- * the algorithmic flops of the launch (2 n_g^3 for every group the launch
- * works on, i.e. one dense n_g x n_g product).  Writes min(cap, count)
- * entries to the host arrays (either may be NULL) and the launch count to
- * *count.  Synchronises.
+ * evaluation, in launch order: device time in ms measured with HIP events on
+ * the context's stream, the algorithmic flops of the launch (2 n_g^3 for
+ * every group the launch works on, i.e. one dense n_g x n_g product), and
+ * its kind: 0/1 FP64 square/update, 2/3 reduced-precision square/update,
+ * 4/5 FP64 polish square/update.  Writes min(cap, count) entries to the host
+ * arrays (any may be NULL) and the launch count to *count.  Synchronises.
  */
 int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,
-                               int32_t *count);
+                               int32_t *kind, int32_t *count);
 
 #ifdef __cplusplus
 }

@@ -34,8 +34,10 @@ SMX_FP64 = 0
 SMX_BF16_3W = 1
 SMX_BF16_1W = 2
 SMX_FP32 = 3
+SMX_FP16_2W = 4
 
-PRECISIONS = {"fp64": SMX_FP64, "bf16x3": SMX_BF16_3W, "bf16": SMX_BF16_1W, "fp32": SMX_FP32}
+PRECISIONS = {"fp64": SMX_FP64, "bf16x3": SMX_BF16_3W, "bf16": SMX_BF16_1W, "fp32": SMX_FP32,
+              "fp16x2": SMX_FP16_2W}
 
 # Every function the header declares, with (restype, argtypes).
 _P = ctypes.POINTER
@@ -70,7 +72,7 @@ SIGNATURES = {
     "smx_get_stats": (_i32, [_vp, _P(SmxStats)]),
     "smx_get_group_info": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "smx_get_sizes": (_i32, [_vp, _P(_i32), _P(_i64)]),
-    "smx_get_launch_profile": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
+    "smx_get_launch_profile": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(_i32)]),
     "smx_get_submatrix": (_i32, [_vp, _i32, _i32, _vp, _i32, _P(_i32)]),
 }
 
@@ -251,15 +253,16 @@ def smx_get_group_info(ctx):
 
 
 def smx_get_launch_profile(ctx):
-    """(ms per launch, algorithmic flops per launch) of the product kernels."""
+    """(ms, algorithmic flops, kind) per product-kernel launch of the last evaluation."""
     cnt = _i32()
-    _check(ctx, load_library().smx_get_launch_profile(ctx, 0, None, None, ctypes.byref(cnt)))
+    _check(ctx, load_library().smx_get_launch_profile(ctx, 0, None, None, None, ctypes.byref(cnt)))
     n = cnt.value
     ms = np.zeros(n, np.float32)
     fl = np.zeros(n)
+    kd = np.zeros(n, np.int32)
     _check(ctx, load_library().smx_get_launch_profile(ctx, n, ms.ctypes.data, fl.ctypes.data,
-                                                       ctypes.byref(cnt)))
-    return ms.astype(np.float64), fl
+                                                       kd.ctypes.data, ctypes.byref(cnt)))
+    return ms.astype(np.float64), fl, kd
 
 
 def smx_get_submatrix(ctx, g: int, what: int = 1) -> np.ndarray:

@@ -55,8 +55,11 @@ struct Plan {
     std::vector<int32_t> bmap;
     std::vector<int32_t> boffs;
     std::vector<ScatterDesc> scat;
+    std::vector<int32_t> own_list;    // own columns of every group (submatrix column indices)
+    std::vector<double> wtiles;       // live 64 x 64 wave tiles of one product, per group
     int64_t work_elems = 0;
-    double exec_flops_per_step = 0;   // issued FP64 MFMA flops of one full product over all groups
+    int64_t thin_elems = 0;
+    int32_t max_npad = 0, max_own = 0;
 };
 
 }  // namespace
@@ -100,6 +103,10 @@ struct smx_context {
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
+    DevBuf<int32_t> d_own;
+    DevBuf<double> d_tau_parts, d_tau_hist;
+    DevBuf<unsigned short> d_wx0, d_wx1, d_ww;   // word planes of X (two steps) and W
+    DevBuf<double> d_t0, d_t1, d_t2;             // own-column buffers of the last polish step
 
     // host polling / timing
     int32_t *h_ndone = nullptr;
@@ -107,7 +114,7 @@ struct smx_context {
     std::vector<hipEvent_t> ev_poll;
     std::vector<hipEvent_t> ev_launch;   // two per product launch (before, after)
     std::vector<int32_t> launch_step;    // step k of each product launch
-    std::vector<int32_t> launch_mode;    // 0 square, 1 update
+    std::vector<int32_t> launch_kind;    // 0/1 FP64 square/update, 2/3 word square/update, 4/5 polish
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
 
     // results of the last evaluation
@@ -115,6 +122,8 @@ struct smx_context {
     int32_t steps_launched = 0;
     int32_t last_precision = SMX_FP64;
     int32_t last_stride = 0;
+    int32_t last_polish = 0;             // FP64 polish steps after the bulk (0 in FP64 mode)
+    int32_t last_max_iter = 0;
 };
 
 namespace {
@@ -201,15 +210,24 @@ int32_t build_plan(smx_ctx c)
                 if (a >= 0) P.bmap[(size_t)d.map_off + a + (size_t)m * tb] = (int32_t)p;
             }
         }
+        d.own_off = (int32_t)P.own_list.size();
+        int32_t ocol = 0;
         for (int32_t q = c->grp_ptr[g]; q < c->grp_ptr[g + 1]; q++) {
             const int32_t j = c->grp_blocks[q];
             const int32_t oj = P.boffs[d.boff_off + pos[j]];
             for (int64_t p = c->col_ptr[j]; p < c->col_ptr[j + 1]; p++) {
                 const int32_t i = c->row_idx[p];
                 const int32_t oi = P.boffs[d.boff_off + pos[i]];
-                P.scat[p] = ScatterDesc{g, oi, oj, c->blk_size[i] | (c->blk_size[j] << 16)};
+                P.scat[p] = ScatterDesc{g, oi, oj, c->blk_size[i] | (c->blk_size[j] << 16), ocol, 0};
             }
+            for (int32_t cc = 0; cc < c->blk_size[j]; cc++) P.own_list.push_back(oj + cc);
+            ocol += c->blk_size[j];
         }
+        d.m_own = ocol;
+        d.thin_off = P.thin_elems;
+        P.thin_elems += (int64_t)d.npad * d.m_own;
+        P.max_npad = std::max(P.max_npad, d.npad);
+        P.max_own = std::max(P.max_own, d.m_own);
         for (int32_t t = 0; t < m; t++) pos[rows[t]] = -1;
         const int32_t nt = (d.npad + kTile - 1) / kTile;
         for (int32_t ti = 0; ti < nt; ti++)
@@ -225,7 +243,7 @@ int32_t build_plan(smx_ctx c)
                         if (ti == tj && wr < wc) continue;
                         wt += 1;
                     }
-        P.exec_flops_per_step += wt * 2.0 * 64 * 64 * d.npad;
+        P.wtiles.push_back(wt);
         P.gd.push_back(d);
     }
     // larger submatrices first: their tiles are the longest, so they should not form the tail
@@ -262,8 +280,15 @@ int32_t check_plan(smx_ctx c)
     for (int64_t p = 0; p < c->nnzb; p++) {
         const ScatterDesc &s = P.scat[p];
         const GroupDesc &d = P.gd[s.g];
-        if (s.oi + (s.bij & 0xffff) > d.n || s.oj + (s.bij >> 16) > d.n)
+        if (s.oi + (s.bij & 0xffff) > d.n || s.oj + (s.bij >> 16) > d.n || s.ocol + (s.bij >> 16) > d.m_own)
             return fail(c, SMX_E_INVALID, "internal: scatter extent");
+    }
+    for (const GroupDesc &d : P.gd) {
+        if (d.own_off + d.m_own > (int64_t)P.own_list.size() || d.thin_off + (int64_t)d.npad * d.m_own > P.thin_elems)
+            return fail(c, SMX_E_INVALID, "internal: own-column tables");
+        for (int32_t q = 0; q < d.m_own; q++)
+            if (P.own_list[d.own_off + q] < 0 || P.own_list[d.own_off + q] >= d.n)
+                return fail(c, SMX_E_INVALID, "internal: own-column index");
     }
     return SMX_OK;
 }
@@ -294,6 +319,7 @@ int32_t ensure_plan(smx_ctx c)
     HIP_TRY(c, upload(c->d_bmap, P.bmap, c->stream));
     HIP_TRY(c, upload(c->d_boffs, P.boffs, c->stream));
     HIP_TRY(c, upload(c->d_scat, P.scat, c->stream));
+    HIP_TRY(c, upload(c->d_own, P.own_list, c->stream));
     const size_t ng = (size_t)std::max(P.ngroups, 1);
     HIP_TRY(c, c->d_scale.ensure(ng));
     HIP_TRY(c, c->d_done.ensure(ng));
@@ -411,6 +437,15 @@ int32_t smx_destroy(smx_ctx c)
     c->d_kfinal.release();
     c->d_flags.release();
     c->d_ndone.release();
+    c->d_own.release();
+    c->d_tau_parts.release();
+    c->d_tau_hist.release();
+    c->d_wx0.release();
+    c->d_wx1.release();
+    c->d_ww.release();
+    c->d_t0.release();
+    c->d_t1.release();
+    c->d_t2.release();
     if (c->h_ndone) (void)hipHostFree(c->h_ndone);
     for (hipEvent_t ev : c->ev_poll) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->ev_launch) (void)hipEventDestroy(ev);
@@ -558,7 +593,7 @@ int32_t smx_set_temperature(smx_ctx c, double kT)
 int32_t smx_set_precision(smx_ctx c, int32_t mode)
 {
     if (!c) return SMX_E_INVALID;
-    if (mode < SMX_FP64 || mode > SMX_FP32) return fail(c, SMX_E_INVALID, "unknown precision mode");
+    if (mode < SMX_FP64 || mode > SMX_FP16_2W) return fail(c, SMX_E_INVALID, "unknown precision mode");
     c->precision = mode;
     return SMX_OK;
 }
@@ -580,14 +615,27 @@ int32_t smx_evaluate(smx_ctx c)
     if (!c) return SMX_E_INVALID;
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (c->kT > 0.0) return fail(c, SMX_E_UNSUPPORTED, "finite temperature (kT > 0) is not implemented on the GPU path");
-    if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented yet");
+    int fmt = -1, nw = 0;
+    switch (c->precision) {
+    case SMX_FP64: break;
+    case SMX_FP16_2W: fmt = 0; nw = 2; break;
+    case SMX_BF16_3W: fmt = 1; nw = 3; break;
+    case SMX_BF16_1W: fmt = 1; nw = 1; break;
+    default: return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented on the GPU path");
+    }
+    const bool mixed = fmt >= 0;
+    if (mixed && c->max_iter <= c->n_polish)
+        return fail(c, SMX_E_INVALID, "max_iter must exceed n_polish in reduced-precision modes");
     if (int32_t st = set_device(c)) return st;
     c->evaluated = false;
     if (int32_t st = ensure_plan(c)) return st;
     const Plan &P = c->plan;
     const int32_t ng = P.ngroups;
-    const int32_t stride = c->max_iter + 2;
+    const int32_t stride = c->max_iter + 2 + c->n_polish;
     HIP_TRY(c, c->d_resid.ensure((size_t)ng * stride));
+    const int32_t tau_nt = (P.max_npad + kTile - 1) / kTile;
+    HIP_TRY(c, c->d_tau_parts.ensure((size_t)ng * std::max(tau_nt, 1)));
+    HIP_TRY(c, c->d_tau_hist.ensure((size_t)ng * stride));
     if (c->h_ndone_cap < stride) {
         if (c->h_ndone) (void)hipHostFree(c->h_ndone);
         c->h_ndone = nullptr;
@@ -599,6 +647,16 @@ int32_t smx_evaluate(smx_ctx c)
         HIP_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         c->ev_poll.push_back(ev);
     }
+    if (mixed) {
+        const size_t words = (size_t)nw * (size_t)P.work_elems;
+        HIP_TRY(c, c->d_wx0.ensure(words));
+        HIP_TRY(c, c->d_wx1.ensure(words));
+        HIP_TRY(c, c->d_ww.ensure(words));
+        const size_t thin = (size_t)std::max<int64_t>(P.thin_elems, 1);
+        HIP_TRY(c, c->d_t0.ensure(thin));
+        HIP_TRY(c, c->d_t1.ensure(thin));
+        HIP_TRY(c, c->d_t2.ensure(thin));
+    }
     hipStream_t st = c->stream;
     IterState it;
     it.scale_bits = c->d_scale.p;
@@ -607,7 +665,10 @@ int32_t smx_evaluate(smx_ctx c)
     it.kfinal = c->d_kfinal.p;
     it.flags = c->d_flags.p;
     it.ndone = c->d_ndone.p;
+    it.tau_parts = c->d_tau_parts.p;
+    it.tau_hist = c->d_tau_hist.p;
     it.resid_stride = stride;
+    it.tau_nt = std::max(tau_nt, 1);
 
     HIP_TRY(c, hipEventRecord(c->ev_t0, st));
     HIP_TRY(c, hipMemsetAsync(it.scale_bits, 0, sizeof(unsigned long long) * ng, st));
@@ -618,13 +679,15 @@ int32_t smx_evaluate(smx_ctx c)
     HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
     HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
                              c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_x0.p, it.scale_bits));
+    const int64_t plane = P.work_elems;
+    if (mixed)
+        HIP_TRY(c, launch_to_words(st, fmt, nw, ng, P.max_npad, c->d_gd.p, c->d_x0.p, it.scale_bits, c->d_wx0.p,
+                                   plane));
     HIP_TRY(c, hipEventRecord(c->ev_t1, st));
 
-    double *xb[2] = {c->d_x0.p, c->d_x1.p};
-    int32_t launched = 0;
     c->launch_step.clear();
-    c->launch_mode.clear();
-    auto timed = [&](int mode, int k, const double *x, const double *b, double *o) -> hipError_t {
+    c->launch_kind.clear();
+    auto timed = [&](int kind, int k, auto &&launch) -> hipError_t {
         const size_t idx = c->launch_step.size();
         while (c->ev_launch.size() < 2 * (idx + 1)) {
             hipEvent_t ev;
@@ -633,17 +696,32 @@ int32_t smx_evaluate(smx_ctx c)
             c->ev_launch.push_back(ev);
         }
         hipError_t e = hipEventRecord(c->ev_launch[2 * idx], st);
-        if (e == hipSuccess)
-            e = launch_ns_f64(st, mode, (int)P.tiles.size(), c->d_tiles.p, c->d_gd.p, x, b, o, it, k, c->tol,
-                              c->max_iter);
+        if (e == hipSuccess) e = launch();
         if (e == hipSuccess) e = hipEventRecord(c->ev_launch[2 * idx + 1], st);
         c->launch_step.push_back(k);
-        c->launch_mode.push_back(mode);
+        c->launch_kind.push_back(kind);
         return e;
     };
-    for (int32_t k = 0; k <= c->max_iter; k++) {
-        HIP_TRY(c, timed(0, k, xb[k & 1], xb[k & 1], c->d_w.p));
-        HIP_TRY(c, timed(1, k, xb[k & 1], c->d_w.p, xb[(k + 1) & 1]));
+    const int ntiles = (int)P.tiles.size();
+    // bulk steps: every group iterates until its own stopping rule; the host
+    // polls the finished-group counter one step behind the device
+    const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
+    double *xb[2] = {c->d_x0.p, c->d_x1.p};
+    unsigned short *wb[2] = {c->d_wx0.p, c->d_wx1.p};
+    int32_t launched = 0;
+    for (int32_t k = 0; k <= kmax; k++) {
+        if (!mixed) {
+            HIP_TRY(c, timed(0, k, [&] { return launch_ns_f64(st, 0, ntiles, c->d_tiles.p, c->d_gd.p, xb[k & 1], xb[k & 1],
+                                                              c->d_w.p, it, k, c->tol, c->max_iter, 0); }));
+            HIP_TRY(c, timed(1, k, [&] { return launch_ns_f64(st, 1, ntiles, c->d_tiles.p, c->d_gd.p, xb[k & 1], c->d_w.p,
+                                                              xb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
+        } else {
+            HIP_TRY(c, timed(2, k, [&] { return launch_ns_words(st, fmt, nw, 0, ntiles, c->d_tiles.p, c->d_gd.p, wb[k & 1],
+                                                                wb[k & 1], c->d_ww.p, plane, it, k, c->switch_tol, kmax); }));
+            HIP_TRY(c, timed(3, k, [&] { return launch_ns_words(st, fmt, nw, 1, ntiles, c->d_tiles.p, c->d_gd.p, wb[k & 1],
+                                                                c->d_ww.p, wb[(k + 1) & 1], plane, it, k, c->switch_tol,
+                                                                kmax); }));
+        }
         launched = k + 1;
         HIP_TRY(c, hipMemcpyAsync(c->h_ndone + k, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipEventRecord(c->ev_poll[k], st));
@@ -652,14 +730,36 @@ int32_t smx_evaluate(smx_ctx c)
             if (c->h_ndone[k - 1] >= ng) break;
         }
     }
+    if (mixed) {
+        // FP64 polish: n_polish - 1 full steps, then the last step on the own columns only
+        HIP_TRY(c, launch_from_words(st, fmt, nw, ng, P.max_npad, c->d_gd.p, c->d_wx0.p, c->d_wx1.p, it.kfinal, plane,
+                                     c->d_x0.p));
+        int cur = 0;
+        for (int32_t q = 0; q + 1 < c->n_polish; q++) {
+            const int slot = c->max_iter + 1 + q;
+            HIP_TRY(c, timed(4, slot, [&] { return launch_ns_f64(st, 0, ntiles, c->d_tiles.p, c->d_gd.p, xb[cur], xb[cur],
+                                                                 c->d_w.p, it, slot, c->tol, c->max_iter, 1); }));
+            HIP_TRY(c, timed(5, slot, [&] { return launch_ns_f64(st, 1, ntiles, c->d_tiles.p, c->d_gd.p, xb[cur], c->d_w.p,
+                                                                 xb[cur ^ 1], it, slot, c->tol, c->max_iter, 1); }));
+            cur ^= 1;
+        }
+        HIP_TRY(c, launch_own_polish(st, ng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, xb[cur], c->d_t0.p,
+                                     c->d_t1.p, c->d_t2.p, it, c->max_iter + c->n_polish));
+    }
     HIP_TRY(c, hipEventRecord(c->ev_t2, st));
-    HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_x0.p, c->d_x1.p, it, c->d_k.p,
-                              c->d_d.p, c->d_pe.p, c->d_pn.p));
+    if (mixed)
+        HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_t2.p, nullptr, it, c->d_k.p,
+                                  c->d_d.p, c->d_pe.p, c->d_pn.p, 1));
+    else
+        HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_x0.p, c->d_x1.p, it, c->d_k.p,
+                                  c->d_d.p, c->d_pe.p, c->d_pn.p, 0));
     HIP_TRY(c, launch_reduce(st, c->nnzb, c->d_pe.p, c->d_pn.p, c->d_ne.p));
     HIP_TRY(c, hipEventRecord(c->ev_t3, st));
     c->steps_launched = launched;
     c->last_precision = c->precision;
     c->last_stride = stride;
+    c->last_polish = mixed ? c->n_polish : 0;
+    c->last_max_iter = c->max_iter;
     c->evaluated = true;
     return SMX_OK;
 }
@@ -731,10 +831,13 @@ int32_t smx_get_group_info(smx_ctx c, int32_t *n_g, int32_t *iters, double *scal
     HIP_TRY(c, hipMemcpy(rb.data(), c->d_resid.p, rb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     for (int32_t g = 0; g < ng; g++) {
         if (n_g) n_g[g] = c->plan.gd[g].n;
-        if (iters) iters[g] = kf[g];
+        if (iters) iters[g] = kf[g] + c->last_polish;
+        // FP64 mode: residual of the returned X_k; reduced-precision modes: residual of
+        // the last full FP64 iterate on the own columns (the final step is own-column only)
+        const size_t slot = c->last_polish ? (size_t)(c->last_max_iter + c->last_polish) : (size_t)kf[g];
         double s, r;
         std::memcpy(&s, &sb[g], sizeof s);
-        std::memcpy(&r, &rb[(size_t)g * c->last_stride + kf[g]], sizeof r);
+        std::memcpy(&r, &rb[(size_t)g * c->last_stride + slot], sizeof r);
         if (scale) scale[g] = s;
         if (resid) resid[g] = r;
     }
@@ -772,24 +875,24 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
     }
     s.n_mean = ng ? nsum / ng : 0;
     s.iters_mean = ng ? isum / ng : 0;
-    // issued matrix-core flops: every step runs the square product; all but the last the update
+    // issued matrix-core flops of the product kernels (live wave tiles, padding included)
     double exec = 0;
     {
-        // per group: (2 k_g + 1) products of its live wave tiles
         const Plan &P = c->plan;
+        int npairs = 1;
+        if (c->last_precision == SMX_FP16_2W) npairs = 3;
+        if (c->last_precision == SMX_BF16_3W) npairs = 6;
         for (int32_t g = 0; g < ng; g++) {
             const GroupDesc &d = P.gd[g];
-            const int32_t nt = (d.npad + kTile - 1) / kTile;
-            double wt = 0;
-            for (int32_t ti = 0; ti < nt; ti++)
-                for (int32_t tj = 0; tj <= ti; tj++)
-                    for (int wr = 0; wr < 2; wr++)
-                        for (int wc = 0; wc < 2; wc++) {
-                            if (ti * kTile + wr * 64 >= d.npad || tj * kTile + wc * 64 >= d.npad) continue;
-                            if (ti == tj && wr < wc) continue;
-                            wt += 1;
-                        }
-            exec += wt * 2.0 * 64 * 64 * d.npad * (2.0 * it[g] + 1.0);
+            const double per = P.wtiles[g] * 2.0 * 64 * 64 * d.npad;
+            const double kb = it[g] - c->last_polish;     // bulk steps taken
+            if (c->last_polish == 0) {
+                exec += per * (2.0 * kb + 1.0);
+            } else {
+                exec += per * npairs * (2.0 * kb + 1.0);
+                exec += per * 2.0 * (c->last_polish - 1);
+                exec += 2.0 * 2.0 * (double)d.n * d.n * d.m_own;
+            }
         }
     }
     s.exec_flops = exec;
@@ -811,7 +914,8 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
     return SMX_OK;
 }
 
-int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_flops, int32_t *count)
+int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_flops, int32_t *kind,
+                               int32_t *count)
 {
     if (!c) return SMX_E_INVALID;
     if (int32_t st = need_sync_results(c)) return st;
@@ -820,6 +924,8 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
     std::vector<int32_t> kf((size_t)c->plan.ngroups);
     HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t l = 0; l < nl && l < cap; l++) {
+        const int32_t kd = c->launch_kind[l];
+        if (kind) kind[l] = kd;
         if (ms) {
             float t = 0;
             HIP_TRY(c, hipEventElapsedTime(&t, c->ev_launch[2 * l], c->ev_launch[2 * l + 1]));
@@ -829,7 +935,9 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
             const int32_t k = c->launch_step[l];
             double f = 0;
             for (int32_t g = 0; g < c->plan.ngroups; g++) {
-                const bool active = c->launch_mode[l] == 0 ? (k <= kf[g]) : (k < kf[g]);
+                bool active = true;                           // polish launches work on every group
+                if (kd == 0 || kd == 2) active = k <= kf[g];  // squares run up to the last step
+                if (kd == 1 || kd == 3) active = k < kf[g];   // updates stop one earlier
                 const double n = c->plan.gd[g].n;
                 if (active) f += 2.0 * n * n * n;
             }
@@ -870,6 +978,11 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dch.release();
         src = c->d_w.p + d.off;
+    } else if (c->last_polish) {
+        // reduced-precision modes: the last full FP64 iterate (the final step
+        // is computed on the own columns only)
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        src = (((c->last_polish - 1) & 1) ? c->d_x1.p : c->d_x0.p) + d.off;
     } else {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         int32_t kf = 0;

@@ -18,10 +18,13 @@ struct GroupDesc {
     int64_t off;        // element offset of the group's dense matrices in the work buffers
     int64_t map_off;    // offset of the m x m block map (int32 storage positions, -1 = not stored)
     int64_t rinfo_off;  // offset of the per-row table (npad entries)
+    int64_t thin_off;   // element offset of the group's npad x m_own own-column buffers
     int32_t boff_off;   // offset of the m+1 block offsets inside the submatrix
     int32_t n;          // true dimension n_g
     int32_t npad;       // padded dimension = leading dimension (multiple of kPad)
     int32_t m;          // number of block rows |R(g)|
+    int32_t own_off;    // offset of the group's own-column list (submatrix column indices)
+    int32_t m_own;      // number of own columns (sum of the member block sizes)
 };
 
 // Row table entry: x = local block index in R(g); y = (row inside block) | (block size << 16).
@@ -36,6 +39,8 @@ struct ScatterDesc {
     int32_t oi;         // row offset of block row I inside the submatrix
     int32_t oj;         // column offset of block column J inside the submatrix
     int32_t bij;        // b_I | (b_J << 16)
+    int32_t ocol;       // position of block column J's first column in the own-column list
+    int32_t pad;
 };
 
 // Per-evaluation device state of the iteration.
@@ -46,7 +51,10 @@ struct IterState {
     int32_t *kfinal;                  // [ngroups] step k whose X_k is the result
     int32_t *flags;                   // [ngroups] bit 0: not converged, bit 1: non-finite
     int32_t *ndone;                   // [1] number of finished groups
-    int32_t resid_stride;             // max_iter + 2
+    double *tau_parts;                // [ngroups * tau_nt] per diagonal tile: sum of (1 - T_ii)
+    double *tau_hist;                 // [ngroups * resid_stride] Tr(I - X_k^2) per step
+    int32_t resid_stride;             // steps 0..max_iter, then one slot per polish step
+    int32_t tau_nt;                   // tile rows of the largest group
 };
 
 // ---- launchers (stream-ordered, no synchronisation) -----------------------
@@ -59,14 +67,36 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
 // mode 0: T = a^2 X X, records max|T - I| for step k, writes W = 1.5 I - 0.5 T.
 // mode 1: if the step-k residual meets the stopping rule the group is finished
 //         at X_k; otherwise X_{k+1} = a X W.   a = 1/s_g at k = 0, else 1.
+// polish != 0: unconditional step on every group (a = 1, no skipping, no
+// stopping); the square's residual goes to slot k of the residual history.
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
-                         const IterState &it, int k, double tol, int max_iter);
+                         const IterState &it, int k, double tol, int max_iter, int polish);
 
+// Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value).
+hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
+                           const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
+                           unsigned short *out, int64_t plane, const IterState &it, int k, double switch_tol,
+                           int kmax);
+hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+                           const double *src, const unsigned long long *scale_bits, unsigned short *dst,
+                           int64_t plane);
+hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+                             const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal,
+                             int64_t plane, double *dst);
+
+// Last polish step restricted to the own columns (FP64, vector ALU):
+//   O = P[:, own];  Y = P O (residual of P^2 on the own columns -> slot);  F = 1.5 O - 0.5 P Y.
+hipError_t launch_own_polish(hipStream_t st, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
+                             const int32_t *own_list, const double *p, double *o, double *y, double *f,
+                             const IterState &it, int slot);
+
+// from_thin = 0: S_g = a X_kfinal (full matrices x0 / x1 by step parity);
+// from_thin = 1: S_g own columns from the npad x m_own buffer x0.
 hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd,
                           const int64_t *valoff, const GroupDesc *groups, const double *x0,
                           const double *x1, const IterState &it, const double *kvals,
-                          double *dvals, double *part_e, double *part_n);
+                          double *dvals, double *part_e, double *part_n, int from_thin);
 
 hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const double *part_n,
                          double *out2);

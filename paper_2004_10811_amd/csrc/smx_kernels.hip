@@ -81,10 +81,12 @@ void gather_shift_kernel(const int2 *__restrict__ chunks, const GroupDesc *__res
 
 // ---------------------------------------------------------------------------
 // Scatter (Sec. III-A step 3): for every stored block (I, J) of an own
-// column J of group g, D_IJ = (delta_IJ I - S_g[I rows, J cols]) / 2 with
-// S_g = a X_k (a = 1/s_g only when the result is X_0).  Also writes the
+// column J of group g, D_IJ = (delta_IJ I - S_g[I rows, J cols]) / 2.  The
+// sign S_g is either a X_k (full matrix, a = 1/s_g only when the result is
+// X_0) or the own-column buffer of the last polish step.  Also writes the
 // block's <D_IJ, K_IJ> and, for diagonal blocks, tr D_JJ.  One wave per block.
 // ---------------------------------------------------------------------------
+template <int FROM_THIN>
 __global__ __launch_bounds__(256)
 void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
                     const int64_t *__restrict__ valoff, const GroupDesc *__restrict__ groups,
@@ -98,12 +100,20 @@ void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
     if (p >= nblocks) return;
     const ScatterDesc d = sd[p];
     const GroupDesc gd = groups[d.g];
-    const int kf = kfinal[d.g];
-    const double *xs = ((kf & 1) ? x1 : x0) + gd.off;
+    const double *xs;
+    int col0;
     double a = 1.0;
-    if (kf == 0) {
-        const double s = __longlong_as_double((long long)scale_bits[d.g]);
-        a = s > 0.0 ? 1.0 / s : 0.0;
+    if (FROM_THIN) {
+        xs = x0 + gd.thin_off;
+        col0 = d.ocol;
+    } else {
+        const int kf = kfinal[d.g];
+        xs = ((kf & 1) ? x1 : x0) + gd.off;
+        col0 = d.oj;
+        if (kf == 0) {
+            const double s = __longlong_as_double((long long)scale_bits[d.g]);
+            a = s > 0.0 ? 1.0 / s : 0.0;
+        }
     }
     const int bi = d.bij & 0xffff, bj = d.bij >> 16;
     const bool diag = (d.oi == d.oj);
@@ -112,7 +122,7 @@ void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
     double e = 0.0, tr = 0.0;
     for (int t = lane; t < nel; t += 64) {
         const int rr = t % bi, cc = t / bi;
-        const double s = a * xs[(int64_t)(d.oi + rr) + (int64_t)(d.oj + cc) * gd.npad];
+        const double s = a * xs[(int64_t)(d.oi + rr) + (int64_t)(col0 + cc) * gd.npad];
         const double dv = 0.5 * ((diag && rr == cc) ? 1.0 : 0.0) - 0.5 * s;
         dvals[vo + t] = dv;
         e += dv * kvals[vo + t];
@@ -123,6 +133,86 @@ void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
     if (lane == 0) {
         part_e[p] = e;
         part_n[p] = tr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Last FP64 polish step on the own columns only.  The scatter needs only the
+// group's own columns of X_{k+1} = X_k (3I - X_k^2) / 2, which equal
+// 1.5 X_k[:, own] - 0.5 X_k (X_k X_k[:, own]): two thin products instead of
+// two dense ones.  One thread per row, up to 32 own columns per pass, the
+// thin operand staged through LDS in steps of 64 rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256)
+void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
+                       const double *__restrict__ p, double *__restrict__ o)
+{
+    const GroupDesc gd = groups[blockIdx.y];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= gd.npad) return;
+    for (int c = 0; c < gd.m_own; c++)
+        o[gd.thin_off + r + (int64_t)c * gd.npad] = p[gd.off + r + (int64_t)own_list[gd.own_off + c] * gd.npad];
+}
+
+// MODE 0: y = P b, residual max|y - I[:, own]| -> slot.  MODE 1: y = 1.5 o - 0.5 P b.
+template <int MODE>
+__global__ __launch_bounds__(256)
+void thin_mul_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
+                     const double *__restrict__ p, const double *__restrict__ b, const double *__restrict__ o,
+                     double *__restrict__ y, IterState it, int slot)
+{
+    __shared__ double bs[64][33];
+    const int g = blockIdx.y;
+    const GroupDesc gd = groups[g];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256 >= gd.npad) return;          // whole block beyond this group
+    const bool live = r < gd.npad;
+    const double *pg = p + gd.off;
+    double rmax = 0.0;
+    for (int c0 = 0; c0 < gd.m_own; c0 += 32) {
+        const int nc = min(32, gd.m_own - c0);
+        double acc[32];
+#pragma unroll
+        for (int c = 0; c < 32; c++) acc[c] = 0.0;
+        for (int k0 = 0; k0 < gd.n; k0 += 64) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < 64 * 32; t += 256) {
+                const int kk = t & 63, cc = t >> 6;
+                const int kr = k0 + kk;
+                bs[kk][cc] = (kr < gd.n && cc < nc) ? b[gd.thin_off + kr + (int64_t)(c0 + cc) * gd.npad] : 0.0;
+            }
+            __syncthreads();
+            const int kend = min(64, gd.n - k0);
+            if (live) {
+                for (int kk = 0; kk < kend; kk++) {
+                    const double pv = pg[r + (int64_t)(k0 + kk) * gd.npad];
+#pragma unroll
+                    for (int c = 0; c < 32; c++) acc[c] = fma(pv, bs[kk][c], acc[c]);
+                }
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < 32; c++) {
+                if (c >= nc) break;
+                const int64_t idx = gd.thin_off + r + (int64_t)(c0 + c) * gd.npad;
+                if (MODE == 0) {
+                    y[idx] = acc[c];
+                    if (r < gd.n) {
+                        double d = fabs(acc[c] - (r == own_list[gd.own_off + c0 + c] ? 1.0 : 0.0));
+                        if (!(d <= 1.7976931348623157e308)) d = __builtin_huge_val();
+                        rmax = fmax(rmax, d);
+                    }
+                } else {
+                    y[idx] = 1.5 * o[idx] - 0.5 * acc[c];
+                }
+            }
+        }
+    }
+    if (MODE == 0) {
+        rmax = wave_max(rmax);
+        if ((threadIdx.x & 63) == 0)
+            atomic_max_nonneg(it.resid_bits + (int64_t)g * it.resid_stride + slot, rmax);
     }
 }
 
@@ -210,12 +300,28 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
 hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd,
                           const int64_t *valoff, const GroupDesc *groups, const double *x0,
                           const double *x1, const IterState &it, const double *kvals,
-                          double *dvals, double *part_e, double *part_n)
+                          double *dvals, double *part_e, double *part_n, int from_thin)
 {
     if (nblocks <= 0) return hipSuccess;
     const int64_t grid = (nblocks + 3) / 4;
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
-                       groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
+    if (from_thin)
+        hipLaunchKernelGGL(scatter_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
+                           groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
+    else
+        hipLaunchKernelGGL(scatter_kernel<0>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
+                           groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_own_polish(hipStream_t st, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
+                             const int32_t *own_list, const double *p, double *o, double *y, double *f,
+                             const IterState &it, int slot)
+{
+    if (ngroups <= 0 || max_own <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_npad + 255) / 256), (unsigned)ngroups);
+    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, p, o);
+    hipLaunchKernelGGL(thin_mul_kernel<0>, grid, dim3(256), 0, st, groups, own_list, p, o, o, y, it, slot);
+    hipLaunchKernelGGL(thin_mul_kernel<1>, grid, dim3(256), 0, st, groups, own_list, p, y, o, f, it, slot);
     return hipGetLastError();
 }
 

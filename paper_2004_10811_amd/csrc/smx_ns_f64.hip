@@ -44,24 +44,24 @@ template <int MODE>
 __global__ __launch_bounds__(256, 2)
 void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
                    const double *__restrict__ xin, const double *__restrict__ bin,
-                   double *__restrict__ out, IterState it, int k, double tol, int max_iter)
+                   double *__restrict__ out, IterState it, int k, double tol, int max_iter, int polish)
 {
     __shared__ double As[2][BM][SK];
     __shared__ double Bs[2][BM][SK];
 
     const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
-    if (it.done[g]) return;                       // finished at an earlier step
+    if (!polish && it.done[g]) return;            // finished at an earlier step
     const int ti = td.y >> 16, tj = td.y & 0xffff;
     const GroupDesc gd = groups[g];
     const int ld = gd.npad;
 
     double a = 1.0;
-    if (k == 0) {
+    if (k == 0 && !polish) {
         const double s = __longlong_as_double((long long)it.scale_bits[g]);
         a = s > 0.0 ? 1.0 / s : 0.0;
     }
-    if (MODE == 1) {
+    if (MODE == 1 && !polish) {
         const double rk = __longlong_as_double((long long)it.resid_bits[(int64_t)g * it.resid_stride + k]);
         const bool finite = rk <= 1.7976931348623157e308;
         if (rk <= tol || k >= max_iter || !finite) {
@@ -203,15 +203,15 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
 
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
-                         const IterState &it, int k, double tol, int max_iter)
+                         const IterState &it, int k, double tol, int max_iter, int polish)
 {
     if (ntiles <= 0) return hipSuccess;
     if (mode == 0)
         hipLaunchKernelGGL(ns_f64_kernel<0>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
-                           out, it, k, tol, max_iter);
+                           out, it, k, tol, max_iter, polish);
     else
         hipLaunchKernelGGL(ns_f64_kernel<1>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
-                           out, it, k, tol, max_iter);
+                           out, it, k, tol, max_iter, polish);
     return hipGetLastError();
 }
 
