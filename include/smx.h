@@ -154,7 +154,8 @@ int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
  * reduced-precision modes the bulk runs until tau_k = Tr(I - X_k^2) <=
  * switch_tol (tau_k bounds the largest 1 - x_i^2 over the eigenvalues x_i
  * of X_k, all of which lie in [-1, 1]), or until tau_k stops falling
- * (tau_k < 0.1 and tau_k > tau_{k-1}/2), or for at most max_iter - n_polish
+ * (tau_k >= tau_{k-1}, or tau_k < 0.1 and tau_k > tau_{k-1}/2), or for at
+ * most max_iter - n_polish
  * steps, and is followed by n_polish FP64 steps (>= 1); the last of them is
  * computed on the group's own columns only, since only those enter D.
  * Defaults: tol 1e-12, max_iter 100, n_polish 2, switch_tol 1e-3.

@@ -246,10 +246,35 @@ int32_t build_plan(smx_ctx c)
         P.wtiles.push_back(wt);
         P.gd.push_back(d);
     }
-    // larger submatrices first: their tiles are the longest, so they should not form the tail
-    std::stable_sort(P.tiles.begin(), P.tiles.end(), [&](const TileDesc &x, const TileDesc &y) {
-        return P.gd[x.x].npad > P.gd[y.x].npad;
-    });
+    // XCD-aware launch order.  Workgroup b of a launch runs on XCD b % 8 (the
+    // dispatcher deals workgroups round-robin over the 8 XCDs), and every XCD
+    // has its own L2.  All tiles of one group go to one XCD, so the group's
+    // panels are fetched into one L2 and shared by its tiles; groups are
+    // dealt to XCDs greedily by work (n_pad x tiles), largest first.  Slot
+    // s of XCD x becomes workgroup 8 s + x; short lists are padded with idle
+    // tiles (group -1).
+    {
+        constexpr int kXcd = 8;
+        std::vector<int32_t> order(ng);
+        for (int32_t g = 0; g < ng; g++) order[g] = g;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.gd[a].npad > P.gd[b].npad; });
+        std::vector<std::vector<TileDesc>> lists(kXcd);
+        std::vector<double> load(kXcd, 0.0);
+        std::vector<std::vector<TileDesc>> per_group(ng);
+        for (const TileDesc &t : P.tiles) per_group[t.x].push_back(t);
+        for (int32_t g : order) {
+            int best = 0;
+            for (int x = 1; x < kXcd; x++)
+                if (load[x] < load[best]) best = x;
+            load[best] += (double)P.gd[g].npad * per_group[g].size();
+            for (const TileDesc &t : per_group[g]) lists[best].push_back(t);
+        }
+        size_t len = 0;
+        for (const auto &l : lists) len = std::max(len, l.size());
+        P.tiles.assign(len * kXcd, TileDesc{-1, 0});
+        for (int x = 0; x < kXcd; x++)
+            for (size_t q = 0; q < lists[x].size(); q++) P.tiles[q * kXcd + x] = lists[x][q];
+    }
     for (int64_t p = 0; p < c->nnzb; p++)
         if (P.scat[p].g < 0) return fail(c, SMX_E_INVALID, "internal: stored block without a group");
     return SMX_OK;
@@ -260,6 +285,7 @@ int32_t check_plan(smx_ctx c)
 {
     const Plan &P = c->plan;
     for (const TileDesc &t : P.tiles) {
+        if (t.x == -1) continue;    // idle slot of the XCD-aware launch order
         if (t.x < 0 || t.x >= P.ngroups) return fail(c, SMX_E_INVALID, "internal: tile group");
         const GroupDesc &d = P.gd[t.x];
         const int ti = t.y >> 16, tj = t.y & 0xffff;

@@ -51,6 +51,7 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
 
     const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
+    if (g < 0) return;                            // idle slot of the launch order
     if (!polish && it.done[g]) return;            // finished at an earlier step
     const int ti = td.y >> 16, tj = td.y & 0xffff;
     const GroupDesc gd = groups[g];

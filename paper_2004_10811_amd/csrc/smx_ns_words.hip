@@ -23,8 +23,9 @@
 // lies in [-1, 1], so tau_k bounds the largest 1 - x_i^2 from above (the
 // entrywise max|X_k^2 - I| does not: for a delocalised eigenvector it is
 // far smaller than the eigenvalue error).  The group leaves the bulk at X_k
-// once tau_k <= switch_tol, or once tau_k stops falling (tau_k < 0.1 and
-// tau_k > tau_{k-1} / 2: the floor of the word format), or at the step cap;
+// once tau_k <= switch_tol, or once tau_k stops falling (tau_k >= tau_{k-1},
+// or tau_k < 0.1 and tau_k > tau_{k-1} / 2: the floor of the word format), or
+// at the step cap;
 // the FP64 polish steps follow.  tau_k is reduced in a fixed order (per
 // diagonal tile, then over the tiles), so the decision is reproducible.
 #include "smx_internal.h"
@@ -39,8 +40,6 @@ typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = kTile;   // 128
-constexpr int BK = 32;      // K per MFMA step
-constexpr int SK = BK + 8;  // LDS row stride in 16-bit words (80 B: 16-B aligned, conflict-free b128 reads)
 
 // Power-of-two scale applied to every value before it is split into words.
 // FP16 has a 5-bit exponent: subnormal FP16 words keep fewer significant
@@ -119,6 +118,62 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+template <int FMT>
+__device__ inline unsigned short to_word_f(float v);
+template <>
+__device__ inline unsigned short to_word_f<0>(float v)
+{
+    return __builtin_bit_cast(unsigned short, (_Float16)v);
+}
+template <>
+__device__ inline unsigned short to_word_f<1>(float v)
+{
+    unsigned int u = __builtin_bit_cast(unsigned int, v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+template <int FMT>
+__device__ inline float from_word_f(unsigned short w)
+{
+    if constexpr (FMT == 0)
+        return (float)__builtin_bit_cast(_Float16, w);
+    else
+        return __builtin_bit_cast(float, ((unsigned int)w) << 16);
+}
+
+// Split 8 FP32 values (already scaled) into NW word vectors.  Each remainder
+// x - round(x) is exact in FP32, so the words sum to x up to the last word's
+// rounding.
+template <int FMT, int NW>
+__device__ inline void split8(const float *v, u16x8 *wv)
+{
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        float rem = v[e];
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const unsigned short u = to_word_f<FMT>(rem);
+            wv[w][e] = u;
+            rem -= from_word_f<FMT>(u);
+        }
+    }
+}
+
+// K is staged in steps of 64 (a full 128-B line per column and word plane),
+// handed to the matrix cores in two sub-steps of 32; the next step's operands
+// are prefetched into registers while the current one is multiplied.  The
+// epilogue stages the FP32 tile in LDS (the operand buffers are reused) and
+// writes words of the tile and of its mirror with 16-B stores.
+constexpr int BK2 = 64;
+constexpr int SK2 = BK2 + 8;      // 144-B LDS rows: 16-B aligned
+constexpr int CST = BM + 4;       // FP32 staging tile, column-major, 528-B columns
+
+template <int NW>
+__host__ __device__ constexpr int words_lds_bytes()
+{
+    return (2 * NW * BM * SK2 * 2) > (BM * CST * 4) ? (2 * NW * BM * SK2 * 2) : (BM * CST * 4);
+}
+
 template <int FMT, int NW, int MODE>
 __global__ __launch_bounds__(256, 2)
 void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
@@ -126,11 +181,15 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                      unsigned short *__restrict__ out, int64_t plane, IterState it, int k,
                      double switch_tol, int kmax)
 {
-    __shared__ unsigned short As[NW][BM][SK];
-    __shared__ unsigned short Bs[NW][BM][SK];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[words_lds_bytes<NW>()];
+    __shared__ double wsum[4];
+    unsigned short *As = reinterpret_cast<unsigned short *>(smem);          // [NW][BM][SK2]
+    unsigned short *Bs = As + NW * BM * SK2;                                 // [NW][BM][SK2]
+    float *Cs = reinterpret_cast<float *>(smem);                             // [BM][CST] after the loop
 
     const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
+    if (g < 0) return;                  // idle slot of the launch order
     if (it.done[g]) return;
     const int ti = td.y >> 16, tj = td.y & 0xffff;
     const GroupDesc gd = groups[g];
@@ -144,7 +203,9 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         for (int t = 0; t < nt; t++) tau += it.tau_parts[(int64_t)g * it.tau_nt + t];
         const double tp = k > 0 ? it.tau_hist[base + k - 1] : __builtin_huge_val();
         const bool finite = (rk <= 1.7976931348623157e308) && (fabs(tau) <= 1.7976931348623157e308);
-        const bool stall = (tau < 0.1) && (tau > 0.5 * tp);
+        // floor of the word format: tau stops halving in the quadratic phase, or
+        // stops falling at all (in the linear phase every 1 - x_i^2 shrinks)
+        const bool stall = ((tau < 0.1) && (tau > 0.5 * tp)) || (tau >= tp);
         if (ti == 0 && tj == 0 && threadIdx.x == 0) it.tau_hist[base + k] = tau;
         if (tau <= switch_tol || stall || k >= kmax || !finite) {
             if (ti == 0 && tj == 0 && threadIdx.x == 0) {
@@ -162,9 +223,9 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    // staging: thread owns 16 consecutive k (32 B per word plane) of one tile column
+    // staging: thread owns 32 consecutive k (64 B per word plane) of one tile column
     const int lcol = tid >> 1;
-    const int lk = (tid & 1) * 16;
+    const int lk = (tid & 1) * 32;
     const int ga = ti * BM + lcol;
     const int gb = tj * BM + lcol;
     const bool va = ga < ld, vb = gb < ld;
@@ -180,28 +241,30 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    u16x8 ra[NW][2], rb[NW][2];
+    u16x8 ra[NW][4], rb[NW][4];
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     auto gload = [&](int k0) {
+        // ld is a multiple of 32: the last step may hold only 32 valid k (lk = 32 half is then zero)
+        const bool kv = k0 + lk < ld;
 #pragma unroll
         for (int w = 0; w < NW; w++)
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                ra[w][h] = va ? *reinterpret_cast<const u16x8 *>(pa + w * plane + k0 + 8 * h) : z8;
-                rb[w][h] = vb ? *reinterpret_cast<const u16x8 *>(pb + w * plane + k0 + 8 * h) : z8;
+            for (int h = 0; h < 4; h++) {
+                ra[w][h] = (va && kv) ? *reinterpret_cast<const u16x8 *>(pa + w * plane + k0 + 8 * h) : z8;
+                rb[w][h] = (vb && kv) ? *reinterpret_cast<const u16x8 *>(pb + w * plane + k0 + 8 * h) : z8;
             }
     };
     auto sstore = [&]() {
 #pragma unroll
         for (int w = 0; w < NW; w++)
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                *reinterpret_cast<u16x8 *>(&As[w][lcol][lk + 8 * h]) = ra[w][h];
-                *reinterpret_cast<u16x8 *>(&Bs[w][lcol][lk + 8 * h]) = rb[w][h];
+            for (int h = 0; h < 4; h++) {
+                *reinterpret_cast<u16x8 *>(&As[(w * BM + lcol) * SK2 + lk + 8 * h]) = ra[w][h];
+                *reinterpret_cast<u16x8 *>(&Bs[(w * BM + lcol) * SK2 + lk + 8 * h]) = rb[w][h];
             }
     };
 
-    const int nk = ld / BK;
+    const int nk = (ld + BK2 - 1) / BK2;
     const int li = lane & 15;
     const int lq = (lane >> 4) * 8;     // k offset of this lane's 8 operand values
     gload(0);
@@ -209,68 +272,126 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         __syncthreads();                // previous step's LDS reads are done
         sstore();
         __syncthreads();
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        const int nsub = (ld - kt * BK2) >= BK2 ? 2 : 1;
+        if (kt + 1 < nk) gload((kt + 1) * BK2);
         if (wave_live) {
-            u16x8 av[4][NW], bv[4][NW];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int w = 0; w < NW; w++) {
-                    av[i][w] = *reinterpret_cast<const u16x8 *>(&As[w][wr * 64 + i * 16 + li][lq]);
-                    bv[i][w] = *reinterpret_cast<const u16x8 *>(&Bs[w][wc * 64 + i * 16 + li][lq]);
-                }
-#pragma unroll
-            for (int pr = npairs<NW>() - 1; pr >= 0; pr--)      // least significant products first
+            for (int sub = 0; sub < nsub; sub++) {
+                u16x8 av[4][NW], bv[4][NW];
 #pragma unroll
                 for (int i = 0; i < 4; i++)
 #pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        acc[i][j] = mfma16<FMT>(av[i][pair_p(pr)], bv[j][pair_q(pr)], acc[i][j]);
+                    for (int w = 0; w < NW; w++) {
+                        av[i][w] = *reinterpret_cast<const u16x8 *>(&As[(w * BM + wr * 64 + i * 16 + li) * SK2 + sub * 32 + lq]);
+                        bv[i][w] = *reinterpret_cast<const u16x8 *>(&Bs[(w * BM + wc * 64 + i * 16 + li) * SK2 + sub * 32 + lq]);
+                    }
+#pragma unroll
+                for (int pr = npairs<NW>() - 1; pr >= 0; pr--)      // least significant products first
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            acc[i][j] = mfma16<FMT>(av[i][pair_p(pr)], bv[j][pair_q(pr)], acc[i][j]);
+            }
         }
     }
 
-    // Epilogue: lane l, register v of block (i, j) holds (row 4*(l/16) + v, column l%16).
-    const int n = gd.n;
-    double rmax = 0.0;
-    double dsum = 0.0;          // sum over this wave's true diagonal of (1 - T_ii)
+    // ---- epilogue: FP32 tile into LDS (lane l, register v of block (i, j) holds
+    // row 4*(l/16) + v, column l%16), then column-wise word stores.
+    __syncthreads();
     if (wave_live) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int c = col_w + j * 16 + li;
+            for (int j = 0; j < 4; j++)
+                *reinterpret_cast<f4 *>(&Cs[(wc * 64 + j * 16 + li) * CST + wr * 64 + i * 16 + (lane >> 4) * 4]) = acc[i][j];
+    }
+    __syncthreads();
+
+    constexpr float inv_s2 = (float)(1.0 / (word_scale<FMT>() * word_scale<FMT>()));
+    constexpr float sc = (float)word_scale<FMT>();
+    const int n = gd.n;
+    const bool diag = (ti == tj);
+    unsigned short *og = out + gd.off;
+    float rmax = 0.f;
+    double dsum = 0.0;
+    auto value = [&](float t, int r, int c) -> float {
+        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
+    };
+    {
+        // direct tile: thread = (column, half of the rows); 8-row groups above
+        // the diagonal of a diagonal tile are left to the mirror pass
+        const int cl = tid >> 1, rh = (tid & 1) * 64;
+        const int c = tj * BM + cl;
+        if (c < ld) {
+#pragma unroll 2
+            for (int q = 0; q < 8; q++) {
+                const int rl = rh + q * 8;
+                const int r0 = ti * BM + rl;
+                if (r0 >= ld) break;
+                if (diag && r0 + 7 < c) continue;
+                float v[8];
+                const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rl]);
+                const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rl + 4]);
+                v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+                v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int r = row_w + i * 16 + (lane >> 4) * 4 + v;
-                const double t = (double)acc[i][j][v] * (1.0 / (word_scale<FMT>() * word_scale<FMT>()));
-                double val;
-                if (MODE == 0) {
-                    if (r < n && c < n) {
-                        double d = fabs(t - (r == c ? 1.0 : 0.0));
-                        if (!(d <= 1.7976931348623157e308)) d = __builtin_huge_val();
-                        rmax = fmax(rmax, d);
-                        if (r == c) dsum += 1.0 - t;
+                for (int e = 0; e < 8; e++) {
+                    const int r = r0 + e;
+                    const float t = v[e] * inv_s2;
+                    if (MODE == 0 && r < n && c < n && r >= c) {
+                        float d = fabsf(t - (r == c ? 1.f : 0.f));
+                        if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
+                        rmax = fmaxf(rmax, d);
+                        if (r == c) dsum += 1.0 - (double)t;
                     }
-                    val = -0.5 * t + (r == c ? 1.5 : 0.0);
-                } else {
-                    val = t;
+                    v[e] = value(t, r, c) * sc;
                 }
-                if (r < ld && c < ld && r >= c) {
-                    const double vs = val * word_scale<FMT>();
-                    split_store<FMT, NW>(out + gd.off, plane, r + (int64_t)c * ld, vs);
-                    if (r > c) split_store<FMT, NW>(out + gd.off, plane, c + (int64_t)r * ld, vs);
+                u16x8 wv[NW];
+                split8<FMT, NW>(v, wv);
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    *reinterpret_cast<u16x8 *>(og + w * plane + r0 + (int64_t)c * ld) = wv[w];
+            }
+        }
+    }
+    __syncthreads();                    // direct stores precede the mirror stores that overlap them
+    {
+        // mirror: element (r, c) of the tile is stored at (c, r); thread = (tile row r,
+        // half of the tile columns); in a diagonal tile only r > c
+        const int rl = tid >> 1, chh = (tid & 1) * 64;
+        const int r = ti * BM + rl;
+        if (r < ld) {
+#pragma unroll 2
+            for (int q = 0; q < 8; q++) {
+                const int cl0 = chh + q * 8;
+                const int c0 = tj * BM + cl0;
+                if (c0 >= ld) break;
+                if (diag && c0 >= r) continue;
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[e] = value(Cs[(cl0 + e) * CST + rl] * inv_s2, r, c0 + e) * sc;
+                u16x8 wv[NW];
+                split8<FMT, NW>(v, wv);
+                if (!diag || c0 + 8 <= r) {
+#pragma unroll
+                    for (int w = 0; w < NW; w++)
+                        *reinterpret_cast<u16x8 *>(og + w * plane + c0 + (int64_t)r * ld) = wv[w];
+                } else {
+                    for (int e = 0; c0 + e < r; e++)
+#pragma unroll
+                        for (int w = 0; w < NW; w++) og[w * plane + c0 + e + (int64_t)r * ld] = wv[w][e];
                 }
             }
         }
     }
-    }
+
     if (MODE == 0) {
-        rmax = wave_max(rmax);
+        double rm = (double)rmax;
+        rm = wave_max(rm);
         if (lane == 0)
-            atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rmax));
-        if (ti == tj) {
+            atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
+        if (diag) {
             // fixed-order reduction of the diagonal partials: lanes, then waves
-            __shared__ double wsum[4];
             for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
             if (lane == 0) wsum[wave] = dsum;
             __syncthreads();
