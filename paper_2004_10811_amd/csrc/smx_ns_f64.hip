@@ -84,14 +84,14 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    // global -> LDS staging: thread owns 8 consecutive k of one tile column
-    const int lcol = tid >> 1;
-    const int lk = (tid & 1) * 8;
-    const int ga = ti * BM + lcol;               // column of X giving A(i = ga, k)
-    const int gb = tj * BM + lcol;               // column of B giving B(k, j = gb)
-    const bool va = ga < ld, vb = gb < ld;
-    const double *pa = xin + gd.off + (int64_t)ga * ld + lk;
-    const double *pb = bin + gd.off + (int64_t)gb * ld + lk;
+    // global -> LDS staging: a K step is 16 k = 128 B per tile column, i.e. eight
+    // 16-B chunks.  Chunk q*256 + tid (q = 0..3) is column 32 q + tid/8, part
+    // tid%8: eight consecutive lanes read one full cache line.
+    const int part = tid & 7;
+    const int col8 = tid >> 3;
+    const double *pa = xin + gd.off + (int64_t)(ti * BM + col8) * ld + part * 2;
+    const double *pb = bin + gd.off + (int64_t)(tj * BM + col8) * ld + part * 2;
+    const int64_t col_stride = (int64_t)32 * ld;
 
     // waves whose 64 x 64 sub-tile lies wholly in the padding, or strictly
     // above the diagonal of a diagonal tile (never stored), skip the math
@@ -109,15 +109,15 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            ra[q] = va ? *reinterpret_cast<const d2 *>(pa + k0 + 2 * q) : z2;
-            rb[q] = vb ? *reinterpret_cast<const d2 *>(pb + k0 + 2 * q) : z2;
+            ra[q] = (ti * BM + 32 * q + col8 < ld) ? *reinterpret_cast<const d2 *>(pa + q * col_stride + k0) : z2;
+            rb[q] = (tj * BM + 32 * q + col8 < ld) ? *reinterpret_cast<const d2 *>(pb + q * col_stride + k0) : z2;
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            *reinterpret_cast<d2 *>(&As[buf][lcol][lk + 2 * q]) = ra[q];
-            *reinterpret_cast<d2 *>(&Bs[buf][lcol][lk + 2 * q]) = rb[q];
+            *reinterpret_cast<d2 *>(&As[buf][32 * q + col8][part * 2]) = ra[q];
+            *reinterpret_cast<d2 *>(&Bs[buf][32 * q + col8][part * 2]) = rb[q];
         }
     };
 

@@ -223,14 +223,14 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    // staging: thread owns 32 consecutive k (64 B per word plane) of one tile column
-    const int lcol = tid >> 1;
-    const int lk = (tid & 1) * 32;
-    const int ga = ti * BM + lcol;
-    const int gb = tj * BM + lcol;
-    const bool va = ga < ld, vb = gb < ld;
-    const unsigned short *pa = xin + gd.off + (int64_t)ga * ld + lk;
-    const unsigned short *pb = bin + gd.off + (int64_t)gb * ld + lk;
+    // staging: a K step is 64 k = 128 B per tile column and word plane, i.e. eight
+    // 16-B chunks.  Chunk q*256 + tid (q = 0..3) is column 32 q + tid/8, part tid%8:
+    // eight consecutive lanes read one full cache line.
+    const int part = tid & 7;
+    const int col8 = tid >> 3;
+    const unsigned short *pa = xin + gd.off + (int64_t)(ti * BM + col8) * ld + part * 8;
+    const unsigned short *pb = bin + gd.off + (int64_t)(tj * BM + col8) * ld + part * 8;
+    const int64_t col_stride = (int64_t)32 * ld;       // 32 columns further
 
     const int row_w = ti * BM + wr * 64, col_w = tj * BM + wc * 64;
     const bool wave_live = (row_w < ld) && (col_w < ld) && !(ti == tj && wr < wc);
@@ -244,23 +244,26 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     u16x8 ra[NW][4], rb[NW][4];
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     auto gload = [&](int k0) {
-        // ld is a multiple of 32: the last step may hold only 32 valid k (lk = 32 half is then zero)
-        const bool kv = k0 + lk < ld;
+        // ld is a multiple of 32: in the last step the parts beyond ld read as zero
+        const bool kv = k0 + part * 8 < ld;
 #pragma unroll
-        for (int w = 0; w < NW; w++)
+        for (int q = 0; q < 4; q++) {
+            const bool ca = kv && (ti * BM + 32 * q + col8 < ld);
+            const bool cb = kv && (tj * BM + 32 * q + col8 < ld);
 #pragma unroll
-            for (int h = 0; h < 4; h++) {
-                ra[w][h] = (va && kv) ? *reinterpret_cast<const u16x8 *>(pa + w * plane + k0 + 8 * h) : z8;
-                rb[w][h] = (vb && kv) ? *reinterpret_cast<const u16x8 *>(pb + w * plane + k0 + 8 * h) : z8;
+            for (int w = 0; w < NW; w++) {
+                ra[w][q] = ca ? *reinterpret_cast<const u16x8 *>(pa + w * plane + q * col_stride + k0) : z8;
+                rb[w][q] = cb ? *reinterpret_cast<const u16x8 *>(pb + w * plane + q * col_stride + k0) : z8;
             }
+        }
     };
     auto sstore = [&]() {
 #pragma unroll
-        for (int w = 0; w < NW; w++)
+        for (int q = 0; q < 4; q++)
 #pragma unroll
-            for (int h = 0; h < 4; h++) {
-                *reinterpret_cast<u16x8 *>(&As[(w * BM + lcol) * SK2 + lk + 8 * h]) = ra[w][h];
-                *reinterpret_cast<u16x8 *>(&Bs[(w * BM + lcol) * SK2 + lk + 8 * h]) = rb[w][h];
+            for (int w = 0; w < NW; w++) {
+                *reinterpret_cast<u16x8 *>(&As[(w * BM + 32 * q + col8) * SK2 + part * 8]) = ra[w][q];
+                *reinterpret_cast<u16x8 *>(&Bs[(w * BM + 32 * q + col8) * SK2 + part * 8]) = rb[w][q];
             }
     };
 
