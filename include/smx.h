@@ -211,6 +211,35 @@ int32_t smx_get_group_info(smx_ctx ctx, int32_t *n_g, int32_t *iters,
 int32_t smx_get_submatrix(smx_ctx ctx, int32_t g, int32_t what, double *out, int32_t ld,
                           int32_t *n_out);
 
+/*
+ * Frozen iteration.  With on != 0 (after an evaluation), later evaluations
+ * take exactly the step counts k_g of that evaluation (FP64 steps, polish
+ * included) and its scales s_g, instead of the stopping rule and a fresh
+ * Gershgorin bound: the map K, mu -> D is then a fixed polynomial, which is
+ * what derivatives and the mu search act on.  Frozen evaluations run in
+ * SMX_FP64 only and also carry the mu tangent of the iteration (one more
+ * symmetric product per step) for smx_dn_dmu.  on = 0 unfreezes.
+ */
+int32_t smx_set_frozen(smx_ctx ctx, int32_t on);
+
+/* dN/dmu of the last (frozen) evaluation: -1/2 times the own-diagonal trace of
+ * the tangent dX_k/dmu, with dX_0/dmu = -I/s_g.  Synchronises. */
+int32_t smx_dn_dmu(smx_ctx ctx, double *out);
+
+/*
+ * Chemical potential for a target electron count (Sec. IV-H, Algorithm 1
+ * reads n_elec off fixed decompositions; here the iteration itself is
+ * frozen).  Bracket: the Gershgorin interval of K; scales s_g: the larger of
+ * the bracket ends' ||K_sub - mu I||_inf (valid for every mu inside); step
+ * counts: one converged FP64 evaluation at the current mu with those scales.
+ * Then safeguarded Newton on the frozen N(mu) with dN/dmu from the tangent,
+ * until |N - n_target| <= tol or max_steps evaluations.  Leaves the context
+ * at mu_out (unfrozen); *steps_out (nullable) = evaluations used.  Returns
+ * SMX_E_NOT_CONVERGED if the tolerance was not reached.
+ */
+int32_t smx_find_mu(smx_ctx ctx, double n_target, double tol, int32_t max_steps,
+                    double *mu_out, int32_t *steps_out);
+
 /* Number of groups and stored values of the loaded problem. */
 int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
 

@@ -193,3 +193,66 @@ def group_eig(s, g: int, mu: float | None = None, values: np.ndarray | None = No
         raise RuntimeError(f"oracle_group_eig failed: {st}")
     info = {f: getattr(gi, f) for f, _ in GroupInfo._fields_}
     return rows[:m].copy(), lam, q.reshape(n, n, order="F"), info
+
+
+# ---------------------------------------------------------------------------
+# Frozen-iteration quantities (k Newton-Schulz steps, fixed scale), computed
+# from the eigendecomposition of each group's submatrix.  Algorithm 1 of the
+# paper (Sec. IV-H) reads the electron count off stored decompositions with
+# signum(lambda - mu); here the signum is replaced by the k-step
+# Newton-Schulz polynomial p_k of the scaled eigenvalue, which is what a
+# frozen iteration evaluates.
+# ---------------------------------------------------------------------------
+
+def ns_poly(x, k):
+    """p_k(x): k steps of p(x) = x (3 - x^2) / 2 (Sec. II-B) applied to scalars."""
+    x = np.asarray(x, dtype=np.float64).copy()
+    for _ in range(int(k)):
+        x = 1.5 * x - 0.5 * x ** 3
+    return x
+
+
+def ns_poly_deriv(x, k):
+    """p_k'(x) by the chain rule through the k steps: prod (3/2)(1 - x_i^2)."""
+    x = np.asarray(x, dtype=np.float64).copy()
+    d = np.ones_like(x)
+    for _ in range(int(k)):
+        d = d * (1.5 - 1.5 * x ** 2)
+        x = 1.5 * x - 0.5 * x ** 3
+    return d
+
+
+class GroupSpectra:
+    """Eigenpairs of every group's unshifted submatrix K[R(g), R(g)] and the
+    own-column weights w_gl = sum_{c in own(g)} Q_cl^2 of Algorithm 1."""
+
+    def __init__(self, s, groups=None, values=None):
+        self.groups = list(range(s.ngroups)) if groups is None else list(groups)
+        self.lam, self.w, self.q, self.rows = [], [], [], []
+        for g in self.groups:
+            rows, lam, q, _ = group_eig(s, g, mu=0.0, values=values)
+            sizes = s.blk_size[rows]
+            off = np.concatenate([[0], np.cumsum(sizes)])
+            pos = {int(b): off[t] for t, b in enumerate(rows)}
+            own = np.concatenate([np.arange(pos[int(j)], pos[int(j)] + s.blk_size[j])
+                                  for j in s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]])
+            self.lam.append(lam)
+            self.q.append(q)
+            self.rows.append(rows)
+            self.w.append((q[own, :] ** 2).sum(axis=0))
+
+    def n_frozen(self, mu, k, scale):
+        """N_k(mu) = sum_g sum_l w_gl (1 - p_k((lam_gl - mu)/s_g)) / 2."""
+        tot = 0.0
+        for t in range(len(self.groups)):
+            x = (self.lam[t] - mu) / scale[t]
+            tot += float((self.w[t] * 0.5 * (1.0 - ns_poly(x, k[t]))).sum())
+        return tot
+
+    def dn_dmu_frozen(self, mu, k, scale):
+        """dN_k/dmu = sum_g sum_l w_gl p_k'((lam_gl - mu)/s_g) / (2 s_g)."""
+        tot = 0.0
+        for t in range(len(self.groups)):
+            x = (self.lam[t] - mu) / scale[t]
+            tot += float((self.w[t] * 0.5 * ns_poly_deriv(x, k[t]) / scale[t]).sum())
+        return tot

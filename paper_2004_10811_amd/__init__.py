@@ -74,6 +74,9 @@ SIGNATURES = {
     "smx_get_sizes": (_i32, [_vp, _P(_i32), _P(_i64)]),
     "smx_get_launch_profile": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(_i32)]),
     "smx_get_submatrix": (_i32, [_vp, _i32, _i32, _vp, _i32, _P(_i32)]),
+    "smx_set_frozen": (_i32, [_vp, _i32]),
+    "smx_dn_dmu": (_i32, [_vp, _P(_f64)]),
+    "smx_find_mu": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
 }
 
 _lib = None
@@ -273,6 +276,24 @@ def smx_get_submatrix(ctx, g: int, what: int = 1) -> np.ndarray:
     _check(ctx, load_library().smx_get_submatrix(ctx, g, what, out.ctypes.data, max(n.value, 1),
                                                   ctypes.byref(n)))
     return np.ascontiguousarray(out)
+
+
+def smx_set_frozen(ctx, on: bool = True):
+    return _check(ctx, load_library().smx_set_frozen(ctx, int(bool(on))))
+
+
+def smx_dn_dmu(ctx) -> float:
+    v = _f64()
+    _check(ctx, load_library().smx_dn_dmu(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def smx_find_mu(ctx, n_target: float, tol: float = 1e-8, max_steps: int = 50):
+    """(mu, evaluations used) with N(mu) = n_target on the frozen iteration."""
+    mu, steps = _f64(), _i32()
+    _check(ctx, load_library().smx_find_mu(ctx, float(n_target), float(tol), int(max_steps),
+                                            ctypes.byref(mu), ctypes.byref(steps)))
+    return mu.value, steps.value
 
 
 # ---- convenience object -----------------------------------------------------

@@ -105,6 +105,10 @@ struct smx_context {
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
     DevBuf<int32_t> d_own;
     DevBuf<double> d_tau_parts, d_tau_hist;
+    // frozen iteration (derivatives, mu search): step counts and scales of a previous evaluation
+    DevBuf<int32_t> d_kfix;
+    DevBuf<unsigned long long> d_sfix, d_scale_scratch;
+    DevBuf<double> d_tx0, d_tx1, d_dnp, d_dn;    // mu tangent of the iterates, its reduction
     DevBuf<unsigned short> d_wx0, d_wx1, d_ww;   // word planes of X (two steps) and W
     DevBuf<double> d_t0, d_t1, d_t2;             // own-column buffers of the last polish step
 
@@ -124,6 +128,9 @@ struct smx_context {
     int32_t last_stride = 0;
     int32_t last_polish = 0;             // FP64 polish steps after the bulk (0 in FP64 mode)
     int32_t last_max_iter = 0;
+    bool use_kfix = false, use_sfix = false;  // frozen step counts / scales
+    bool have_tangent = false;                 // last evaluation computed dN/dmu
+    bool last_sfix = false;                    // last evaluation ran on the frozen scales
 };
 
 namespace {
@@ -466,6 +473,13 @@ int32_t smx_destroy(smx_ctx c)
     c->d_own.release();
     c->d_tau_parts.release();
     c->d_tau_hist.release();
+    c->d_kfix.release();
+    c->d_sfix.release();
+    c->d_scale_scratch.release();
+    c->d_tx0.release();
+    c->d_tx1.release();
+    c->d_dnp.release();
+    c->d_dn.release();
     c->d_wx0.release();
     c->d_wx1.release();
     c->d_ww.release();
@@ -501,6 +515,7 @@ int32_t smx_load_k(smx_ctx c, int32_t nblk, const int32_t *blk_size, const int64
     c->loaded = false;
     c->evaluated = false;
     c->plan_dirty = true;
+    c->use_kfix = c->use_sfix = false;
     if (nblk <= 0 || !blk_size || !col_ptr || !row_idx || !values)
         return fail(c, SMX_E_INVALID, "nblk must be positive and all arrays non-NULL");
     if (int32_t st = set_device(c)) return st;
@@ -597,6 +612,7 @@ int32_t smx_set_groups(smx_ctx c, int32_t ngroups, const int32_t *grp_ptr, const
     c->grp_blocks.assign(grp_blocks, grp_blocks + c->nblk);
     c->plan_dirty = true;
     c->evaluated = false;
+    c->use_kfix = c->use_sfix = false;
     return SMX_OK;
 }
 
@@ -650,6 +666,9 @@ int32_t smx_evaluate(smx_ctx c)
     default: return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented on the GPU path");
     }
     const bool mixed = fmt >= 0;
+    const bool frozen = c->use_kfix || c->use_sfix;
+    if (frozen && mixed)
+        return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) runs in SMX_FP64 only");
     if (mixed && c->max_iter <= c->n_polish)
         return fail(c, SMX_E_INVALID, "max_iter must exceed n_polish in reduced-precision modes");
     if (int32_t st = set_device(c)) return st;
@@ -691,20 +710,35 @@ int32_t smx_evaluate(smx_ctx c)
     it.kfinal = c->d_kfinal.p;
     it.flags = c->d_flags.p;
     it.ndone = c->d_ndone.p;
+    it.kfix = c->use_kfix ? c->d_kfix.p : nullptr;
     it.tau_parts = c->d_tau_parts.p;
     it.tau_hist = c->d_tau_hist.p;
     it.resid_stride = stride;
     it.tau_nt = std::max(tau_nt, 1);
 
+    // the mu tangent is carried whenever the step count is frozen (FP64)
+    const bool tangent = c->use_kfix;
+    if (c->use_sfix) {
+        HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
+        it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
+    }
+    if (tangent) {
+        HIP_TRY(c, c->d_tx0.ensure((size_t)P.work_elems));
+        HIP_TRY(c, c->d_tx1.ensure((size_t)P.work_elems));
+        HIP_TRY(c, c->d_dnp.ensure((size_t)std::max(ng, 1)));
+        HIP_TRY(c, c->d_dn.ensure(2));
+    }
+    unsigned long long *gather_scale = c->use_sfix ? c->d_scale_scratch.p : it.scale_bits;
     HIP_TRY(c, hipEventRecord(c->ev_t0, st));
-    HIP_TRY(c, hipMemsetAsync(it.scale_bits, 0, sizeof(unsigned long long) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(gather_scale, 0, sizeof(unsigned long long) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.resid_bits, 0, sizeof(unsigned long long) * (size_t)ng * stride, st));
     HIP_TRY(c, hipMemsetAsync(it.done, 0, sizeof(int32_t) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.kfinal, 0, sizeof(int32_t) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.flags, 0, sizeof(int32_t) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
     HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_x0.p, it.scale_bits));
+                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_x0.p, gather_scale));
+    if (tangent) HIP_TRY(c, launch_tangent_init(st, ng, P.max_npad, c->d_gd.p, it.scale_bits, c->d_tx0.p));
     const int64_t plane = P.work_elems;
     if (mixed)
         HIP_TRY(c, launch_to_words(st, fmt, nw, ng, P.max_npad, c->d_gd.p, c->d_x0.p, it.scale_bits, c->d_wx0.p,
@@ -741,6 +775,12 @@ int32_t smx_evaluate(smx_ctx c)
                                                               c->d_w.p, it, k, c->tol, c->max_iter, 0); }));
             HIP_TRY(c, timed(1, k, [&] { return launch_ns_f64(st, 1, ntiles, c->d_tiles.p, c->d_gd.p, xb[k & 1], c->d_w.p,
                                                               xb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
+            if (tangent) {
+                double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
+                HIP_TRY(c, timed(6, k, [&] { return launch_ns_f64(st, 2, ntiles, c->d_tiles.p, c->d_gd.p, tb[k & 1],
+                                                                  c->d_w.p, tb[(k + 1) & 1], it, k, c->tol,
+                                                                  c->max_iter, 0); }));
+            }
         } else {
             HIP_TRY(c, timed(2, k, [&] { return launch_ns_words(st, fmt, nw, 0, ntiles, c->d_tiles.p, c->d_gd.p, wb[k & 1],
                                                                 wb[k & 1], c->d_ww.p, plane, it, k, c->switch_tol, kmax); }));
@@ -780,6 +820,12 @@ int32_t smx_evaluate(smx_ctx c)
         HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_x0.p, c->d_x1.p, it, c->d_k.p,
                                   c->d_d.p, c->d_pe.p, c->d_pn.p, 0));
     HIP_TRY(c, launch_reduce(st, c->nnzb, c->d_pe.p, c->d_pn.p, c->d_ne.p));
+    if (tangent) {
+        HIP_TRY(c, launch_own_trace(st, ng, c->d_gd.p, c->d_own.p, c->d_tx0.p, c->d_tx1.p, it.kfinal, c->d_dnp.p));
+        HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dn.p));
+    }
+    c->have_tangent = tangent;
+    c->last_sfix = c->use_sfix;
     HIP_TRY(c, hipEventRecord(c->ev_t3, st));
     c->steps_launched = launched;
     c->last_precision = c->precision;
@@ -853,7 +899,8 @@ int32_t smx_get_group_info(smx_ctx c, int32_t *n_g, int32_t *iters, double *scal
     std::vector<int32_t> kf((size_t)ng);
     std::vector<unsigned long long> sb((size_t)ng), rb((size_t)ng * c->last_stride);
     HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(sb.data(), c->d_scale.p, sb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(sb.data(), c->last_sfix ? c->d_sfix.p : c->d_scale.p, sb.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(rb.data(), c->d_resid.p, rb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     for (int32_t g = 0; g < ng; g++) {
         if (n_g) n_g[g] = c->plan.gd[g].n;
@@ -963,7 +1010,7 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
             for (int32_t g = 0; g < c->plan.ngroups; g++) {
                 bool active = true;                           // polish launches work on every group
                 if (kd == 0 || kd == 2) active = k <= kf[g];  // squares run up to the last step
-                if (kd == 1 || kd == 3) active = k < kf[g];   // updates stop one earlier
+                if (kd == 1 || kd == 3 || kd == 6) active = k < kf[g];   // updates (and tangents) stop one earlier
                 const double n = c->plan.gd[g].n;
                 if (active) f += 2.0 * n * n * n;
             }
@@ -1014,7 +1061,7 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         int32_t kf = 0;
         unsigned long long sb = 0;
         HIP_TRY(c, hipMemcpy(&kf, c->d_kfinal.p + g, sizeof kf, hipMemcpyDeviceToHost));
-        HIP_TRY(c, hipMemcpy(&sb, c->d_scale.p + g, sizeof sb, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(&sb, (c->last_sfix ? c->d_sfix.p : c->d_scale.p) + g, sizeof sb, hipMemcpyDeviceToHost));
         if (kf == 0) {
             double s;
             std::memcpy(&s, &sb, sizeof s);
@@ -1027,6 +1074,164 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
     for (int32_t j = 0; j < d.n; j++)
         for (int32_t i = 0; i < d.n; i++) out[i + (size_t)j * ld] = a * tmp[i + (size_t)j * d.npad];
     return SMX_OK;
+}
+
+int32_t smx_set_frozen(smx_ctx c, int32_t on)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!on) {
+        c->use_kfix = c->use_sfix = false;
+        return SMX_OK;
+    }
+    if (int32_t st = need_sync_results(c)) return st;
+    const int32_t ng = c->plan.ngroups;
+    std::vector<int32_t> kf((size_t)ng);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t &k : kf) k += c->last_polish;          // total steps, polish included
+    HIP_TRY(c, upload(c->d_kfix, kf, c->stream));
+    if (!c->last_sfix) {
+        HIP_TRY(c, c->d_sfix.ensure((size_t)std::max(ng, 1)));
+        HIP_TRY(c, hipMemcpyAsync(c->d_sfix.p, c->d_scale.p, sizeof(unsigned long long) * ng,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->use_kfix = c->use_sfix = true;
+    return SMX_OK;
+}
+
+int32_t smx_dn_dmu(smx_ctx c, double *out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!out) return fail(c, SMX_E_INVALID, "out is NULL");
+    if (int32_t st = need_sync_results(c)) return st;
+    if (!c->have_tangent) return fail(c, SMX_E_STATE, "the last evaluation was not frozen (smx_set_frozen)");
+    double v[2];
+    HIP_TRY(c, hipMemcpy(v, c->d_dn.p, sizeof v, hipMemcpyDeviceToHost));
+    *out = -0.5 * v[0];
+    return SMX_OK;
+}
+
+// Gershgorin interval of the whole K (host copy of the values): every
+// principal submatrix has its spectrum inside it (Cauchy interlacing).
+static int32_t gershgorin_interval(smx_ctx c, double *lo, double *hi)
+{
+    std::vector<double> v((size_t)c->nvals);
+    HIP_TRY(c, hipMemcpy(v.data(), c->d_k.p, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int64_t> boff((size_t)c->nblk + 1, 0);
+    for (int32_t j = 0; j < c->nblk; j++) boff[j + 1] = boff[j] + c->blk_size[j];
+    const int64_t n = boff[c->nblk];
+    std::vector<double> diag((size_t)n, 0.0), rad((size_t)n, 0.0);
+    for (int32_t j = 0; j < c->nblk; j++) {
+        const int32_t bj = c->blk_size[j];
+        for (int64_t p = c->col_ptr[j]; p < c->col_ptr[j + 1]; p++) {
+            const int32_t i = c->row_idx[p], bi = c->blk_size[i];
+            const double *b = v.data() + c->val_off[p];
+            for (int32_t cc = 0; cc < bj; cc++)
+                for (int32_t rr = 0; rr < bi; rr++) {
+                    const int64_t gi = boff[i] + rr, gj = boff[j] + cc;
+                    if (gi == gj) diag[gi] = b[rr + (int64_t)cc * bi];
+                    else rad[gi] += std::fabs(b[rr + (int64_t)cc * bi]);
+                }
+        }
+    }
+    double l = INFINITY, h = -INFINITY;
+    for (int64_t i = 0; i < n; i++) {
+        l = std::min(l, diag[i] - rad[i]);
+        h = std::max(h, diag[i] + rad[i]);
+    }
+    *lo = l;
+    *hi = h;
+    return SMX_OK;
+}
+
+// Gershgorin scales s_g = ||K_sub - mu I||_inf of every group at mu (device gather into scratch).
+static int32_t scales_at(smx_ctx c, double mu, std::vector<double> &out)
+{
+    const Plan &P = c->plan;
+    const int32_t ng = P.ngroups;
+    HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
+    HIP_TRY(c, hipMemsetAsync(c->d_scale_scratch.p, 0, sizeof(unsigned long long) * ng, c->stream));
+    HIP_TRY(c, launch_gather(c->stream, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
+                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, mu, c->d_w.p, c->d_scale_scratch.p));
+    std::vector<unsigned long long> b((size_t)ng);
+    HIP_TRY(c, hipMemcpyAsync(b.data(), c->d_scale_scratch.p, b.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out.resize((size_t)ng);
+    for (int32_t g = 0; g < ng; g++) std::memcpy(&out[g], &b[g], sizeof(double));
+    return SMX_OK;
+}
+
+int32_t smx_find_mu(smx_ctx c, double n_target, double tol, int32_t max_steps, double *mu_out, int32_t *steps_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (!mu_out || !(tol > 0.0) || max_steps < 1) return fail(c, SMX_E_INVALID, "need mu_out, tol > 0, max_steps >= 1");
+    if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "the mu search runs in SMX_FP64");
+    if (int32_t st = set_device(c)) return st;
+    if (int32_t st = ensure_plan(c)) return st;
+    const int32_t ng = c->plan.ngroups;
+    double lo, hi;
+    if (int32_t st = gershgorin_interval(c, &lo, &hi)) return st;
+    // scales valid over the whole bracket (the norm is convex in mu)
+    std::vector<double> s_lo, s_hi;
+    if (int32_t st = scales_at(c, lo, s_lo)) return st;
+    if (int32_t st = scales_at(c, hi, s_hi)) return st;
+    std::vector<unsigned long long> sb((size_t)ng);
+    for (int32_t g = 0; g < ng; g++) {
+        const double sv = std::max(s_lo[g], s_hi[g]);
+        std::memcpy(&sb[g], &sv, sizeof sv);
+    }
+    HIP_TRY(c, upload(c->d_sfix, sb, c->stream));
+    // step counts: a converged evaluation at the starting mu with those scales
+    double mu = std::min(std::max(c->mu, lo), hi);
+    c->mu = mu;
+    c->use_sfix = true;
+    c->use_kfix = false;
+    int32_t st = smx_evaluate(c);
+    if (st == SMX_OK) st = smx_wait(c);
+    if (st != SMX_OK) {
+        c->use_sfix = false;
+        return st;
+    }
+    {
+        std::vector<int32_t> kf((size_t)ng);
+        HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(c, upload(c->d_kfix, kf, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    c->use_kfix = true;
+    // safeguarded Newton on the frozen approximant N_k(mu) (increasing in mu)
+    int32_t steps = 0;
+    int32_t result = SMX_E_NOT_CONVERGED;
+    double blo = lo, bhi = hi;
+    for (steps = 1; steps <= max_steps; steps++) {
+        c->mu = mu;
+        st = smx_evaluate(c);
+        if (st == SMX_OK) st = smx_wait(c);
+        double nval = 0, dn = 0;
+        if (st == SMX_OK) st = smx_trace(c, &nval);
+        if (st == SMX_OK) st = smx_dn_dmu(c, &dn);
+        if (st != SMX_OK) {
+            result = st;
+            break;
+        }
+        const double f = nval - n_target;
+        if (std::fabs(f) <= tol) {
+            result = SMX_OK;
+            break;
+        }
+        if (f > 0) bhi = mu;
+        else blo = mu;
+        double next = (dn > 0) ? mu - f / dn : NAN;
+        if (!(next > blo && next < bhi)) next = 0.5 * (blo + bhi);
+        mu = next;
+    }
+    c->use_kfix = c->use_sfix = false;
+    *mu_out = c->mu;
+    if (steps_out) *steps_out = std::min(steps, max_steps);
+    if (result == SMX_E_NOT_CONVERGED) return fail(c, SMX_E_NOT_CONVERGED, "mu search did not reach the tolerance");
+    return result;
 }
 
 int32_t smx_get_sizes(smx_ctx c, int32_t *ngroups, int64_t *nvalues)

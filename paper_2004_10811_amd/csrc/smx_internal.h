@@ -51,6 +51,7 @@ struct IterState {
     int32_t *kfinal;                  // [ngroups] step k whose X_k is the result
     int32_t *flags;                   // [ngroups] bit 0: not converged, bit 1: non-finite
     int32_t *ndone;                   // [1] number of finished groups
+    const int32_t *kfix;              // [ngroups] frozen step counts (nullptr: stopping rule)
     double *tau_parts;                // [ngroups * tau_nt] per diagonal tile: sum of (1 - T_ii)
     double *tau_hist;                 // [ngroups * resid_stride] Tr(I - X_k^2) per step
     int32_t resid_stride;             // steps 0..max_iter, then one slot per polish step
@@ -67,8 +68,11 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
 // mode 0: T = a^2 X X, records max|T - I| for step k, writes W = 1.5 I - 0.5 T.
 // mode 1: if the step-k residual meets the stopping rule the group is finished
 //         at X_k; otherwise X_{k+1} = a X W.   a = 1/s_g at k = 0, else 1.
+// mode 2: tangent of the step, Xd_{k+1} = 3 (W - I) Xd_k = 3 Xd_k W - 3 Xd_k, for groups
+//         still iterating after step k (x = Xd_k, b = W).
 // polish != 0: unconditional step on every group (a = 1, no skipping, no
 // stopping); the square's residual goes to slot k of the residual history.
+// With it.kfix set, a group stops exactly at step kfix[g] (frozen iteration).
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
                          const IterState &it, int k, double tol, int max_iter, int polish);
@@ -100,6 +104,15 @@ hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd
 
 hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const double *part_n,
                          double *out2);
+
+// Xd_0 = -a I on the true n_g x n_g block (a = 1/s_g), zero elsewhere: the mu tangent
+// of X_0 = (K_sub - mu I) / s_g with s_g frozen.
+hipError_t launch_tangent_init(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups,
+                               const unsigned long long *scale_bits, double *xd);
+
+// part[g] = sum over the own columns c of Xd_{kfinal}[c, c] (Xd in xd0 / xd1 by step parity).
+hipError_t launch_own_trace(hipStream_t st, int ngroups, const GroupDesc *groups, const int32_t *own_list,
+                            const double *xd0, const double *xd1, const int32_t *kfinal, double *part);
 
 hipError_t launch_check_values(hipStream_t st, int64_t nblocks, const int64_t *valoff,
                                const int32_t *blk_rows, const int32_t *blk_cols,

@@ -3,6 +3,8 @@
 // fixed-order final reduction, and validation of K's values.
 #include "smx_internal.h"
 
+#include <algorithm>
+
 namespace smx {
 
 namespace {
@@ -284,7 +286,58 @@ void check_values_kernel(int64_t nblocks, const int64_t *__restrict__ valoff,
     }
 }
 
+// Xd_0 = -a I on the true block (a = 1/s_g), one group per blockIdx.y.
+__global__ __launch_bounds__(256)
+void tangent_init_kernel(const GroupDesc *__restrict__ groups, const unsigned long long *__restrict__ scale_bits,
+                         double *__restrict__ xd)
+{
+    const GroupDesc gd = groups[blockIdx.y];
+    const int64_t tot = (int64_t)gd.npad * gd.npad;
+    const double s = __longlong_as_double((long long)scale_bits[blockIdx.y]);
+    const double a = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t r = e % gd.npad, c = e / gd.npad;
+        xd[gd.off + e] = (r == c && r < gd.n) ? -a : 0.0;
+    }
+}
+
+// part[g] = sum of Xd_kfinal over the group's own diagonal, in list order.
+__global__ __launch_bounds__(64)
+void own_trace_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
+                      const double *__restrict__ xd0, const double *__restrict__ xd1,
+                      const int32_t *__restrict__ kfinal, double *__restrict__ part)
+{
+    const int g = blockIdx.x;
+    const GroupDesc gd = groups[g];
+    const double *xd = ((kfinal[g] & 1) ? xd1 : xd0) + gd.off;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < gd.m_own; q += 64) {
+        const int c = own_list[gd.own_off + q];
+        acc += xd[c + (int64_t)c * gd.npad];
+    }
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) part[g] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_tangent_init(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups,
+                               const unsigned long long *scale_bits, double *xd)
+{
+    if (ngroups <= 0) return hipSuccess;
+    const int64_t tot = (int64_t)max_npad * max_npad;
+    const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
+    hipLaunchKernelGGL(tangent_init_kernel, grid, dim3(256), 0, st, groups, scale_bits, xd);
+    return hipGetLastError();
+}
+
+hipError_t launch_own_trace(hipStream_t st, int ngroups, const GroupDesc *groups, const int32_t *own_list,
+                            const double *xd0, const double *xd1, const int32_t *kfinal, double *part)
+{
+    if (ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(own_trace_kernel, dim3(ngroups), dim3(64), 0, st, groups, own_list, xd0, xd1, kfinal, part);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const GroupDesc *groups,
                          const RowInfo *rinfo, const int32_t *bmap, const int32_t *boffs,

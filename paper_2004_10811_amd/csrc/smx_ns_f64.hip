@@ -58,19 +58,21 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const int ld = gd.npad;
 
     double a = 1.0;
-    if (k == 0 && !polish) {
+    if (k == 0 && !polish && MODE != 2) {
         const double s = __longlong_as_double((long long)it.scale_bits[g]);
         a = s > 0.0 ? 1.0 / s : 0.0;
     }
+    if (MODE == 2 && it.done[g]) return;          // tangent only while the group iterates
     if (MODE == 1 && !polish) {
         const double rk = __longlong_as_double((long long)it.resid_bits[(int64_t)g * it.resid_stride + k]);
         const bool finite = rk <= 1.7976931348623157e308;
-        if (rk <= tol || k >= max_iter || !finite) {
+        const bool stop = it.kfix ? (k >= it.kfix[g]) : (rk <= tol || k >= max_iter);
+        if (stop || !finite) {
             if (ti == 0 && tj == 0 && threadIdx.x == 0) {
                 it.done[g] = 1;
                 it.kfinal[g] = k;
                 int fl = 0;
-                if (!(rk <= tol)) fl |= 1;
+                if (!it.kfix && !(rk <= tol)) fl |= 1;
                 if (!finite) fl |= 2;
                 it.flags[g] = fl;
                 atomicAdd(it.ndone, 1);
@@ -181,8 +183,11 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
                         rmax = fmax(rmax, d);
                     }
                     val = -0.5 * t + (r == c ? 1.5 : 0.0);
-                } else {
+                } else if (MODE == 1) {
                     val = a * acc[i][j][v];
+                } else {
+                    // tangent: 3 Xd W - 3 Xd (Xd and W commute, so the product is symmetric)
+                    val = (r < ld && c < ld) ? 3.0 * acc[i][j][v] - 3.0 * xin[gd.off + r + (int64_t)c * ld] : 0.0;
                 }
                 if (r < ld && c < ld && r >= c) {
                     og[r + (int64_t)c * ld] = val;
@@ -210,8 +215,11 @@ hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *t
     if (mode == 0)
         hipLaunchKernelGGL(ns_f64_kernel<0>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
                            out, it, k, tol, max_iter, polish);
-    else
+    else if (mode == 1)
         hipLaunchKernelGGL(ns_f64_kernel<1>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
+                           out, it, k, tol, max_iter, polish);
+    else
+        hipLaunchKernelGGL(ns_f64_kernel<2>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
                            out, it, k, tol, max_iter, polish);
     return hipGetLastError();
 }

@@ -1,0 +1,47 @@
+"""Pins of the oracle's frozen-iteration quantities (electron count and dN/dmu)."""
+
+import numpy as np
+
+from waterbox import water_system, random_block_system
+
+
+def test_ns_poly_fixed_points_and_derivative():
+    import oracle
+    # +-1 and 0 are fixed points of p(x) = x(3 - x^2)/2; p'(0) = 3/2 per step
+    assert np.allclose(oracle.ns_poly([-1.0, 0.0, 1.0], 7), [-1.0, 0.0, 1.0])
+    assert np.isclose(oracle.ns_poly_deriv(0.0, 5), 1.5 ** 5)
+    x = np.linspace(-0.9, 0.9, 13)
+    h = 1e-6
+    fd = (oracle.ns_poly(x + h, 6) - oracle.ns_poly(x - h, 6)) / (2 * h)
+    assert np.allclose(oracle.ns_poly_deriv(x, 6), fd, rtol=1e-6, atol=1e-8)
+
+
+def test_frozen_count_converges_to_the_submatrix_count(oracle_lib):
+    """Many steps: p_k -> sign, so N_k(mu) -> Tr D of the submatrix method."""
+    s = water_system(n_mol=6, box=6.0, r_cut=3.5, seed=41)
+    spec = oracle_lib.GroupSpectra(s)
+    mu = 0.02
+    ref = oracle_lib.submatrix(s, mu=mu)
+    scale = [np.abs(np.linalg.eigvalsh(np.diag(l) - mu * np.eye(len(l)))).max() * 1.3 for l in spec.lam]
+    k = [80] * s.ngroups
+    assert abs(spec.n_frozen(mu, k, scale) - ref.n_elec) < 1e-10
+    # dN/dmu of the converged map vanishes inside the gap
+    assert abs(spec.dn_dmu_frozen(mu, k, scale)) < 1e-8
+
+
+def test_frozen_dn_dmu_matches_finite_differences(oracle_lib):
+    s = random_block_system(43, [4, 3, 5, 2, 6], density=0.6, coupling=0.05, groups="column")
+    spec = oracle_lib.GroupSpectra(s)
+    k = [3, 4, 5, 2, 6]
+    scale = [2.0, 1.5, 2.5, 1.8, 2.2]
+    mu, h = 0.05, 1e-6
+    fd = (spec.n_frozen(mu + h, k, scale) - spec.n_frozen(mu - h, k, scale)) / (2 * h)
+    assert abs(spec.dn_dmu_frozen(mu, k, scale) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_weights_sum_to_own_column_count(oracle_lib):
+    s = water_system(n_mol=4, box=5.0, r_cut=3.0, seed=42)
+    spec = oracle_lib.GroupSpectra(s)
+    for t, g in enumerate(spec.groups):
+        own = s.blk_size[s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]].sum()
+        assert abs(spec.w[t].sum() - own) < 1e-12
