@@ -240,6 +240,26 @@ int32_t smx_dn_dmu(smx_ctx ctx, double *out);
 int32_t smx_find_mu(smx_ctx ctx, double n_target, double tol, int32_t max_steps,
                     double *mu_out, int32_t *steps_out);
 
+/*
+ * Reverse-mode derivative of L = gE E + gN N + <gD, D> (gD nullable, K's
+ * layout, host or device) through the frozen map of the last evaluation:
+ * its step counts k_g and scales s_g are held fixed, and the iterates are
+ * recomputed in FP64 from checkpoints kept every 8 steps.  Per step the
+ * adjoint is Xb_k = (3 Xb - Xb X_k^2 - X_k^2 Xb - X_k Xb X_k) / 2 (the
+ * transpose of the derivative of X (3I - X^2) / 2), seeded at the sign with
+ * the symmetrised -1/2 dL/dD of the own columns; A_g = K_sub - mu I and
+ * X_0 = A_g / s_g give dK by the transpose of the gather, plus gE D for the
+ * explicit K in E = Tr(DK).
+ *   dK_out (nullable; host, or device when dK_on_device != 0): dL/dK for
+ *   every stored value of K, each treated as an independent variable; since
+ *   only symmetric changes of K are meaningful, the symmetric part
+ *   dK_IJ + dK_JI^T is what is fixed (each group's part is symmetrised).
+ *   dmu_out (nullable): dL/dmu = -sum_g tr(dL/dA_g).
+ * Needs free device memory for 4 + 8 + k_max/8 + 1 work slabs.  Synchronises.
+ */
+int32_t smx_backward(smx_ctx ctx, double gE, double gN, const double *gD, int32_t gD_on_device,
+                     double *dK_out, int32_t dK_on_device, double *dmu_out);
+
 /* Number of groups and stored values of the loaded problem. */
 int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
 

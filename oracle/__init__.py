@@ -256,3 +256,110 @@ class GroupSpectra:
             x = (self.lam[t] - mu) / scale[t]
             tot += float((self.w[t] * 0.5 * ns_poly_deriv(x, k[t]) / scale[t]).sum())
         return tot
+
+
+def ns_divided_differences(x, k):
+    """Matrix of divided differences (p_k(x_j) - p_k(x_l)) / (x_j - x_l) of the
+    k-step polynomial, p_k'(x_j) on the diagonal.  Through one step of
+    p(u) = u (3 - u^2)/2 the divided difference is 3/2 - (u^2 + u v + v^2)/2
+    exactly, so the product over the steps has no cancellation."""
+    u = np.asarray(x, dtype=np.float64)[:, None] * np.ones((1, len(x)))
+    v = u.T.copy()
+    d = np.ones_like(u)
+    for _ in range(int(k)):
+        d *= 1.5 - 0.5 * (u * u + u * v + v * v)
+        u = 1.5 * u - 0.5 * u ** 3
+        v = 1.5 * v - 0.5 * v ** 3
+    return d
+
+
+def frozen_gradient(s, k, scale, mu, gE=0.0, gN=0.0, gD=None, values=None):
+    """Frozen map D = (I - p_k(A_g / s_g))/2 (own columns, K's layout), its N and
+    E = Tr(DK), and the gradient of L = gE E + gN N + <gD, D> with respect to
+    every stored value of K and to mu, by the Daleckii-Krein formula
+    dL/dA_g = Q (Gamma o (Q^T W Q)) Q^T, Gamma_jl = divided differences of
+    f(lam) = (1 - p_k(lam / s_g))/2 (Higham, Functions of Matrices, Thm 3.11),
+    W = dL/dD_g at the own-column stored positions."""
+    vals = s.values if values is None else np.asarray(values, dtype=np.float64)
+    voff = s.val_off()
+    d_out = np.zeros_like(vals)
+    dk = np.zeros_like(vals)
+    dmu = 0.0
+    nblk = s.nblk
+    stored = {}
+    for j in range(nblk):
+        for p in range(s.col_ptr[j], s.col_ptr[j + 1]):
+            stored[(int(s.row_idx[p]), j)] = p
+    per_group = []
+    for g in range(s.ngroups):
+        rows, lam, q, _ = group_eig(s, g, mu=mu, values=vals)
+        sizes = s.blk_size[rows]
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        pos = {int(b): int(off[t]) for t, b in enumerate(rows)}
+        x = lam / scale[g]
+        f = 0.5 * (1.0 - ns_poly(x, k[g]))
+        dg = (q * f) @ q.T
+        per_group.append((rows, pos, lam, q, dg))
+        for j in s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]:
+            j = int(j)
+            bj = s.blk_size[j]
+            for p in range(s.col_ptr[j], s.col_ptr[j + 1]):
+                i = int(s.row_idx[p])
+                bi = s.blk_size[i]
+                blk = dg[pos[i]:pos[i] + bi, pos[j]:pos[j] + bj]
+                d_out[voff[p]:voff[p + 1]] = blk.reshape(-1, order="F")
+    n_e = 0.0
+    for j in range(nblk):
+        p = stored[(j, j)]
+        b = s.blk_size[j]
+        n_e += np.trace(d_out[voff[p]:voff[p + 1]].reshape(b, b, order="F"))
+    energy = float(np.dot(d_out, vals))
+    gdl = gE * vals.copy()
+    for j in range(nblk):
+        p = stored[(j, j)]
+        b = s.blk_size[j]
+        blk = gdl[voff[p]:voff[p + 1]].reshape(b, b, order="F")
+        blk[np.arange(b), np.arange(b)] += gN
+        gdl[voff[p]:voff[p + 1]] = blk.reshape(-1, order="F")
+    if gD is not None:
+        gdl = gdl + np.asarray(gD, dtype=np.float64)
+    for g in range(s.ngroups):
+        rows, pos, lam, q, dg = per_group[g]
+        n = q.shape[0]
+        w = np.zeros((n, n))
+        for j in s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]:
+            j = int(j)
+            bj = s.blk_size[j]
+            for p in range(s.col_ptr[j], s.col_ptr[j + 1]):
+                i = int(s.row_idx[p])
+                bi = s.blk_size[i]
+                w[pos[i]:pos[i] + bi, pos[j]:pos[j] + bj] = gdl[voff[p]:voff[p + 1]].reshape(bi, bj, order="F")
+        gamma = -0.5 * ns_divided_differences(lam / scale[g], k[g]) / scale[g]
+        ga = q @ (gamma * (q.T @ w @ q)) @ q.T          # dL/dA_g
+        dmu -= np.trace(ga)
+        for a in rows:
+            for b in rows:
+                p = stored.get((int(a), int(b)))
+                if p is None:
+                    continue
+                ba, bb = s.blk_size[a], s.blk_size[b]
+                dk[voff[p]:voff[p + 1]] += ga[pos[int(a)]:pos[int(a)] + ba, pos[int(b)]:pos[int(b)] + bb].reshape(-1, order="F")
+    dk += gE * d_out
+    return dict(d_values=d_out, n_elec=n_e, energy=energy, dk=dk, dmu=dmu)
+
+
+def symmetric_part(s, dk):
+    """dK_IJ + dK_JI^T for every stored block: what symmetric changes of K see."""
+    voff = s.val_off()
+    where = {}
+    for j in range(s.nblk):
+        for p in range(s.col_ptr[j], s.col_ptr[j + 1]):
+            where[(int(s.row_idx[p]), j)] = p
+    out = np.empty_like(dk)
+    for (i, j), p in where.items():
+        q = where[(j, i)]
+        bi, bj = s.blk_size[i], s.blk_size[j]
+        a = dk[voff[p]:voff[p + 1]].reshape(bi, bj, order="F")
+        b = dk[voff[q]:voff[q + 1]].reshape(bj, bi, order="F")
+        out[voff[p]:voff[p + 1]] = (a + b.T).reshape(-1, order="F")
+    return out

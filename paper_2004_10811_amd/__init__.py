@@ -77,6 +77,7 @@ SIGNATURES = {
     "smx_set_frozen": (_i32, [_vp, _i32]),
     "smx_dn_dmu": (_i32, [_vp, _P(_f64)]),
     "smx_find_mu": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
+    "smx_backward": (_i32, [_vp, _f64, _f64, _vp, _i32, _vp, _i32, _P(_f64)]),
 }
 
 _lib = None
@@ -296,6 +297,21 @@ def smx_find_mu(ctx, n_target: float, tol: float = 1e-8, max_steps: int = 50):
     return mu.value, steps.value
 
 
+def smx_backward(ctx, gE: float = 0.0, gN: float = 0.0, gD=None, out=None):
+    """(dL/dK in K's layout, dL/dmu) for L = gE E + gN N + <gD, D> on the frozen last evaluation."""
+    if gD is not None and isinstance(gD, np.ndarray):
+        gD = np.ascontiguousarray(gD, dtype=np.float64)
+    if out is None:
+        _, nv = smx_get_sizes(ctx)
+        out = np.empty(nv)
+    dmu = _f64()
+    _check(ctx, load_library().smx_backward(ctx, float(gE), float(gN),
+                                             None if gD is None else _ptr(gD),
+                                             0 if gD is None else _on_device(gD),
+                                             _ptr(out), _on_device(out), ctypes.byref(dmu)))
+    return out, dmu.value
+
+
 # ---- convenience object -----------------------------------------------------
 
 @dataclass
@@ -364,3 +380,70 @@ class Context:
 
     def launch_profile(self):
         return smx_get_launch_profile(self.handle)
+
+    def backward(self, gE=0.0, gN=0.0, gD=None, out=None):
+        return smx_backward(self.handle, gE, gN, gD, out)
+
+
+def submatrix_sign_function():
+    """torch.autograd.Function mapping (K values, mu) -> (D values, N, E).
+
+    Forward: one evaluation of the hot path (any precision mode of the
+    context).  Backward: the hand-written adjoint (smx_backward) of the frozen
+    Newton-Schulz map of that evaluation, returning (dK, dmu).  Built lazily so
+    the binding does not need torch.
+    """
+    import torch
+
+    class SubmatrixSign(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, kvals, mu, holder):
+            c = holder.ctx
+            smx_update_values(c.handle, kvals.detach().contiguous())
+            smx_set_mu(c.handle, float(mu))
+            d = torch.empty_like(kvals)
+            r = c.evaluate(out=d)
+            holder.token += 1
+            fctx.holder = holder
+            fctx.token = holder.token
+            fctx.save_for_backward(kvals, mu if torch.is_tensor(mu) else torch.tensor(float(mu)))
+            dev = kvals.device
+            return d, torch.tensor(r.n_elec, dtype=torch.float64, device=dev), \
+                torch.tensor(r.energy, dtype=torch.float64, device=dev)
+
+        @staticmethod
+        def backward(fctx, gD, gN, gE):
+            holder = fctx.holder
+            c = holder.ctx
+            kvals, mu = fctx.saved_tensors
+            if holder.token != fctx.token:
+                # another evaluation ran in between: restore this one's state
+                smx_update_values(c.handle, kvals.detach().contiguous())
+                smx_set_mu(c.handle, float(mu))
+                c.evaluate(out=torch.empty_like(kvals))
+                holder.token += 1
+            ge = 0.0 if gE is None else float(gE)
+            gn = 0.0 if gN is None else float(gN)
+            gd = None if gD is None else gD.detach().contiguous().to(torch.float64)
+            dk = torch.empty_like(kvals)
+            _, dmu = smx_backward(c.handle, ge, gn, gd, dk)
+            gmu = torch.tensor(dmu, dtype=torch.float64, device=mu.device) if fctx.needs_input_grad[1] else None
+            return (dk if fctx.needs_input_grad[0] else None), gmu, None
+
+    return SubmatrixSign
+
+
+class SubmatrixSign:
+    """Differentiable (K values, mu) -> (D values, N, E) on one context.
+
+    ``SubmatrixSign(ctx)(kvals, mu)`` with ``kvals`` a CUDA float64 tensor in
+    the layout loaded into ``ctx`` (``ctx.load(system)`` first).
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.token = 0
+        self._fn = submatrix_sign_function()
+
+    def __call__(self, kvals, mu):
+        return self._fn.apply(kvals, mu, self)

@@ -57,6 +57,9 @@ struct Plan {
     std::vector<ScatterDesc> scat;
     std::vector<int32_t> own_list;    // own columns of every group (submatrix column indices)
     std::vector<double> wtiles;       // live 64 x 64 wave tiles of one product, per group
+    std::vector<TileDesc> tiles_full; // every tile (general products of the adjoint), XCD-ordered
+    std::vector<int64_t> cptr;        // per stored block: its contributions from the groups (adjoint)
+    std::vector<int4> contrib;        // (group, row offset, column offset, 0), ascending group per block
     int64_t work_elems = 0;
     int64_t thin_elems = 0;
     int32_t max_npad = 0, max_own = 0;
@@ -109,6 +112,12 @@ struct smx_context {
     DevBuf<int32_t> d_kfix;
     DevBuf<unsigned long long> d_sfix, d_scale_scratch;
     DevBuf<double> d_tx0, d_tx1, d_dnp, d_dn;    // mu tangent of the iterates, its reduction
+    // adjoint
+    DevBuf<TileDesc> d_tiles_full;
+    DevBuf<int64_t> d_cptr;
+    DevBuf<int4> d_contrib;
+    DevBuf<double> d_adj, d_dk, d_dmu;
+    bool contrib_ready = false;
     DevBuf<unsigned short> d_wx0, d_wx1, d_ww;   // word planes of X (two steps) and W
     DevBuf<double> d_t0, d_t1, d_t2;             // own-column buffers of the last polish step
 
@@ -158,6 +167,36 @@ hipError_t upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
     if (e != hipSuccess) return e;
     if (v.empty()) return hipSuccess;
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// XCD-aware launch order.  Workgroup b of a launch runs on XCD b % 8 (the
+// dispatcher deals workgroups round-robin over the 8 XCDs), and every XCD has
+// its own L2.  All tiles of one group go to one XCD, so the group's panels are
+// fetched into one L2 and shared by its tiles; groups are dealt to XCDs
+// greedily by work (n_pad x tiles), largest first.  Slot s of XCD x becomes
+// workgroup 8 s + x; short lists are padded with idle tiles (group -1).
+void xcd_order(const Plan &P, std::vector<TileDesc> &tiles)
+{
+    constexpr int kXcd = 8;
+    const int32_t ng = P.ngroups;
+    std::vector<int32_t> order(ng);
+    for (int32_t g = 0; g < ng; g++) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.gd[a].npad > P.gd[b].npad; });
+    std::vector<std::vector<TileDesc>> per_group(ng), lists(kXcd);
+    for (const TileDesc &t : tiles) per_group[t.x].push_back(t);
+    std::vector<double> load(kXcd, 0.0);
+    for (int32_t g : order) {
+        int best = 0;
+        for (int x = 1; x < kXcd; x++)
+            if (load[x] < load[best]) best = x;
+        load[best] += (double)P.gd[g].npad * per_group[g].size();
+        for (const TileDesc &t : per_group[g]) lists[best].push_back(t);
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = std::max(len, l.size());
+    tiles.assign(len * kXcd, TileDesc{-1, 0});
+    for (int x = 0; x < kXcd; x++)
+        for (size_t q = 0; q < lists[x].size(); q++) tiles[q * kXcd + x] = lists[x][q];
 }
 
 int32_t build_plan(smx_ctx c)
@@ -253,35 +292,14 @@ int32_t build_plan(smx_ctx c)
         P.wtiles.push_back(wt);
         P.gd.push_back(d);
     }
-    // XCD-aware launch order.  Workgroup b of a launch runs on XCD b % 8 (the
-    // dispatcher deals workgroups round-robin over the 8 XCDs), and every XCD
-    // has its own L2.  All tiles of one group go to one XCD, so the group's
-    // panels are fetched into one L2 and shared by its tiles; groups are
-    // dealt to XCDs greedily by work (n_pad x tiles), largest first.  Slot
-    // s of XCD x becomes workgroup 8 s + x; short lists are padded with idle
-    // tiles (group -1).
-    {
-        constexpr int kXcd = 8;
-        std::vector<int32_t> order(ng);
-        for (int32_t g = 0; g < ng; g++) order[g] = g;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.gd[a].npad > P.gd[b].npad; });
-        std::vector<std::vector<TileDesc>> lists(kXcd);
-        std::vector<double> load(kXcd, 0.0);
-        std::vector<std::vector<TileDesc>> per_group(ng);
-        for (const TileDesc &t : P.tiles) per_group[t.x].push_back(t);
-        for (int32_t g : order) {
-            int best = 0;
-            for (int x = 1; x < kXcd; x++)
-                if (load[x] < load[best]) best = x;
-            load[best] += (double)P.gd[g].npad * per_group[g].size();
-            for (const TileDesc &t : per_group[g]) lists[best].push_back(t);
-        }
-        size_t len = 0;
-        for (const auto &l : lists) len = std::max(len, l.size());
-        P.tiles.assign(len * kXcd, TileDesc{-1, 0});
-        for (int x = 0; x < kXcd; x++)
-            for (size_t q = 0; q < lists[x].size(); q++) P.tiles[q * kXcd + x] = lists[x][q];
+    // XCD-aware launch order (see xcd_order) for the lower-tile and full-tile lists
+    for (int32_t g = 0; g < ng; g++) {
+        const int32_t nt = (P.gd[g].npad + kTile - 1) / kTile;
+        for (int32_t ti = 0; ti < nt; ti++)
+            for (int32_t tj = 0; tj < nt; tj++) P.tiles_full.push_back(TileDesc{g, (ti << 16) | tj});
     }
+    xcd_order(P, P.tiles);
+    xcd_order(P, P.tiles_full);
     for (int64_t p = 0; p < c->nnzb; p++)
         if (P.scat[p].g < 0) return fail(c, SMX_E_INVALID, "internal: stored block without a group");
     return SMX_OK;
@@ -297,6 +315,13 @@ int32_t check_plan(smx_ctx c)
         const GroupDesc &d = P.gd[t.x];
         const int ti = t.y >> 16, tj = t.y & 0xffff;
         if (tj > ti || ti * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
+    }
+    for (const TileDesc &t : P.tiles_full) {
+        if (t.x == -1) continue;
+        if (t.x < 0 || t.x >= P.ngroups) return fail(c, SMX_E_INVALID, "internal: tile group");
+        const GroupDesc &d = P.gd[t.x];
+        const int ti = t.y >> 16, tj = t.y & 0xffff;
+        if (ti * kTile >= d.npad || tj * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
     }
     for (const GroupDesc &d : P.gd) {
         if (d.npad % 16 || d.npad < d.n || d.off + (int64_t)d.npad * d.npad > P.work_elems)
@@ -347,6 +372,8 @@ int32_t ensure_plan(smx_ctx c)
     HIP_TRY(c, c->d_w.ensure((size_t)P.work_elems));
     HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
+    HIP_TRY(c, upload(c->d_tiles_full, P.tiles_full, c->stream));
+    c->contrib_ready = false;
     HIP_TRY(c, upload(c->d_chunks, P.chunks, c->stream));
     HIP_TRY(c, upload(c->d_rinfo, P.rinfo, c->stream));
     HIP_TRY(c, upload(c->d_bmap, P.bmap, c->stream));
@@ -480,6 +507,12 @@ int32_t smx_destroy(smx_ctx c)
     c->d_tx1.release();
     c->d_dnp.release();
     c->d_dn.release();
+    c->d_tiles_full.release();
+    c->d_cptr.release();
+    c->d_contrib.release();
+    c->d_adj.release();
+    c->d_dk.release();
+    c->d_dmu.release();
     c->d_wx0.release();
     c->d_wx1.release();
     c->d_ww.release();
@@ -711,6 +744,7 @@ int32_t smx_evaluate(smx_ctx c)
     it.flags = c->d_flags.p;
     it.ndone = c->d_ndone.p;
     it.kfix = c->use_kfix ? c->d_kfix.p : nullptr;
+    it.kact = -1;
     it.tau_parts = c->d_tau_parts.p;
     it.tau_hist = c->d_tau_hist.p;
     it.resid_stride = stride;
@@ -1232,6 +1266,173 @@ int32_t smx_find_mu(smx_ctx c, double n_target, double tol, int32_t max_steps, d
     if (steps_out) *steps_out = std::min(steps, max_steps);
     if (result == SMX_E_NOT_CONVERGED) return fail(c, SMX_E_NOT_CONVERGED, "mu search did not reach the tolerance");
     return result;
+}
+
+// Per stored block of K, the groups whose submatrix contains it, with the
+// block's offsets there (the transpose of the gather), ascending in group.
+static int32_t ensure_contrib(smx_ctx c)
+{
+    if (c->contrib_ready) return SMX_OK;
+    Plan &P = c->plan;
+    std::vector<int64_t> cnt((size_t)c->nnzb + 1, 0);
+    for (int32_t g = 0; g < P.ngroups; g++) {
+        const GroupDesc &d = P.gd[g];
+        for (int64_t q = 0; q < (int64_t)d.m * d.m; q++) {
+            const int32_t p = P.bmap[(size_t)(d.map_off + q)];
+            if (p >= 0) cnt[(size_t)p + 1]++;
+        }
+    }
+    for (int64_t p = 0; p < c->nnzb; p++) cnt[(size_t)p + 1] += cnt[(size_t)p];
+    P.cptr = cnt;
+    P.contrib.assign((size_t)cnt[(size_t)c->nnzb], int4{0, 0, 0, 0});
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t g = 0; g < P.ngroups; g++) {
+        const GroupDesc &d = P.gd[g];
+        for (int32_t b = 0; b < d.m; b++)
+            for (int32_t a = 0; a < d.m; a++) {
+                const int32_t p = P.bmap[(size_t)(d.map_off + a + (int64_t)d.m * b)];
+                if (p < 0) continue;
+                P.contrib[(size_t)fill[(size_t)p]++] =
+                    int4{g, P.boffs[d.boff_off + a], P.boffs[d.boff_off + b], 0};
+            }
+    }
+    HIP_TRY(c, upload(c->d_cptr, P.cptr, c->stream));
+    HIP_TRY(c, upload(c->d_contrib, P.contrib, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->contrib_ready = true;
+    return SMX_OK;
+}
+
+int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t gD_on_device, double *dK_out,
+                     int32_t dK_on_device, double *dmu_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!dK_out && !dmu_out) return fail(c, SMX_E_INVALID, "nothing to compute (dK_out and dmu_out are NULL)");
+    if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
+    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = set_device(c)) return st;
+    if (int32_t st = ensure_contrib(c)) return st;
+    const Plan &P = c->plan;
+    const int32_t ng = P.ngroups;
+    hipStream_t st = c->stream;
+    // the frozen map of the last evaluation: its step counts and scales
+    std::vector<int32_t> kf((size_t)ng);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int32_t kmax = 0;
+    for (int32_t &k : kf) {
+        k += c->last_polish;
+        kmax = std::max(kmax, k);
+    }
+    HIP_TRY(c, upload(c->d_kfix, kf, st));
+    const unsigned long long *sptr = c->last_sfix ? c->d_sfix.p : c->d_scale.p;
+    // slabs: Xbar, W, Z, Y, 8 segment iterates, checkpoints X_{8m}
+    constexpr int kSeg = 8;
+    const int32_t ncp = kmax / kSeg + 1;
+    const int64_t E = P.work_elems;
+    const size_t nslab = (size_t)(4 + kSeg + ncp);
+    {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(c, hipMemGetInfo(&fr, &tot));
+        const size_t need = nslab * (size_t)E * sizeof(double);
+        if (need > fr + c->d_adj.bytes())
+            return fail(c, SMX_E_NOMEM, "adjoint needs " + std::to_string(need >> 20) + " MiB of device memory");
+    }
+    HIP_TRY(c, c->d_adj.ensure(nslab * (size_t)E));
+    HIP_TRY(c, c->d_dk.ensure((size_t)std::max<int64_t>(c->nvals, 1)));
+    HIP_TRY(c, c->d_dmu.ensure(2));
+    HIP_TRY(c, c->d_dnp.ensure((size_t)std::max(ng, 1)));
+    double *xb = c->d_adj.p, *wb = xb + E, *zb = wb + E, *yb = zb + E;
+    double *seg[kSeg];
+    for (int q = 0; q < kSeg; q++) seg[q] = yb + E * (q + 1);
+    double *cp0 = yb + E * (kSeg + 1);
+    auto cp = [&](int m) { return cp0 + E * m; };
+
+    IterState it;
+    it.scale_bits = const_cast<unsigned long long *>(sptr);
+    it.resid_bits = c->d_resid.p;
+    it.done = c->d_done.p;
+    it.kfinal = c->d_kfinal.p;
+    it.flags = c->d_flags.p;
+    it.ndone = c->d_ndone.p;
+    it.kfix = c->d_kfix.p;
+    it.kact = -1;
+    it.tau_parts = c->d_tau_parts.p;
+    it.tau_hist = c->d_tau_hist.p;
+    it.resid_stride = c->last_stride;
+    it.tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
+    const int scratch_slot = c->last_max_iter + 1;    // residual slot the adjoint squares may use
+    const int nt = (int)P.tiles.size(), ntf = (int)P.tiles_full.size();
+    const TileDesc *tl = c->d_tiles.p, *tf = c->d_tiles_full.p;
+
+    // seed: Xbar_K = sym(-1/2 dL/dD at the own-column stored positions)
+    HIP_TRY(c, hipMemsetAsync(xb, 0, sizeof(double) * (size_t)E, st));
+    const double *gdp = nullptr;
+    DevBuf<double> gdd;
+    if (gD) {
+        if (gD_on_device) {
+            gdp = gD;
+        } else {
+            HIP_TRY(c, gdd.ensure((size_t)c->nvals));
+            HIP_TRY(c, hipMemcpyAsync(gdd.p, gD, sizeof(double) * (size_t)c->nvals, hipMemcpyHostToDevice, st));
+            gdp = gdd.p;
+        }
+    }
+    HIP_TRY(c, launch_adj_seed(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_k.p, gdp, gE, gN, xb));
+    HIP_TRY(c, launch_symmetrize(st, ng, P.max_npad, c->d_gd.p, xb));
+
+    // forward with checkpoints: X_0 = A / s_g, X_{k+1} = X_k W_k
+    HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, 2 * sizeof(double), st));
+    HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
+    HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
+                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, seg[0], c->d_scale_scratch.p));
+    HIP_TRY(c, launch_scale_slab(st, ng, P.max_npad, c->d_gd.p, sptr, seg[0]));
+    HIP_TRY(c, hipMemcpyAsync(cp(0), seg[0], sizeof(double) * (size_t)E, hipMemcpyDeviceToDevice, st));
+    auto fwd_step = [&](int k, const double *x, double *xnext) -> int32_t {
+        it.kact = k;
+        HIP_TRY(c, launch_ns_f64(st, 0, nt, tl, c->d_gd.p, x, x, wb, it, scratch_slot, 0.0, c->last_max_iter, 1));
+        HIP_TRY(c, launch_ns_f64(st, 1, nt, tl, c->d_gd.p, x, wb, xnext, it, scratch_slot, 0.0, c->last_max_iter, 1));
+        return SMX_OK;
+    };
+    const int32_t mlast = (kmax > 0) ? (kmax - 1) / kSeg : 0;
+    for (int32_t m = 0; m <= mlast; m++) {
+        if (m > 0) HIP_TRY(c, hipMemcpyAsync(seg[0], cp(m), sizeof(double) * (size_t)E, hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j + 1 < kSeg && m * kSeg + j + 1 <= kmax - 1; j++)
+            if (int32_t e = fwd_step(m * kSeg + j, seg[j], seg[j + 1])) return e;
+        if (m < mlast)
+            if (int32_t e = fwd_step(m * kSeg + kSeg - 1, seg[kSeg - 1], cp(m + 1))) return e;
+    }
+    // backward over the segments, the last one still in place
+    for (int32_t m = mlast; m >= 0 && kmax > 0; m--) {
+        if (m < mlast) {
+            HIP_TRY(c, hipMemcpyAsync(seg[0], cp(m), sizeof(double) * (size_t)E, hipMemcpyDeviceToDevice, st));
+            for (int j = 0; j + 1 < kSeg; j++)
+                if (int32_t e = fwd_step(m * kSeg + j, seg[j], seg[j + 1])) return e;
+        }
+        const int32_t khi = std::min(m * kSeg + kSeg - 1, kmax - 1);
+        for (int32_t k = khi; k >= m * kSeg; k--) {
+            const double *x = seg[k - m * kSeg];
+            it.kact = k;
+            HIP_TRY(c, launch_ns_f64(st, 0, nt, tl, c->d_gd.p, x, x, wb, it, scratch_slot, 0.0, c->last_max_iter, 1));
+            HIP_TRY(c, launch_ns_f64(st, 4, ntf, tf, c->d_gd.p, xb, wb, zb, it, scratch_slot, 0.0, c->last_max_iter, 1));
+            HIP_TRY(c, launch_ns_f64(st, 4, ntf, tf, c->d_gd.p, xb, x, yb, it, scratch_slot, 0.0, c->last_max_iter, 1));
+            HIP_TRY(c, launch_ns_f64(st, 3, nt, tl, c->d_gd.p, x, yb, xb, it, scratch_slot, 0.0, c->last_max_iter, 1,
+                                     zb));
+        }
+    }
+    // dK: transposed gather of Abar = Xbar_0 / s_g plus gE D; dL/dmu = -sum_g tr(Abar_g)
+    HIP_TRY(c, launch_gather_t(st, c->nnzb, c->d_cptr.p, c->d_contrib.p, c->d_valoff.p, c->d_brow.p, c->d_bcol.p,
+                               c->d_gd.p, sptr, xb, c->d_d.p, gE, c->d_dk.p));
+    HIP_TRY(c, launch_diag_part(st, ng, c->d_gd.p, sptr, xb, c->d_dnp.p));
+    HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dmu.p));
+    if (dK_out && c->nvals > 0)
+        HIP_TRY(c, hipMemcpyAsync(dK_out, c->d_dk.p, sizeof(double) * (size_t)c->nvals,
+                                  dK_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    double dm[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(dm, c->d_dmu.p, sizeof dm, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    gdd.release();
+    if (dmu_out) *dmu_out = dm[0];
+    return SMX_OK;
 }
 
 int32_t smx_get_sizes(smx_ctx c, int32_t *ngroups, int64_t *nvalues)

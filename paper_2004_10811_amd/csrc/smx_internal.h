@@ -52,6 +52,7 @@ struct IterState {
     int32_t *flags;                   // [ngroups] bit 0: not converged, bit 1: non-finite
     int32_t *ndone;                   // [1] number of finished groups
     const int32_t *kfix;              // [ngroups] frozen step counts (nullptr: stopping rule)
+    int32_t kact;                     // >= 0: only groups with kact < kfix[g] take part (adjoint passes)
     double *tau_parts;                // [ngroups * tau_nt] per diagonal tile: sum of (1 - T_ii)
     double *tau_hist;                 // [ngroups * resid_stride] Tr(I - X_k^2) per step
     int32_t resid_stride;             // steps 0..max_iter, then one slot per polish step
@@ -73,9 +74,33 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
 // polish != 0: unconditional step on every group (a = 1, no skipping, no
 // stopping); the square's residual goes to slot k of the residual history.
 // With it.kfix set, a group stops exactly at step kfix[g] (frozen iteration).
+// mode 3 (adjoint step, lower tiles): acc = X Y; out = Xb is updated in place to
+//         -1.5 Xb + Z + Z^T - 0.5 acc with Z = aux (= Xb W).
+// mode 4 (full tiles, plain product): out = x b with x symmetric (read by columns)
+//         and b general; every tile of the group is listed.
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
-                         const IterState &it, int k, double tol, int max_iter, int polish);
+                         const IterState &it, int k, double tol, int max_iter, int polish,
+                         const double *aux = nullptr);
+
+// ---- adjoint helpers ------------------------------------------------------
+// xb (zeroed) at the own-column stored positions: -1/2 (gE K + gN I_diag + gD).
+hipError_t launch_adj_seed(hipStream_t st, int64_t nblocks, const ScatterDesc *sd, const int64_t *valoff,
+                           const GroupDesc *groups, const double *kvals, const double *gd, double ge, double gn,
+                           double *xb);
+// in place: xb = (xb + xb^T) / 2 on each group's n_pad x n_pad slab.
+hipError_t launch_symmetrize(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups, double *xb);
+// in place: x = a x with a = 1/s_g (the Gershgorin prescaling of X_0).
+hipError_t launch_scale_slab(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups,
+                             const unsigned long long *scale_bits, double *x);
+// dK[p] = ge D[p] + sum over the contributions (g, oi, oj) of block p of Xb_g[oi.., oj..] / s_g,
+// in list order; part[g] = -sum_i Xb_g[i, i] / s_g (the mu derivative).
+hipError_t launch_gather_t(hipStream_t st, int64_t nblocks, const int64_t *cptr, const int4 *contrib,
+                           const int64_t *valoff, const int32_t *brow, const int32_t *bcol,
+                           const GroupDesc *groups, const unsigned long long *scale_bits, const double *xb,
+                           const double *dvals, double ge, double *dk);
+hipError_t launch_diag_part(hipStream_t st, int ngroups, const GroupDesc *groups,
+                            const unsigned long long *scale_bits, const double *xb, double *part);
 
 // Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value).
 hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,

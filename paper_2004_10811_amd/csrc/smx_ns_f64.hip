@@ -44,7 +44,8 @@ template <int MODE>
 __global__ __launch_bounds__(256, 2)
 void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
                    const double *__restrict__ xin, const double *__restrict__ bin,
-                   double *__restrict__ out, IterState it, int k, double tol, int max_iter, int polish)
+                   double *__restrict__ out, IterState it, int k, double tol, int max_iter, int polish,
+                   const double *__restrict__ aux)
 {
     __shared__ double As[2][BM][SK];
     __shared__ double Bs[2][BM][SK];
@@ -52,13 +53,14 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
     if (g < 0) return;                            // idle slot of the launch order
-    if (!polish && it.done[g]) return;            // finished at an earlier step
+    if (it.kact >= 0 && it.kfix && it.kact >= it.kfix[g]) return;   // group not in this adjoint step
+    if (!polish && MODE <= 2 && it.done[g]) return;                 // finished at an earlier step
     const int ti = td.y >> 16, tj = td.y & 0xffff;
     const GroupDesc gd = groups[g];
     const int ld = gd.npad;
 
     double a = 1.0;
-    if (k == 0 && !polish && MODE != 2) {
+    if (k == 0 && !polish && MODE < 2) {
         const double s = __longlong_as_double((long long)it.scale_bits[g]);
         a = s > 0.0 ? 1.0 / s : 0.0;
     }
@@ -98,7 +100,7 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     // waves whose 64 x 64 sub-tile lies wholly in the padding, or strictly
     // above the diagonal of a diagonal tile (never stored), skip the math
     const int row_w = ti * BM + wr * 64, col_w = tj * BM + wc * 64;
-    const bool wave_live = (row_w < ld) && (col_w < ld) && !(ti == tj && wr < wc);
+    const bool wave_live = (row_w < ld) && (col_w < ld) && (MODE == 4 || !(ti == tj && wr < wc));
 
     d4 acc[4][4];
 #pragma unroll
@@ -185,9 +187,21 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
                     val = -0.5 * t + (r == c ? 1.5 : 0.0);
                 } else if (MODE == 1) {
                     val = a * acc[i][j][v];
-                } else {
+                } else if (MODE == 2) {
                     // tangent: 3 Xd W - 3 Xd (Xd and W commute, so the product is symmetric)
                     val = (r < ld && c < ld) ? 3.0 * acc[i][j][v] - 3.0 * xin[gd.off + r + (int64_t)c * ld] : 0.0;
+                } else if (MODE == 3) {
+                    // adjoint step: Xb_k = -1.5 Xb + Z + Z^T - 0.5 X (Xb X), Z = Xb W
+                    val = 0.0;
+                    if (r < ld && c < ld && r >= c)
+                        val = -1.5 * og[r + (int64_t)c * ld] + aux[gd.off + r + (int64_t)c * ld] +
+                              aux[gd.off + c + (int64_t)r * ld] - 0.5 * acc[i][j][v];
+                } else {
+                    val = acc[i][j][v];
+                }
+                if (MODE == 4) {
+                    if (r < ld && c < ld) og[r + (int64_t)c * ld] = val;
+                    continue;
                 }
                 if (r < ld && c < ld && r >= c) {
                     og[r + (int64_t)c * ld] = val;
@@ -209,18 +223,21 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
 
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
-                         const IterState &it, int k, double tol, int max_iter, int polish)
+                         const IterState &it, int k, double tol, int max_iter, int polish, const double *aux)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (mode == 0)
-        hipLaunchKernelGGL(ns_f64_kernel<0>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
-                           out, it, k, tol, max_iter, polish);
-    else if (mode == 1)
-        hipLaunchKernelGGL(ns_f64_kernel<1>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
-                           out, it, k, tol, max_iter, polish);
-    else
-        hipLaunchKernelGGL(ns_f64_kernel<2>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b,
-                           out, it, k, tol, max_iter, polish);
+#define SMX_NS_LAUNCH(M)                                                                                    \
+    hipLaunchKernelGGL(ns_f64_kernel<M>, dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b, out, it, k, tol, \
+                       max_iter, polish, aux)
+    switch (mode) {
+    case 0: SMX_NS_LAUNCH(0); break;
+    case 1: SMX_NS_LAUNCH(1); break;
+    case 2: SMX_NS_LAUNCH(2); break;
+    case 3: SMX_NS_LAUNCH(3); break;
+    case 4: SMX_NS_LAUNCH(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_NS_LAUNCH
     return hipGetLastError();
 }
 

@@ -45,3 +45,61 @@ def test_weights_sum_to_own_column_count(oracle_lib):
     for t, g in enumerate(spec.groups):
         own = s.blk_size[s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]].sum()
         assert abs(spec.w[t].sum() - own) < 1e-12
+
+
+def _sym_direction(s, rng, i, j):
+    """Random symmetric change of K on the block pair (I, J) and (J, I)."""
+    voff = s.val_off()
+    v = np.zeros_like(s.values)
+    where = {}
+    for jj in range(s.nblk):
+        for p in range(s.col_ptr[jj], s.col_ptr[jj + 1]):
+            where[(int(s.row_idx[p]), jj)] = p
+    bi, bj = s.blk_size[i], s.blk_size[j]
+    m = rng.normal(size=(bi, bj))
+    if i == j:
+        m = m + m.T
+    p = where[(i, j)]
+    v[voff[p]:voff[p + 1]] = m.reshape(-1, order="F")
+    if i != j:
+        q = where[(j, i)]
+        v[voff[q]:voff[q + 1]] = m.T.reshape(-1, order="F")
+    return v
+
+
+def test_frozen_gradient_matches_finite_differences(oracle_lib):
+    """Daleckii-Krein gradient of L = gE E + gN N + <gD, D> vs central differences."""
+    s = random_block_system(47, [3, 4, 2, 5, 3], density=0.6, coupling=0.06, groups=[[0, 1], [2], [3, 4]])
+    k = [4, 3, 5]
+    scale = [2.0, 2.5, 1.7]
+    mu = 0.03
+    rng = np.random.default_rng(5)
+    gd = rng.normal(size=s.values.shape)
+    ge, gn = 0.7, -1.3
+
+    def loss(vals, m):
+        r = oracle_lib.frozen_gradient(s, k, scale, m, values=vals)
+        return ge * r["energy"] + gn * r["n_elec"] + float(np.dot(gd, r["d_values"]))
+
+    r0 = oracle_lib.frozen_gradient(s, k, scale, mu, ge, gn, gd)
+    h = 1e-6
+    for (i, j) in [(0, 0), (1, 0), (3, 4), (2, 2), (4, 3)]:
+        try:
+            v = _sym_direction(s, rng, i, j)
+        except KeyError:
+            continue
+        fd = (loss(s.values + h * v, mu) - loss(s.values - h * v, mu)) / (2 * h)
+        ad = float(np.dot(r0["dk"], v))
+        assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)), (i, j, fd, ad)
+    fd_mu = (loss(s.values, mu + h) - loss(s.values, mu - h)) / (2 * h)
+    assert abs(fd_mu - r0["dmu"]) <= 1e-6 * max(1.0, abs(fd_mu))
+
+
+def test_frozen_gradient_dmu_equals_tangent_form(oracle_lib):
+    """dN/dmu from the reverse form equals the closed form sum w p_k'/(2s)."""
+    s = water_system(n_mol=4, box=5.0, r_cut=3.0, seed=44)
+    spec = oracle_lib.GroupSpectra(s)
+    k = [5] * s.ngroups
+    scale = [4.0] * s.ngroups
+    r = oracle_lib.frozen_gradient(s, k, scale, 0.02, gN=1.0)
+    assert abs(r["dmu"] - spec.dn_dmu_frozen(0.02, k, scale)) <= 1e-10 * max(1.0, abs(r["dmu"]))
