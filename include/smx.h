@@ -86,7 +86,8 @@ typedef struct {
                                       polish), i.e. the k at which X_k was taken   */
     int32_t n_not_converged;  /* groups that hit max_iter                         */
     int32_t precision;        /* precision mode of the last evaluation            */
-    int32_t pad0;
+    int32_t nwaves;           /* waves the groups were processed in (see
+                                 smx_set_workspace_limit)                          */
     double  n_mean;           /* mean n_g                                         */
     double  iters_mean;
     double  resid_max;        /* max over groups of the last computed max|X^2 - I| */
@@ -162,6 +163,22 @@ int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
  */
 int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
                             int32_t n_polish, double switch_tol);
+
+/*
+ * Device work space.  The dense submatrices are processed in waves of
+ * consecutive groups; all groups of a wave are resident together (three FP64
+ * n_pad x n_pad slabs per group, the reduced-precision word planes laid over
+ * two of them, 26 bytes per element, plus 24 n_pad m_own bytes of own-column
+ * buffers), and the waves reuse one arena.  bytes = 0 (the default) sizes the
+ * waves to the free device memory at plan time, less the plan's tables and
+ * 1 GiB, and at most 3/4 of the device; bytes > 0 caps the arena and forces
+ * more waves.  A group that does
+ * not fit alone fails with SMX_E_NOMEM.  Results do not depend on the wave
+ * split (bitwise).  With more than one wave, smx_backward is unsupported and
+ * smx_get_submatrix(what = 1) serves only the last wave's groups.  Takes
+ * effect at the next call that builds the plan; invalidates results.
+ */
+int32_t smx_set_workspace_limit(smx_ctx ctx, int64_t bytes);
 
 /*
  * Evaluate D, N and E for the current K, groups and mu.  The work is

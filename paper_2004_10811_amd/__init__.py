@@ -46,7 +46,7 @@ _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.
 
 class SmxStats(ctypes.Structure):
     _fields_ = [("ngroups", _i32), ("n_min", _i32), ("n_max", _i32), ("iters_min", _i32),
-                ("iters_max", _i32), ("n_not_converged", _i32), ("precision", _i32), ("pad0", _i32),
+                ("iters_max", _i32), ("n_not_converged", _i32), ("precision", _i32), ("nwaves", _i32),
                 ("n_mean", _f64), ("iters_mean", _f64), ("resid_max", _f64), ("algo_flops", _f64),
                 ("exec_flops", _f64), ("time_gather_ms", _f64), ("time_iterate_ms", _f64),
                 ("time_scatter_ms", _f64), ("time_total_ms", _f64), ("workspace_bytes", _f64)]
@@ -64,6 +64,7 @@ SIGNATURES = {
     "smx_set_temperature": (_i32, [_vp, _f64]),
     "smx_set_precision": (_i32, [_vp, _i32]),
     "smx_set_convergence": (_i32, [_vp, _f64, _i32, _i32, _f64]),
+    "smx_set_workspace_limit": (_i32, [_vp, _i64]),
     "smx_evaluate": (_i32, [_vp]),
     "smx_wait": (_i32, [_vp]),
     "smx_get_d": (_i32, [_vp, _vp, _i32]),
@@ -206,6 +207,10 @@ def smx_set_convergence(ctx, tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-
                                                            int(n_polish), float(switch_tol)))
 
 
+def smx_set_workspace_limit(ctx, nbytes=0):
+    return _check(ctx, load_library().smx_set_workspace_limit(ctx, int(nbytes)))
+
+
 def smx_evaluate(ctx):
     return _check(ctx, load_library().smx_evaluate(ctx))
 
@@ -236,7 +241,7 @@ def smx_energy(ctx) -> float:
 def smx_get_stats(ctx) -> dict:
     s = SmxStats()
     _check(ctx, load_library().smx_get_stats(ctx, ctypes.byref(s)))
-    return {f: getattr(s, f) for f, _ in SmxStats._fields_ if f != "pad0"}
+    return {f: getattr(s, f) for f, _ in SmxStats._fields_}
 
 
 def smx_get_sizes(ctx):
@@ -352,8 +357,10 @@ class Context:
         return self
 
     def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
-                  mu=None, kT=None):
+                  mu=None, kT=None, workspace_limit=None):
         smx_set_precision(self.handle, precision)
+        if workspace_limit is not None:
+            smx_set_workspace_limit(self.handle, workspace_limit)
         smx_set_convergence(self.handle, tol, max_iter, n_polish, switch_tol)
         if mu is not None:
             smx_set_mu(self.handle, mu)

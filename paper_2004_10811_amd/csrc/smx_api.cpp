@@ -60,10 +60,26 @@ struct Plan {
     std::vector<TileDesc> tiles_full; // every tile (general products of the adjoint), XCD-ordered
     std::vector<int64_t> cptr;        // per stored block: its contributions from the groups (adjoint)
     std::vector<int4> contrib;        // (group, row offset, column offset, 0), ascending group per block
-    int64_t work_elems = 0;
-    int64_t thin_elems = 0;
+    // waves: consecutive group ranges [wave_g[w], wave_g[w+1]) whose slabs share one arena;
+    // slab and own-column offsets (GroupDesc::off, thin_off) are relative to the wave
+    std::vector<int32_t> wave_g;
+    std::vector<int32_t> wave_of;      // wave of every group
+    std::vector<int64_t> tile_beg;     // wave w's lower tiles: tiles[tile_beg[w] .. tile_beg[w+1])
+    std::vector<int64_t> chunk_beg;    // wave w's gather chunks (chunks are in group order)
+    std::vector<int64_t> plist;        // stored blocks of the own columns of each wave (more than one wave)
+    std::vector<int64_t> plist_beg;
+    int64_t work_elems = 0;            // slab elements of the largest wave
+    int64_t thin_elems = 0;            // own-column elements of the largest wave
+    int64_t total_elems = 0;           // slab elements of all groups
     int32_t max_npad = 0, max_own = 0;
+    int32_t nwaves() const { return (int32_t)wave_g.size() - 1; }
 };
+
+// Arena of one wave: three FP64 slabs X_a | X_b | W (24 bytes per element);
+// in the reduced-precision modes the word planes of X_a, X_b and W start at
+// byte 8E (over X_b and W, dead during the bulk) and reach 8E + 6 nw E bytes,
+// i.e. 26 bytes per element with three BF16 words.
+constexpr int64_t kArenaBytesPerElem = 26;
 
 }  // namespace
 
@@ -102,7 +118,8 @@ struct smx_context {
     DevBuf<int32_t> d_bmap, d_boffs;
     DevBuf<ScatterDesc> d_scat;
     // device: work
-    DevBuf<double> d_x0, d_x1, d_w;
+    DevBuf<double> d_arena;                 // one wave's slabs (see kArenaBytesPerElem)
+    int64_t ws_limit = 0;                   // arena byte limit (0: from free device memory)
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
@@ -118,8 +135,8 @@ struct smx_context {
     DevBuf<int4> d_contrib;
     DevBuf<double> d_adj, d_dk, d_dmu;
     bool contrib_ready = false;
-    DevBuf<unsigned short> d_wx0, d_wx1, d_ww;   // word planes of X (two steps) and W
     DevBuf<double> d_t0, d_t1, d_t2;             // own-column buffers of the last polish step
+    DevBuf<int64_t> d_plist;
 
     // host polling / timing
     int32_t *h_ndone = nullptr;
@@ -128,7 +145,9 @@ struct smx_context {
     std::vector<hipEvent_t> ev_launch;   // two per product launch (before, after)
     std::vector<int32_t> launch_step;    // step k of each product launch
     std::vector<int32_t> launch_kind;    // 0/1 FP64 square/update, 2/3 word square/update, 4/5 polish
-    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
+    std::vector<int32_t> launch_wave;    // wave of each product launch
+    std::vector<hipEvent_t> ev_wave;     // four per wave: start, iterate, scatter, end
+    hipEvent_t ev_t0 = nullptr, ev_t3 = nullptr;
 
     // results of the last evaluation
     bool evaluated = false;
@@ -169,28 +188,30 @@ hipError_t upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
+double *slab(smx_ctx c, int i) { return c->d_arena.p + (size_t)i * (size_t)c->plan.work_elems; }
+
 // XCD-aware launch order.  Workgroup b of a launch runs on XCD b % 8 (the
 // dispatcher deals workgroups round-robin over the 8 XCDs), and every XCD has
 // its own L2.  All tiles of one group go to one XCD, so the group's panels are
 // fetched into one L2 and shared by its tiles; groups are dealt to XCDs
 // greedily by work (n_pad x tiles), largest first.  Slot s of XCD x becomes
 // workgroup 8 s + x; short lists are padded with idle tiles (group -1).
-void xcd_order(const Plan &P, std::vector<TileDesc> &tiles)
+void xcd_order(const Plan &P, int32_t g0, int32_t g1, std::vector<TileDesc> &tiles)
 {
     constexpr int kXcd = 8;
-    const int32_t ng = P.ngroups;
+    const int32_t ng = g1 - g0;
     std::vector<int32_t> order(ng);
-    for (int32_t g = 0; g < ng; g++) order[g] = g;
+    for (int32_t g = 0; g < ng; g++) order[g] = g0 + g;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.gd[a].npad > P.gd[b].npad; });
     std::vector<std::vector<TileDesc>> per_group(ng), lists(kXcd);
-    for (const TileDesc &t : tiles) per_group[t.x].push_back(t);
+    for (const TileDesc &t : tiles) per_group[t.x - g0].push_back(t);
     std::vector<double> load(kXcd, 0.0);
     for (int32_t g : order) {
         int best = 0;
         for (int x = 1; x < kXcd; x++)
             if (load[x] < load[best]) best = x;
-        load[best] += (double)P.gd[g].npad * per_group[g].size();
-        for (const TileDesc &t : per_group[g]) lists[best].push_back(t);
+        load[best] += (double)P.gd[g].npad * per_group[g - g0].size();
+        for (const TileDesc &t : per_group[g - g0]) lists[best].push_back(t);
     }
     size_t len = 0;
     for (const auto &l : lists) len = std::max(len, l.size());
@@ -239,8 +260,7 @@ int32_t build_plan(smx_ctx c)
         if (n > 60000) return fail(c, SMX_E_INVALID, "submatrix dimension above 60000 in group " + std::to_string(g));
         d.n = (int32_t)n;
         d.npad = (int32_t)(((std::max<int64_t>(n, 1) + kPad - 1) / kPad) * kPad);
-        d.off = P.work_elems;
-        P.work_elems += (int64_t)d.npad * d.npad;
+        P.total_elems += (int64_t)d.npad * d.npad;
         d.rinfo_off = (int64_t)P.rinfo.size();
         for (int32_t t = 0; t < m; t++) {
             const int32_t b = c->blk_size[rows[t]];
@@ -270,14 +290,10 @@ int32_t build_plan(smx_ctx c)
             ocol += c->blk_size[j];
         }
         d.m_own = ocol;
-        d.thin_off = P.thin_elems;
-        P.thin_elems += (int64_t)d.npad * d.m_own;
         P.max_npad = std::max(P.max_npad, d.npad);
         P.max_own = std::max(P.max_own, d.m_own);
         for (int32_t t = 0; t < m; t++) pos[rows[t]] = -1;
         const int32_t nt = (d.npad + kTile - 1) / kTile;
-        for (int32_t ti = 0; ti < nt; ti++)
-            for (int32_t tj = 0; tj <= ti; tj++) P.tiles.push_back(TileDesc{g, (ti << 16) | tj});
         for (int32_t r0 = 0; r0 < d.npad; r0 += 256) P.chunks.push_back(int2{g, r0});
         // issued flops of one product: live 64 x 64 wave tiles x K
         double wt = 0;
@@ -292,16 +308,95 @@ int32_t build_plan(smx_ctx c)
         P.wtiles.push_back(wt);
         P.gd.push_back(d);
     }
-    // XCD-aware launch order (see xcd_order) for the lower-tile and full-tile lists
-    for (int32_t g = 0; g < ng; g++) {
-        const int32_t nt = (P.gd[g].npad + kTile - 1) / kTile;
-        for (int32_t ti = 0; ti < nt; ti++)
-            for (int32_t tj = 0; tj < nt; tj++) P.tiles_full.push_back(TileDesc{g, (ti << 16) | tj});
-    }
-    xcd_order(P, P.tiles);
-    xcd_order(P, P.tiles_full);
     for (int64_t p = 0; p < c->nnzb; p++)
         if (P.scat[p].g < 0) return fail(c, SMX_E_INVALID, "internal: stored block without a group");
+    return SMX_OK;
+}
+
+// Device bytes one group adds to a wave: its share of the arena and of the
+// three own-column buffers of the last polish step.
+int64_t group_bytes(const GroupDesc &d)
+{
+    return kArenaBytesPerElem * (int64_t)d.npad * d.npad + 3 * 8 * (int64_t)d.npad * d.m_own;
+}
+
+// Split the groups into consecutive waves of at most `budget` bytes each
+// (balanced: about total / ceil(total / budget) per wave), assign the
+// wave-relative slab offsets, and build each wave's launch lists.
+int32_t partition_waves(smx_ctx c, int64_t budget)
+{
+    Plan &P = c->plan;
+    const int32_t ng = P.ngroups;
+    int64_t total = 0;
+    for (int32_t g = 0; g < ng; g++) {
+        const int64_t b = group_bytes(P.gd[g]);
+        if (b > budget)
+            return fail(c, SMX_E_NOMEM, "group " + std::to_string(g) + " needs " + std::to_string(b >> 20) +
+                                            " MiB of work space, more than the " + std::to_string(budget >> 20) +
+                                            " MiB available");
+        total += b;
+    }
+    const int64_t nw0 = std::max<int64_t>(1, (total + budget - 1) / budget);
+    const int64_t target = std::min<int64_t>(budget, (total + nw0 - 1) / nw0);
+    P.wave_g.assign(1, 0);
+    P.wave_of.assign((size_t)ng, 0);
+    int64_t cur = 0;
+    for (int32_t g = 0; g < ng; g++) {
+        const int64_t b = group_bytes(P.gd[g]);
+        if (cur > 0 && cur + b > target) {
+            P.wave_g.push_back(g);
+            cur = 0;
+        }
+        cur += b;
+        P.wave_of[g] = (int32_t)P.wave_g.size() - 1;
+    }
+    P.wave_g.push_back(ng);
+    const int32_t nw = P.nwaves();
+    P.work_elems = P.thin_elems = 0;
+    P.tiles.clear();
+    P.tiles_full.clear();
+    P.tile_beg.assign(1, 0);
+    P.chunk_beg.assign(1, 0);
+    P.plist.clear();
+    P.plist_beg.assign(1, 0);
+    size_t ch = 0;
+    for (int32_t w = 0; w < nw; w++) {
+        int64_t e = 0, t = 0;
+        std::vector<TileDesc> tl;
+        for (int32_t g = P.wave_g[w]; g < P.wave_g[w + 1]; g++) {
+            GroupDesc &d = P.gd[g];
+            d.off = e;
+            e += (int64_t)d.npad * d.npad;
+            d.thin_off = t;
+            t += (int64_t)d.npad * d.m_own;
+            const int32_t nt = (d.npad + kTile - 1) / kTile;
+            for (int32_t ti = 0; ti < nt; ti++)
+                for (int32_t tj = 0; tj <= ti; tj++) tl.push_back(TileDesc{g, (ti << 16) | tj});
+        }
+        P.work_elems = std::max(P.work_elems, e);
+        P.thin_elems = std::max(P.thin_elems, t);
+        xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
+        P.tiles.insert(P.tiles.end(), tl.begin(), tl.end());
+        P.tile_beg.push_back((int64_t)P.tiles.size());
+        while (ch < P.chunks.size() && P.chunks[ch].x < P.wave_g[w + 1]) ch++;
+        P.chunk_beg.push_back((int64_t)ch);
+    }
+    if (nw == 1) {
+        // every tile (general products of the adjoint), XCD-ordered
+        for (int32_t g = 0; g < ng; g++) {
+            const int32_t nt = (P.gd[g].npad + kTile - 1) / kTile;
+            for (int32_t ti = 0; ti < nt; ti++)
+                for (int32_t tj = 0; tj < nt; tj++) P.tiles_full.push_back(TileDesc{g, (ti << 16) | tj});
+        }
+        xcd_order(P, 0, ng, P.tiles_full);
+    } else {
+        std::vector<int64_t> cnt((size_t)nw + 1, 0);
+        for (int64_t p = 0; p < c->nnzb; p++) cnt[(size_t)P.wave_of[P.scat[p].g] + 1]++;
+        for (int32_t w = 0; w < nw; w++) cnt[w + 1] += cnt[w];
+        P.plist_beg = cnt;
+        P.plist.assign((size_t)c->nnzb, 0);
+        for (int64_t p = 0; p < c->nnzb; p++) P.plist[(size_t)cnt[(size_t)P.wave_of[P.scat[p].g]]++] = p;
+    }
     return SMX_OK;
 }
 
@@ -309,13 +404,35 @@ int32_t build_plan(smx_ctx c)
 int32_t check_plan(smx_ctx c)
 {
     const Plan &P = c->plan;
-    for (const TileDesc &t : P.tiles) {
-        if (t.x == -1) continue;    // idle slot of the XCD-aware launch order
-        if (t.x < 0 || t.x >= P.ngroups) return fail(c, SMX_E_INVALID, "internal: tile group");
-        const GroupDesc &d = P.gd[t.x];
-        const int ti = t.y >> 16, tj = t.y & 0xffff;
-        if (tj > ti || ti * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
+    const int32_t nw = P.nwaves();
+    if (nw < 1 || P.wave_g[0] != 0 || P.wave_g[nw] != P.ngroups || (int32_t)P.tile_beg.size() != nw + 1 ||
+        (int32_t)P.chunk_beg.size() != nw + 1 || P.tile_beg[nw] != (int64_t)P.tiles.size() ||
+        P.chunk_beg[nw] != (int64_t)P.chunks.size())
+        return fail(c, SMX_E_INVALID, "internal: wave tables");
+    for (int32_t w = 0; w < nw; w++) {
+        if (P.wave_g[w + 1] <= P.wave_g[w]) return fail(c, SMX_E_INVALID, "internal: empty wave");
+        for (int64_t q = P.tile_beg[w]; q < P.tile_beg[w + 1]; q++) {
+            const TileDesc &t = P.tiles[(size_t)q];
+            if (t.x == -1) continue;    // idle slot of the XCD-aware launch order
+            if (t.x < P.wave_g[w] || t.x >= P.wave_g[w + 1]) return fail(c, SMX_E_INVALID, "internal: tile group");
+            const GroupDesc &d = P.gd[t.x];
+            const int ti = t.y >> 16, tj = t.y & 0xffff;
+            if (tj > ti || ti * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
+        }
+        for (int64_t q = P.chunk_beg[w]; q < P.chunk_beg[w + 1]; q++) {
+            const int2 &ch = P.chunks[(size_t)q];
+            if (ch.x < P.wave_g[w] || ch.x >= P.wave_g[w + 1] || ch.y < 0 || ch.y >= P.gd[ch.x].npad)
+                return fail(c, SMX_E_INVALID, "internal: gather chunk");
+        }
+        if (nw > 1)
+            for (int64_t q = P.plist_beg[w]; q < P.plist_beg[w + 1]; q++) {
+                const int64_t p = P.plist[(size_t)q];
+                if (p < 0 || p >= c->nnzb || P.wave_of[P.scat[p].g] != w)
+                    return fail(c, SMX_E_INVALID, "internal: scatter list");
+            }
     }
+    if (nw > 1 && (P.plist_beg[nw] != c->nnzb || !P.tiles_full.empty()))
+        return fail(c, SMX_E_INVALID, "internal: scatter list");
     for (const TileDesc &t : P.tiles_full) {
         if (t.x == -1) continue;
         if (t.x < 0 || t.x >= P.ngroups) return fail(c, SMX_E_INVALID, "internal: tile group");
@@ -324,7 +441,7 @@ int32_t check_plan(smx_ctx c)
         if (ti * kTile >= d.npad || tj * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
     }
     for (const GroupDesc &d : P.gd) {
-        if (d.npad % 16 || d.npad < d.n || d.off + (int64_t)d.npad * d.npad > P.work_elems)
+        if (d.npad % 16 || d.npad < d.n || d.off < 0 || d.off + (int64_t)d.npad * d.npad > P.work_elems)
             return fail(c, SMX_E_INVALID, "internal: group extent");
         if (d.rinfo_off + d.npad > (int64_t)P.rinfo.size() ||
             d.map_off + (int64_t)d.m * d.m > (int64_t)P.bmap.size() ||
@@ -342,7 +459,8 @@ int32_t check_plan(smx_ctx c)
             return fail(c, SMX_E_INVALID, "internal: scatter extent");
     }
     for (const GroupDesc &d : P.gd) {
-        if (d.own_off + d.m_own > (int64_t)P.own_list.size() || d.thin_off + (int64_t)d.npad * d.m_own > P.thin_elems)
+        if (d.own_off + d.m_own > (int64_t)P.own_list.size() || d.thin_off < 0 ||
+            d.thin_off + (int64_t)d.npad * d.m_own > P.thin_elems)
             return fail(c, SMX_E_INVALID, "internal: own-column tables");
         for (int32_t q = 0; q < d.m_own; q++)
             if (P.own_list[d.own_off + q] < 0 || P.own_list[d.own_off + q] >= d.n)
@@ -351,28 +469,51 @@ int32_t check_plan(smx_ctx c)
     return SMX_OK;
 }
 
+template <typename T>
+size_t vbytes(const std::vector<T> &v) { return v.size() * sizeof(T); }
+
 int32_t ensure_plan(smx_ctx c)
 {
     if (!c->plan_dirty) return SMX_OK;
     int32_t st = build_plan(c);
     if (st) return st;
+    Plan &P = c->plan;
+    // work space: release what depends on the plan, then size the waves to
+    // the limit set by smx_set_workspace_limit or to the free device memory
+    // left after the plan's tables (with 1 GiB held back, and no more than
+    // 3/4 of the device)
+    c->d_arena.release();
+    c->d_t0.release();
+    c->d_t1.release();
+    c->d_t2.release();
+    c->d_tx0.release();
+    c->d_tx1.release();
+    c->d_adj.release();
+    int64_t budget = c->ws_limit;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(c, hipMemGetInfo(&fr, &tot));
+        int64_t tiles_est = 0;
+        for (const GroupDesc &d : P.gd) {
+            const int64_t nt = (d.npad + kTile - 1) / kTile;
+            tiles_est += nt * nt;
+        }
+        const int64_t tables = (int64_t)(vbytes(P.gd) + vbytes(P.chunks) + vbytes(P.rinfo) + vbytes(P.bmap) +
+                                         vbytes(P.boffs) + vbytes(P.scat) + vbytes(P.own_list)) +
+                               (int64_t)sizeof(TileDesc) * 2 * tiles_est + 8 * c->nnzb + 64 * (int64_t)P.ngroups;
+        // at most 3/4 of the device in one allocation
+        budget = std::min<int64_t>((int64_t)fr - tables - (int64_t)(1ll << 30), (int64_t)(tot / 4 * 3));
+        if (budget <= 0) return fail(c, SMX_E_NOMEM, "no device memory left for the submatrix work space");
+    }
+    st = partition_waves(c, budget);
+    if (st) return st;
     st = check_plan(c);
     if (st) return st;
-    const Plan &P = c->plan;
-    // device memory: three group buffers + tables
-    size_t need = 3 * (size_t)P.work_elems * sizeof(double);
-    size_t fr = 0, tot = 0;
-    HIP_TRY(c, hipMemGetInfo(&fr, &tot));
-    const size_t have = fr + c->d_x0.bytes() + c->d_x1.bytes() + c->d_w.bytes();
-    if (need + (64u << 20) > have)
-        return fail(c, SMX_E_NOMEM, "submatrix buffers need " + std::to_string(need >> 20) +
-                                        " MiB, device has " + std::to_string(have >> 20) + " MiB free");
-    HIP_TRY(c, c->d_x0.ensure((size_t)P.work_elems));
-    HIP_TRY(c, c->d_x1.ensure((size_t)P.work_elems));
-    HIP_TRY(c, c->d_w.ensure((size_t)P.work_elems));
+    HIP_TRY(c, c->d_arena.ensure((size_t)(3 * P.work_elems)));
     HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
     HIP_TRY(c, upload(c->d_tiles_full, P.tiles_full, c->stream));
+    HIP_TRY(c, upload(c->d_plist, P.plist, c->stream));
     c->contrib_ready = false;
     HIP_TRY(c, upload(c->d_chunks, P.chunks, c->stream));
     HIP_TRY(c, upload(c->d_rinfo, P.rinfo, c->stream));
@@ -461,8 +602,6 @@ int32_t smx_create(int32_t device, smx_ctx *out)
     c->device = device;
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_t0);
-    if (e == hipSuccess) e = hipEventCreate(&c->ev_t1);
-    if (e == hipSuccess) e = hipEventCreate(&c->ev_t2);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_t3);
     if (e != hipSuccess) {
         g_create_err = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
@@ -478,8 +617,9 @@ int32_t smx_destroy(smx_ctx c)
     if (!c) return SMX_E_INVALID;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (auto *b : {&c->d_k, &c->d_d, &c->d_x0, &c->d_x1, &c->d_w, &c->d_pe, &c->d_pn, &c->d_ne, &c->d_check})
+    for (auto *b : {&c->d_k, &c->d_d, &c->d_arena, &c->d_pe, &c->d_pn, &c->d_ne, &c->d_check})
         b->release();
+    c->d_plist.release();
     c->d_valoff.release();
     c->d_mirror.release();
     c->d_brow.release();
@@ -513,16 +653,14 @@ int32_t smx_destroy(smx_ctx c)
     c->d_adj.release();
     c->d_dk.release();
     c->d_dmu.release();
-    c->d_wx0.release();
-    c->d_wx1.release();
-    c->d_ww.release();
     c->d_t0.release();
     c->d_t1.release();
     c->d_t2.release();
     if (c->h_ndone) (void)hipHostFree(c->h_ndone);
     for (hipEvent_t ev : c->ev_poll) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->ev_launch) (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : {c->ev_t0, c->ev_t1, c->ev_t2, c->ev_t3})
+    for (hipEvent_t ev : c->ev_wave) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : {c->ev_t0, c->ev_t3})
         if (ev) (void)hipEventDestroy(ev);
     delete c;
     return SMX_OK;
@@ -685,6 +823,18 @@ int32_t smx_set_convergence(smx_ctx c, double tol, int32_t max_iter, int32_t n_p
     return SMX_OK;
 }
 
+int32_t smx_set_workspace_limit(smx_ctx c, int64_t bytes)
+{
+    if (!c) return SMX_E_INVALID;
+    if (bytes < 0) return fail(c, SMX_E_INVALID, "bytes must be >= 0");
+    c->ws_limit = bytes;
+    c->plan_dirty = true;
+    c->evaluated = false;
+    c->use_kfix = c->use_sfix = false;
+    c->contrib_ready = false;
+    return SMX_OK;
+}
+
 int32_t smx_evaluate(smx_ctx c)
 {
     if (!c) return SMX_E_INVALID;
@@ -726,14 +876,19 @@ int32_t smx_evaluate(smx_ctx c)
         c->ev_poll.push_back(ev);
     }
     if (mixed) {
-        const size_t words = (size_t)nw * (size_t)P.work_elems;
-        HIP_TRY(c, c->d_wx0.ensure(words));
-        HIP_TRY(c, c->d_wx1.ensure(words));
-        HIP_TRY(c, c->d_ww.ensure(words));
         const size_t thin = (size_t)std::max<int64_t>(P.thin_elems, 1);
         HIP_TRY(c, c->d_t0.ensure(thin));
         HIP_TRY(c, c->d_t1.ensure(thin));
         HIP_TRY(c, c->d_t2.ensure(thin));
+        // word planes from byte 8E to 8E + 6 nw E of the arena
+        const size_t need = (size_t)((8 * P.work_elems + 6 * (int64_t)nw * P.work_elems + 7) / 8);
+        if (c->d_arena.cap < need) HIP_TRY(c, c->d_arena.ensure(need));
+    }
+    const int32_t nwave = P.nwaves();
+    while ((int32_t)c->ev_wave.size() < 4 * nwave) {
+        hipEvent_t ev;
+        HIP_TRY(c, hipEventCreate(&ev));
+        c->ev_wave.push_back(ev);
     }
     hipStream_t st = c->stream;
     IterState it;
@@ -769,18 +924,11 @@ int32_t smx_evaluate(smx_ctx c)
     HIP_TRY(c, hipMemsetAsync(it.done, 0, sizeof(int32_t) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.kfinal, 0, sizeof(int32_t) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.flags, 0, sizeof(int32_t) * ng, st));
-    HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
-    HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_x0.p, gather_scale));
-    if (tangent) HIP_TRY(c, launch_tangent_init(st, ng, P.max_npad, c->d_gd.p, it.scale_bits, c->d_tx0.p));
-    const int64_t plane = P.work_elems;
-    if (mixed)
-        HIP_TRY(c, launch_to_words(st, fmt, nw, ng, P.max_npad, c->d_gd.p, c->d_x0.p, it.scale_bits, c->d_wx0.p,
-                                   plane));
-    HIP_TRY(c, hipEventRecord(c->ev_t1, st));
 
     c->launch_step.clear();
     c->launch_kind.clear();
+    c->launch_wave.clear();
+    int32_t wave = 0;
     auto timed = [&](int kind, int k, auto &&launch) -> hipError_t {
         const size_t idx = c->launch_step.size();
         while (c->ev_launch.size() < 2 * (idx + 1)) {
@@ -794,70 +942,90 @@ int32_t smx_evaluate(smx_ctx c)
         if (e == hipSuccess) e = hipEventRecord(c->ev_launch[2 * idx + 1], st);
         c->launch_step.push_back(k);
         c->launch_kind.push_back(kind);
+        c->launch_wave.push_back(wave);
         return e;
     };
-    const int ntiles = (int)P.tiles.size();
-    // bulk steps: every group iterates until its own stopping rule; the host
-    // polls the finished-group counter one step behind the device
+    const int64_t plane = P.work_elems;
+    double *xb[2] = {slab(c, 0), slab(c, 1)};
+    double *wslab = slab(c, 2);
+    unsigned short *wbase = reinterpret_cast<unsigned short *>(slab(c, 1));
+    unsigned short *wb[2] = {wbase, wbase + (size_t)nw * plane};
+    unsigned short *wwp = wbase + (size_t)2 * nw * plane;
+    double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
     const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
-    double *xb[2] = {c->d_x0.p, c->d_x1.p};
-    unsigned short *wb[2] = {c->d_wx0.p, c->d_wx1.p};
     int32_t launched = 0;
-    for (int32_t k = 0; k <= kmax; k++) {
-        if (!mixed) {
-            HIP_TRY(c, timed(0, k, [&] { return launch_ns_f64(st, 0, ntiles, c->d_tiles.p, c->d_gd.p, xb[k & 1], xb[k & 1],
-                                                              c->d_w.p, it, k, c->tol, c->max_iter, 0); }));
-            HIP_TRY(c, timed(1, k, [&] { return launch_ns_f64(st, 1, ntiles, c->d_tiles.p, c->d_gd.p, xb[k & 1], c->d_w.p,
-                                                              xb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
-            if (tangent) {
-                double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
-                HIP_TRY(c, timed(6, k, [&] { return launch_ns_f64(st, 2, ntiles, c->d_tiles.p, c->d_gd.p, tb[k & 1],
-                                                                  c->d_w.p, tb[(k + 1) & 1], it, k, c->tol,
-                                                                  c->max_iter, 0); }));
+    // waves run one after the other through the same arena; every group's
+    // arithmetic is independent of the wave it falls in
+    for (wave = 0; wave < nwave; wave++) {
+        const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
+        const int ntiles = (int)(P.tile_beg[wave + 1] - P.tile_beg[wave]);
+        const TileDesc *tl = c->d_tiles.p + P.tile_beg[wave];
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
+        HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
+        HIP_TRY(c, launch_gather(st, (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]), c->d_chunks.p + P.chunk_beg[wave],
+                                 c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu,
+                                 xb[0], gather_scale));
+        if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, c->d_gd.p, it.scale_bits, tb[0]));
+        if (mixed)
+            HIP_TRY(c, launch_to_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, xb[0], it.scale_bits, wb[0], plane));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
+        // bulk steps: every group iterates until its own stopping rule; the
+        // host polls the wave's finished-group counter one step behind the device
+        for (int32_t k = 0; k <= kmax; k++) {
+            if (!mixed) {
+                HIP_TRY(c, timed(0, k, [&] { return launch_ns_f64(st, 0, ntiles, tl, c->d_gd.p, xb[k & 1], xb[k & 1],
+                                                                  wslab, it, k, c->tol, c->max_iter, 0); }));
+                HIP_TRY(c, timed(1, k, [&] { return launch_ns_f64(st, 1, ntiles, tl, c->d_gd.p, xb[k & 1], wslab,
+                                                                  xb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
+                if (tangent)
+                    HIP_TRY(c, timed(6, k, [&] { return launch_ns_f64(st, 2, ntiles, tl, c->d_gd.p, tb[k & 1], wslab,
+                                                                      tb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
+            } else {
+                HIP_TRY(c, timed(2, k, [&] { return launch_ns_words(st, fmt, nw, 0, ntiles, tl, c->d_gd.p, wb[k & 1],
+                                                                    wb[k & 1], wwp, plane, it, k, c->switch_tol, kmax); }));
+                HIP_TRY(c, timed(3, k, [&] { return launch_ns_words(st, fmt, nw, 1, ntiles, tl, c->d_gd.p, wb[k & 1],
+                                                                    wwp, wb[(k + 1) & 1], plane, it, k, c->switch_tol,
+                                                                    kmax); }));
             }
-        } else {
-            HIP_TRY(c, timed(2, k, [&] { return launch_ns_words(st, fmt, nw, 0, ntiles, c->d_tiles.p, c->d_gd.p, wb[k & 1],
-                                                                wb[k & 1], c->d_ww.p, plane, it, k, c->switch_tol, kmax); }));
-            HIP_TRY(c, timed(3, k, [&] { return launch_ns_words(st, fmt, nw, 1, ntiles, c->d_tiles.p, c->d_gd.p, wb[k & 1],
-                                                                c->d_ww.p, wb[(k + 1) & 1], plane, it, k, c->switch_tol,
-                                                                kmax); }));
+            launched = std::max(launched, k + 1);
+            HIP_TRY(c, hipMemcpyAsync(c->h_ndone + k, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipEventRecord(c->ev_poll[k], st));
+            if (k >= 1) {
+                HIP_TRY(c, hipEventSynchronize(c->ev_poll[k - 1]));
+                if (c->h_ndone[k - 1] >= wng) break;
+            }
         }
-        launched = k + 1;
-        HIP_TRY(c, hipMemcpyAsync(c->h_ndone + k, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipEventRecord(c->ev_poll[k], st));
-        if (k >= 1) {
-            HIP_TRY(c, hipEventSynchronize(c->ev_poll[k - 1]));
-            if (c->h_ndone[k - 1] >= ng) break;
+        if (mixed) {
+            // FP64 polish: n_polish - 1 full steps, then the last step on the own columns only
+            HIP_TRY(c, launch_from_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, wb[0], wb[1], it.kfinal, plane,
+                                         xb[0]));
+            int cur = 0;
+            for (int32_t q = 0; q + 1 < c->n_polish; q++) {
+                const int slot = c->max_iter + 1 + q;
+                HIP_TRY(c, timed(4, slot, [&] { return launch_ns_f64(st, 0, ntiles, tl, c->d_gd.p, xb[cur], xb[cur],
+                                                                     wslab, it, slot, c->tol, c->max_iter, 1); }));
+                HIP_TRY(c, timed(5, slot, [&] { return launch_ns_f64(st, 1, ntiles, tl, c->d_gd.p, xb[cur], wslab,
+                                                                     xb[cur ^ 1], it, slot, c->tol, c->max_iter, 1); }));
+                cur ^= 1;
+            }
+            HIP_TRY(c, launch_own_polish(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, xb[cur], c->d_t0.p,
+                                         c->d_t1.p, c->d_t2.p, it, c->max_iter + c->n_polish));
         }
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
+        const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
+        const int64_t *pl = nwave > 1 ? c->d_plist.p + P.plist_beg[wave] : nullptr;
+        if (mixed)
+            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_t2.p, nullptr, it,
+                                      c->d_k.p, c->d_d.p, c->d_pe.p, c->d_pn.p, 1));
+        else
+            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, xb[0], xb[1], it, c->d_k.p,
+                                      c->d_d.p, c->d_pe.p, c->d_pn.p, 0));
+        if (tangent)
+            HIP_TRY(c, launch_own_trace(st, g0, wng, c->d_gd.p, c->d_own.p, tb[0], tb[1], it.kfinal, c->d_dnp.p));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
     }
-    if (mixed) {
-        // FP64 polish: n_polish - 1 full steps, then the last step on the own columns only
-        HIP_TRY(c, launch_from_words(st, fmt, nw, ng, P.max_npad, c->d_gd.p, c->d_wx0.p, c->d_wx1.p, it.kfinal, plane,
-                                     c->d_x0.p));
-        int cur = 0;
-        for (int32_t q = 0; q + 1 < c->n_polish; q++) {
-            const int slot = c->max_iter + 1 + q;
-            HIP_TRY(c, timed(4, slot, [&] { return launch_ns_f64(st, 0, ntiles, c->d_tiles.p, c->d_gd.p, xb[cur], xb[cur],
-                                                                 c->d_w.p, it, slot, c->tol, c->max_iter, 1); }));
-            HIP_TRY(c, timed(5, slot, [&] { return launch_ns_f64(st, 1, ntiles, c->d_tiles.p, c->d_gd.p, xb[cur], c->d_w.p,
-                                                                 xb[cur ^ 1], it, slot, c->tol, c->max_iter, 1); }));
-            cur ^= 1;
-        }
-        HIP_TRY(c, launch_own_polish(st, ng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, xb[cur], c->d_t0.p,
-                                     c->d_t1.p, c->d_t2.p, it, c->max_iter + c->n_polish));
-    }
-    HIP_TRY(c, hipEventRecord(c->ev_t2, st));
-    if (mixed)
-        HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_t2.p, nullptr, it, c->d_k.p,
-                                  c->d_d.p, c->d_pe.p, c->d_pn.p, 1));
-    else
-        HIP_TRY(c, launch_scatter(st, c->nnzb, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_x0.p, c->d_x1.p, it, c->d_k.p,
-                                  c->d_d.p, c->d_pe.p, c->d_pn.p, 0));
     HIP_TRY(c, launch_reduce(st, c->nnzb, c->d_pe.p, c->d_pn.p, c->d_ne.p));
-    if (tangent) {
-        HIP_TRY(c, launch_own_trace(st, ng, c->d_gd.p, c->d_own.p, c->d_tx0.p, c->d_tx1.p, it.kfinal, c->d_dnp.p));
-        HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dn.p));
-    }
+    if (tangent) HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dn.p));
     c->have_tangent = tangent;
     c->last_sfix = c->use_sfix;
     HIP_TRY(c, hipEventRecord(c->ev_t3, st));
@@ -1003,18 +1171,28 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
         }
     }
     s.exec_flops = exec;
+    // phase times summed over the waves (the first wave's start includes the
+    // state clears, the final reductions count as scatter)
+    const int32_t nwave = c->plan.nwaves();
+    s.nwaves = nwave;
     float ms = 0;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
-    s.time_gather_ms = ms;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t1, c->ev_t2));
-    s.time_iterate_ms = ms;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t2, c->ev_t3));
-    s.time_scatter_ms = ms;
+    for (int32_t w = 0; w < nwave; w++) {
+        HIP_TRY(c, hipEventElapsedTime(&ms, w ? c->ev_wave[4 * w] : c->ev_t0, c->ev_wave[4 * w + 1]));
+        s.time_gather_ms += ms;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_wave[4 * w + 1], c->ev_wave[4 * w + 2]));
+        s.time_iterate_ms += ms;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_wave[4 * w + 2], c->ev_wave[4 * w + 3]));
+        s.time_scatter_ms += ms;
+    }
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_wave[4 * (nwave - 1) + 3], c->ev_t3));
+    s.time_scatter_ms += ms;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t0, c->ev_t3));
     s.time_total_ms = ms;
     double ws = 0;
-    for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_x0.bytes(), c->d_x1.bytes(), c->d_w.bytes(),
-                     c->d_bmap.bytes(), c->d_rinfo.bytes(), c->d_scat.bytes(), c->d_resid.bytes()})
+    for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_arena.bytes(), c->d_t0.bytes(), c->d_t1.bytes(),
+                     c->d_t2.bytes(), c->d_tx0.bytes(), c->d_tx1.bytes(), c->d_adj.bytes(), c->d_bmap.bytes(),
+                     c->d_rinfo.bytes(), c->d_scat.bytes(), c->d_resid.bytes(), c->d_tiles.bytes(),
+                     c->d_tiles_full.bytes(), c->d_plist.bytes()})
         ws += (double)b;
     s.workspace_bytes = ws;
     *out = s;
@@ -1039,9 +1217,9 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
             ms[l] = t;
         }
         if (algo_flops) {
-            const int32_t k = c->launch_step[l];
+            const int32_t k = c->launch_step[l], w = c->launch_wave[l];
             double f = 0;
-            for (int32_t g = 0; g < c->plan.ngroups; g++) {
+            for (int32_t g = c->plan.wave_g[w]; g < c->plan.wave_g[w + 1]; g++) {
                 bool active = true;                           // polish launches work on every group
                 if (kd == 0 || kd == 2) active = k <= kf[g];  // squares run up to the last step
                 if (kd == 1 || kd == 3 || kd == 6) active = k < kf[g];   // updates (and tangents) stop one earlier
@@ -1068,6 +1246,9 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
     if (n_out) *n_out = d.n;
     if (!out) return SMX_OK;
     if (ld < d.n) return fail(c, SMX_E_INVALID, "ld < n_g");
+    if (what == 1 && P.wave_of[g] != P.nwaves() - 1)
+        return fail(c, SMX_E_UNSUPPORTED, "the iterates of group " + std::to_string(g) +
+                                              " were overwritten by a later wave (only the last wave's are kept)");
     const double *src = nullptr;
     double a = 1.0;
     if (what == 0) {
@@ -1080,16 +1261,16 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         HIP_TRY(c, c->d_check.ensure((size_t)std::max(P.ngroups, 2)));
         HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, sizeof(double) * std::max(P.ngroups, 2), c->stream));
         HIP_TRY(c, launch_gather(c->stream, (int)ch.size(), dch.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                                 c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, c->d_w.p,
+                                 c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, slab(c, 2),
                                  reinterpret_cast<unsigned long long *>(c->d_check.p)));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dch.release();
-        src = c->d_w.p + d.off;
+        src = slab(c, 2) + d.off;
     } else if (c->last_polish) {
         // reduced-precision modes: the last full FP64 iterate (the final step
         // is computed on the own columns only)
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        src = (((c->last_polish - 1) & 1) ? c->d_x1.p : c->d_x0.p) + d.off;
+        src = slab(c, (c->last_polish - 1) & 1) + d.off;
     } else {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         int32_t kf = 0;
@@ -1101,7 +1282,7 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
             std::memcpy(&s, &sb, sizeof s);
             a = s > 0 ? 1.0 / s : 0.0;
         }
-        src = ((kf & 1) ? c->d_x1.p : c->d_x0.p) + d.off;
+        src = slab(c, kf & 1) + d.off;
     }
     std::vector<double> tmp((size_t)d.npad * d.npad);
     HIP_TRY(c, hipMemcpy(tmp.data(), src, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1185,8 +1366,10 @@ static int32_t scales_at(smx_ctx c, double mu, std::vector<double> &out)
     const int32_t ng = P.ngroups;
     HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_scale_scratch.p, 0, sizeof(unsigned long long) * ng, c->stream));
-    HIP_TRY(c, launch_gather(c->stream, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, mu, c->d_w.p, c->d_scale_scratch.p));
+    for (int32_t w = 0; w < P.nwaves(); w++)
+        HIP_TRY(c, launch_gather(c->stream, (int)(P.chunk_beg[w + 1] - P.chunk_beg[w]), c->d_chunks.p + P.chunk_beg[w],
+                                 c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p, c->d_valoff.p, c->d_k.p, mu,
+                                 slab(c, 2), c->d_scale_scratch.p));
     std::vector<unsigned long long> b((size_t)ng);
     HIP_TRY(c, hipMemcpyAsync(b.data(), c->d_scale_scratch.p, b.size() * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, c->stream));
@@ -1311,6 +1494,9 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
     if (int32_t st = need_sync_results(c)) return st;
     if (int32_t st = set_device(c)) return st;
+    if (c->plan.nwaves() != 1)
+        return fail(c, SMX_E_UNSUPPORTED, "the adjoint needs every submatrix resident at once (one wave); "
+                                          "raise the work-space limit");
     if (int32_t st = ensure_contrib(c)) return st;
     const Plan &P = c->plan;
     const int32_t ng = P.ngroups;

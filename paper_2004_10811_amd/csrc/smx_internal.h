@@ -107,22 +107,24 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                            unsigned short *out, int64_t plane, const IterState &it, int k, double switch_tol,
                            int kmax);
-hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+// Group-walking launchers take the first group g0 and the count ngroups (a wave).
+hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                            const double *src, const unsigned long long *scale_bits, unsigned short *dst,
                            int64_t plane);
-hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                              const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal,
                              int64_t plane, double *dst);
 
 // Last polish step restricted to the own columns (FP64, vector ALU):
 //   O = P[:, own];  Y = P O (residual of P^2 on the own columns -> slot);  F = 1.5 O - 0.5 P Y.
-hipError_t launch_own_polish(hipStream_t st, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
+hipError_t launch_own_polish(hipStream_t st, int g0, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
                              const int32_t *own_list, const double *p, double *o, double *y, double *f,
                              const IterState &it, int slot);
 
 // from_thin = 0: S_g = a X_kfinal (full matrices x0 / x1 by step parity);
 // from_thin = 1: S_g own columns from the npad x m_own buffer x0.
-hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd,
+// plist (nullable): the stored-block positions to scatter (one wave's own columns).
+hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const int64_t *plist, const ScatterDesc *sd,
                           const int64_t *valoff, const GroupDesc *groups, const double *x0,
                           const double *x1, const IterState &it, const double *kvals,
                           double *dvals, double *part_e, double *part_n, int from_thin);
@@ -132,11 +134,11 @@ hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const 
 
 // Xd_0 = -a I on the true n_g x n_g block (a = 1/s_g), zero elsewhere: the mu tangent
 // of X_0 = (K_sub - mu I) / s_g with s_g frozen.
-hipError_t launch_tangent_init(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups,
+hipError_t launch_tangent_init(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                                const unsigned long long *scale_bits, double *xd);
 
 // part[g] = sum over the own columns c of Xd_{kfinal}[c, c] (Xd in xd0 / xd1 by step parity).
-hipError_t launch_own_trace(hipStream_t st, int ngroups, const GroupDesc *groups, const int32_t *own_list,
+hipError_t launch_own_trace(hipStream_t st, int g0, int ngroups, const GroupDesc *groups, const int32_t *own_list,
                             const double *xd0, const double *xd1, const int32_t *kfinal, double *part);
 
 hipError_t launch_check_values(hipStream_t st, int64_t nblocks, const int64_t *valoff,

@@ -90,16 +90,17 @@ void gather_shift_kernel(const int2 *__restrict__ chunks, const GroupDesc *__res
 // ---------------------------------------------------------------------------
 template <int FROM_THIN>
 __global__ __launch_bounds__(256)
-void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
+void scatter_kernel(int64_t nblocks, const int64_t *__restrict__ plist, const ScatterDesc *__restrict__ sd,
                     const int64_t *__restrict__ valoff, const GroupDesc *__restrict__ groups,
                     const double *__restrict__ x0, const double *__restrict__ x1,
                     const int32_t *__restrict__ kfinal, const unsigned long long *__restrict__ scale_bits,
                     const double *__restrict__ kvals, double *__restrict__ dvals,
                     double *__restrict__ part_e, double *__restrict__ part_n)
 {
-    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (p >= nblocks) return;
+    if (i >= nblocks) return;
+    const int64_t p = plist ? plist[i] : i;
     const ScatterDesc d = sd[p];
     const GroupDesc gd = groups[d.g];
     const double *xs;
@@ -147,9 +148,9 @@ void scatter_kernel(int64_t nblocks, const ScatterDesc *__restrict__ sd,
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256)
 void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
-                       const double *__restrict__ p, double *__restrict__ o)
+                       const double *__restrict__ p, double *__restrict__ o, int g0)
 {
-    const GroupDesc gd = groups[blockIdx.y];
+    const GroupDesc gd = groups[g0 + blockIdx.y];
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= gd.npad) return;
     for (int c = 0; c < gd.m_own; c++)
@@ -161,10 +162,10 @@ template <int MODE>
 __global__ __launch_bounds__(256)
 void thin_mul_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
                      const double *__restrict__ p, const double *__restrict__ b, const double *__restrict__ o,
-                     double *__restrict__ y, IterState it, int slot)
+                     double *__restrict__ y, IterState it, int slot, int g0)
 {
     __shared__ double bs[64][33];
-    const int g = blockIdx.y;
+    const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (blockIdx.x * 256 >= gd.npad) return;          // whole block beyond this group
@@ -289,11 +290,11 @@ void check_values_kernel(int64_t nblocks, const int64_t *__restrict__ valoff,
 // Xd_0 = -a I on the true block (a = 1/s_g), one group per blockIdx.y.
 __global__ __launch_bounds__(256)
 void tangent_init_kernel(const GroupDesc *__restrict__ groups, const unsigned long long *__restrict__ scale_bits,
-                         double *__restrict__ xd)
+                         double *__restrict__ xd, int g0)
 {
-    const GroupDesc gd = groups[blockIdx.y];
+    const GroupDesc gd = groups[g0 + blockIdx.y];
     const int64_t tot = (int64_t)gd.npad * gd.npad;
-    const double s = __longlong_as_double((long long)scale_bits[blockIdx.y]);
+    const double s = __longlong_as_double((long long)scale_bits[g0 + blockIdx.y]);
     const double a = s > 0.0 ? 1.0 / s : 0.0;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
         const int64_t r = e % gd.npad, c = e / gd.npad;
@@ -305,9 +306,9 @@ void tangent_init_kernel(const GroupDesc *__restrict__ groups, const unsigned lo
 __global__ __launch_bounds__(64)
 void own_trace_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
                       const double *__restrict__ xd0, const double *__restrict__ xd1,
-                      const int32_t *__restrict__ kfinal, double *__restrict__ part)
+                      const int32_t *__restrict__ kfinal, double *__restrict__ part, int g0)
 {
-    const int g = blockIdx.x;
+    const int g = g0 + blockIdx.x;
     const GroupDesc gd = groups[g];
     const double *xd = ((kfinal[g] & 1) ? xd1 : xd0) + gd.off;
     double acc = 0.0;
@@ -321,21 +322,21 @@ void own_trace_kernel(const GroupDesc *__restrict__ groups, const int32_t *__res
 
 }  // namespace
 
-hipError_t launch_tangent_init(hipStream_t st, int ngroups, int max_npad, const GroupDesc *groups,
+hipError_t launch_tangent_init(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                                const unsigned long long *scale_bits, double *xd)
 {
     if (ngroups <= 0) return hipSuccess;
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-    hipLaunchKernelGGL(tangent_init_kernel, grid, dim3(256), 0, st, groups, scale_bits, xd);
+    hipLaunchKernelGGL(tangent_init_kernel, grid, dim3(256), 0, st, groups, scale_bits, xd, g0);
     return hipGetLastError();
 }
 
-hipError_t launch_own_trace(hipStream_t st, int ngroups, const GroupDesc *groups, const int32_t *own_list,
+hipError_t launch_own_trace(hipStream_t st, int g0, int ngroups, const GroupDesc *groups, const int32_t *own_list,
                             const double *xd0, const double *xd1, const int32_t *kfinal, double *part)
 {
     if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(own_trace_kernel, dim3(ngroups), dim3(64), 0, st, groups, own_list, xd0, xd1, kfinal, part);
+    hipLaunchKernelGGL(own_trace_kernel, dim3(ngroups), dim3(64), 0, st, groups, own_list, xd0, xd1, kfinal, part, g0);
     return hipGetLastError();
 }
 
@@ -350,7 +351,7 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd,
+hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const int64_t *plist, const ScatterDesc *sd,
                           const int64_t *valoff, const GroupDesc *groups, const double *x0,
                           const double *x1, const IterState &it, const double *kvals,
                           double *dvals, double *part_e, double *part_n, int from_thin)
@@ -358,23 +359,23 @@ hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const ScatterDesc *sd
     if (nblocks <= 0) return hipSuccess;
     const int64_t grid = (nblocks + 3) / 4;
     if (from_thin)
-        hipLaunchKernelGGL(scatter_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
+        hipLaunchKernelGGL(scatter_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, plist, sd, valoff,
                            groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
     else
-        hipLaunchKernelGGL(scatter_kernel<0>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, sd, valoff,
+        hipLaunchKernelGGL(scatter_kernel<0>, dim3((unsigned)grid), dim3(256), 0, st, nblocks, plist, sd, valoff,
                            groups, x0, x1, it.kfinal, it.scale_bits, kvals, dvals, part_e, part_n);
     return hipGetLastError();
 }
 
-hipError_t launch_own_polish(hipStream_t st, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
+hipError_t launch_own_polish(hipStream_t st, int g0, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
                              const int32_t *own_list, const double *p, double *o, double *y, double *f,
                              const IterState &it, int slot)
 {
     if (ngroups <= 0 || max_own <= 0) return hipSuccess;
     const dim3 grid((unsigned)((max_npad + 255) / 256), (unsigned)ngroups);
-    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, p, o);
-    hipLaunchKernelGGL(thin_mul_kernel<0>, grid, dim3(256), 0, st, groups, own_list, p, o, o, y, it, slot);
-    hipLaunchKernelGGL(thin_mul_kernel<1>, grid, dim3(256), 0, st, groups, own_list, p, y, o, f, it, slot);
+    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, p, o, g0);
+    hipLaunchKernelGGL(thin_mul_kernel<0>, grid, dim3(256), 0, st, groups, own_list, p, o, o, y, it, slot, g0);
+    hipLaunchKernelGGL(thin_mul_kernel<1>, grid, dim3(256), 0, st, groups, own_list, p, y, o, f, it, slot, g0);
     return hipGetLastError();
 }
 

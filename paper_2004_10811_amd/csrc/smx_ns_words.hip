@@ -408,9 +408,9 @@ template <int FMT, int NW>
 __global__ __launch_bounds__(256)
 void f64_to_words_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ src,
                          const unsigned long long *__restrict__ scale_bits, unsigned short *__restrict__ dst,
-                         int64_t plane)
+                         int64_t plane, int g0)
 {
-    const int g = blockIdx.y;
+    const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
     const int64_t tot = (int64_t)gd.npad * gd.npad;
     const double s = __longlong_as_double((long long)scale_bits[g]);
@@ -424,9 +424,9 @@ template <int FMT, int NW>
 __global__ __launch_bounds__(256)
 void words_to_f64_kernel(const GroupDesc *__restrict__ groups, const unsigned short *__restrict__ x0,
                          const unsigned short *__restrict__ x1, const int32_t *__restrict__ kfinal,
-                         int64_t plane, double *__restrict__ dst)
+                         int64_t plane, double *__restrict__ dst, int g0)
 {
-    const int g = blockIdx.y;
+    const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
     const int64_t tot = (int64_t)gd.npad * gd.npad;
     const unsigned short *src = ((kfinal[g] & 1) ? x1 : x0) + gd.off;
@@ -467,32 +467,36 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                            const double *src, const unsigned long long *scale_bits, unsigned short *dst, int64_t plane)
 {
     if (ngroups <= 0) return hipSuccess;
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-    if (fmt == 0 && nw == 1) hipLaunchKernelGGL((f64_to_words_kernel<0, 1>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane);
-    else if (fmt == 0 && nw == 2) hipLaunchKernelGGL((f64_to_words_kernel<0, 2>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane);
-    else if (fmt == 1 && nw == 1) hipLaunchKernelGGL((f64_to_words_kernel<1, 1>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane);
-    else if (fmt == 1 && nw == 3) hipLaunchKernelGGL((f64_to_words_kernel<1, 3>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane);
+#define SMX_TW(F, N) hipLaunchKernelGGL((f64_to_words_kernel<F, N>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane, g0)
+    if (fmt == 0 && nw == 1) SMX_TW(0, 1);
+    else if (fmt == 0 && nw == 2) SMX_TW(0, 2);
+    else if (fmt == 1 && nw == 1) SMX_TW(1, 1);
+    else if (fmt == 1 && nw == 3) SMX_TW(1, 3);
     else return hipErrorInvalidValue;
+#undef SMX_TW
     return hipGetLastError();
 }
 
-hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int ngroups, int max_npad, const GroupDesc *groups,
+hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                              const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal, int64_t plane,
                              double *dst)
 {
     if (ngroups <= 0) return hipSuccess;
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-    if (fmt == 0 && nw == 1) hipLaunchKernelGGL((words_to_f64_kernel<0, 1>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst);
-    else if (fmt == 0 && nw == 2) hipLaunchKernelGGL((words_to_f64_kernel<0, 2>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst);
-    else if (fmt == 1 && nw == 1) hipLaunchKernelGGL((words_to_f64_kernel<1, 1>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst);
-    else if (fmt == 1 && nw == 3) hipLaunchKernelGGL((words_to_f64_kernel<1, 3>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst);
+#define SMX_FW(F, N) hipLaunchKernelGGL((words_to_f64_kernel<F, N>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst, g0)
+    if (fmt == 0 && nw == 1) SMX_FW(0, 1);
+    else if (fmt == 0 && nw == 2) SMX_FW(0, 2);
+    else if (fmt == 1 && nw == 1) SMX_FW(1, 1);
+    else if (fmt == 1 && nw == 3) SMX_FW(1, 3);
     else return hipErrorInvalidValue;
+#undef SMX_FW
     return hipGetLastError();
 }
 
