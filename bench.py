@@ -37,7 +37,14 @@ WORKLOADS = {
                 "one submatrix per molecule",
     "water16": "16 water-like molecules (368 basis functions), periodic 7.8 A box, 4 A cutoff, "
                "one submatrix per molecule",
+    "water6912": "6912 water-like molecules (158976 basis functions), periodic 59.6 A box, 7 A cutoff, "
+                 "one submatrix per molecule, processed in memory-bounded waves",
 }
+
+
+def progress(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(system, gpu_d, stats_iters, n_g, nthreads, n_sample, seed=2024):
@@ -74,8 +81,9 @@ def run_path(smx, ctx, precision, steps, warmup, d_out):
         smx.smx_evaluate(ctx.handle)
         smx.smx_wait(ctx.handle)
 
-    for _ in range(warmup):
+    for w in range(warmup):
         step()
+        progress(f"{precision}: warm-up step {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     prof = {}
     dev_ms = []
@@ -90,6 +98,8 @@ def run_path(smx, ctx, precision, steps, warmup, d_out):
             e[1] += f
             e[2] += 1
         dev_ms.append(ctx.stats()["time_total_ms"])
+        if dev_ms[-1] > 2000:
+            progress(f"{precision}: timed step {len(dev_ms)}/{steps} done ({dev_ms[-1]:.0f} ms)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stats = ctx.stats()
@@ -142,6 +152,7 @@ def main():
     from waterbox import water_config
 
     system = water_config(args.workload)
+    progress(f"{args.workload}: {system.n} basis functions, {system.ngroups} submatrices generated")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = smx.Context(0, stream=stream.cuda_stream).load(system)
@@ -205,6 +216,7 @@ def main():
                                       int(stats["iters_max"])],
             "fp64_ns_steps_mean": round(r64["stats"]["iters_mean"], 2),
             "tol": 1e-12,
+            "waves": int(stats["nwaves"]),
         },
         "device_ms_per_D_median": float(np.median(run["dev_ms"])),
         "phase_ms": {"gather": stats["time_gather_ms"], "iterate": stats["time_iterate_ms"],
@@ -220,6 +232,7 @@ def main():
 
     if not args.no_cpu_baseline:
         nth = min(16, os.cpu_count() or 1)
+        progress(f"CPU oracle on a sample of {args.cpu_sample or nth} submatrices, {nth} threads")
         base, err, pick = cpu_baseline(system, d_out.cpu().numpy(), r64["info"]["iters"], r64["info"]["n"],
                                        nth, args.cpu_sample or nth)
         out["cpu_baseline"] = base

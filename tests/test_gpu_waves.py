@@ -119,3 +119,32 @@ def test_waves_limits_of_the_api(smx):
         smx.smx_evaluate(ctx.handle)
     assert e.value.code == smx.SMX_E_NOMEM
     ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_water6912_mixed_in_waves_sampled_groups(smx, oracle_lib):
+    """6912 molecules (158,976 basis functions): the slabs exceed one GPU's
+    memory, so the groups run in waves; sampled groups (largest, smallest,
+    and seeded random ones from different waves) match the oracle."""
+    s = water_config("water6912")
+    print(f"water6912 generated: {s.n} basis functions", flush=True)
+    ctx = smx.Context(0).load(s).configure(precision="fp16x2")
+    res = ctx.evaluate()
+    info = ctx.group_info()
+    stats = ctx.stats()
+    ctx.close()
+    print(f"water6912 evaluated in {stats['nwaves']} waves", flush=True)
+    n_g = info["n"]
+    rng = np.random.default_rng(6912)
+    pick = {int(np.argmax(n_g)), int(np.argmin(n_g)), 0, s.ngroups - 1}
+    while len(pick) < 6:
+        pick.add(int(rng.integers(s.ngroups)))
+    ref = oracle_lib.submatrix(s, which=sorted(pick), nthreads=6)
+    ok = ~np.isnan(ref.d_values)
+    err = float(np.abs(res.d_values[ok] - ref.d_values[ok]).max())
+    print(f"water6912 fp16x2: {stats['nwaves']} waves, n_g {stats['n_min']}-{stats['n_max']}, "
+          f"sampled {sorted(pick)}: max|dD| = {err:.2e}; {stats['time_total_ms']:.0f} ms")
+    assert stats["nwaves"] >= 2
+    assert stats["n_not_converged"] == 0
+    assert err <= 1e-6
+    assert np.all(np.isfinite(res.d_values))

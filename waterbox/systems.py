@@ -268,20 +268,24 @@ def _quat_to_rot(q: np.ndarray) -> np.ndarray:
     return r
 
 
-def _min_image_pairs(pos: np.ndarray, box: float, r_cut: float, chunk: int = 1024):
-    """All pairs i < j with minimum-image distance < r_cut, sorted by (j, i)."""
-    n = pos.shape[0]
-    ii, jj, dd = [], [], []
-    for j0 in range(0, n, chunk):
-        j1 = min(n, j0 + chunk)
-        delta = pos[None, :j1, :] - pos[j0:j1, None, :]      # [cj, j1, 3]: pos_i - pos_j
-        delta -= box * np.round(delta / box)
-        d = np.sqrt((delta * delta).sum(-1))
-        jl, il = np.nonzero(d < r_cut)
-        jg = jl + j0
-        keep = il < jg
-        ii.append(il[keep]); jj.append(jg[keep]); dd.append(d[jl[keep], il[keep]])
-    i = np.concatenate(ii); j = np.concatenate(jj); d = np.concatenate(dd)
+def _min_image_pairs(pos: np.ndarray, box: float, r_cut: float):
+    """All pairs i < j with minimum-image distance < r_cut, sorted by (j, i).
+
+    A periodic k-d tree proposes the candidate pairs (with a slightly larger
+    radius); the distance that decides is then computed for each candidate as
+    d = |pos_i - pos_j - box * round((pos_i - pos_j) / box)|.
+    """
+    from scipy.spatial import cKDTree
+    wrapped = np.where(pos >= box, pos - box, pos)        # mod() may round up to box
+    tree = cKDTree(wrapped, boxsize=box)
+    cand = tree.query_pairs(r_cut * (1.0 + 1e-9), output_type="ndarray")
+    i = cand[:, 0].astype(np.int64)
+    j = cand[:, 1].astype(np.int64)
+    delta = pos[i] - pos[j]
+    delta -= box * np.round(delta / box)
+    d = np.sqrt((delta * delta).sum(-1))
+    keep = d < r_cut
+    i, j, d = i[keep], j[keep], d[keep]
     order = np.lexsort((i, j))
     return i[order].astype(np.int64), j[order].astype(np.int64), d[order]
 
