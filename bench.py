@@ -114,6 +114,30 @@ DTYPES = {"fp64": "f64", "fp16x2": "f16x2 words, f32 accumulation; f64 polish",
           "bf16": "bf16 words, f32 accumulation; f64 polish"}
 PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf16", 2516.6)}
 
+# HBM bytes per launch of the dominant kernel on water1024, from two rocprofv3
+# counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the
+# figure is valid only while the kernel's sources hash to the recorded value.
+TRAFFIC = {
+    ("water1024", "ns_words_kernel"): (8.702e9, ("smx_ns_words.hip", "smx_internal.h"), "3cf0730487e0c8de",
+                                       "profiles/ns_words_kernel_water1024_fp16x2.md"),
+    ("water1024", "ns_f64_kernel"): (17.527e9, ("smx_ns_f64.hip", "smx_internal.h"), "bedb4ed27e5f1da5",
+                                     "profiles/ns_f64_kernel_water1024_fp64.md"),
+}
+
+
+def measured_traffic(workload, kernel):
+    """Counter-measured HBM bytes per launch, or None if absent or the kernel changed since."""
+    import hashlib
+    ent = TRAFFIC.get((workload, kernel))
+    if ent is None:
+        return None, None
+    nbytes, files, digest, src = ent
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2004_10811_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return (nbytes, src) if h.hexdigest()[:16] == digest else (None, None)
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -177,13 +201,16 @@ def main():
     kname, (kms, kfl, kn) = max(run["prof"].items(), key=lambda kv: kv[1][0])
     pdt, peak = PEAK_BY_KERNEL[kname]
     achieved = kfl / (kms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic(args.workload, kname)
     roofline = {
         "bound": "mfma",
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-calibrated)",
+        "traffic_source": traffic_src,
         "kernel": kname,
         "peak_dtype": pdt,
         "launches": kn,
