@@ -159,19 +159,39 @@ __device__ inline void split8(const float *v, u16x8 *wv)
     }
 }
 
-// K is staged in steps of 64 (a full 128-B line per column and word plane),
-// handed to the matrix cores in two sub-steps of 32; the next step's operands
-// are prefetched into registers while the current one is multiplied.  The
-// epilogue stages the FP32 tile in LDS (the operand buffers are reused) and
-// writes words of the tile and of its mirror with 16-B stores.
-constexpr int BK2 = 64;
-constexpr int SK2 = BK2 + 8;      // 144-B LDS rows: 16-B aligned
-constexpr int CST = BM + 4;       // FP32 staging tile, column-major, 528-B columns
+// Operands go straight from global memory into LDS (global_load_lds_dwordx4,
+// no register staging) in K steps of 32: per operand and word plane a
+// [128 columns][32] halves region, 64 B per column, whose four 16-B chunks are
+// XOR-swizzled by column so that the matrix-core operand reads (16 columns x
+// one chunk) hit all 64 banks.  One stage per workgroup: the operand traffic
+// of one workgroup overlaps the products of the others on the CU.  The
+// epilogue stages half of the FP32 tile at a time in LDS, column-major for
+// the tile itself and row-major for its mirror, so that 16 consecutive lanes
+// write one 128-row column segment (coalesced 16-B stores).
+constexpr int BK = 32;
+constexpr int CPC = BK / 8;        // 16-B chunks per column, word plane and K step
+constexpr int CST = 132;           // column-major staging: 528-B columns (conflict-free f4 stores)
+constexpr int CSTH = 68;           // row-major staging of a 64-column half
+
+__device__ inline int swz(int col) { return (col >> 2) & 3; }
+
+// s_waitcnt vmcnt(0) (the gfx9 encoding with expcnt and lgkmcnt left at their maxima)
+__device__ inline void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Workgroup barrier without the memory fence of __syncthreads(): the operand
+// loads are waited for explicitly; the empty asm statements keep the compiler
+// from moving LDS accesses across it.
+__device__ inline void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <int NW>
 __host__ __device__ constexpr int words_lds_bytes()
 {
-    return (2 * NW * BM * SK2 * 2) > (BM * CST * 4) ? (2 * NW * BM * SK2 * 2) : (BM * CST * 4);
+    return (2 * NW * BM * BK * 2) > (BM * CSTH * 4) ? (2 * NW * BM * BK * 2) : (BM * CSTH * 4);
 }
 
 template <int FMT, int NW, int MODE>
@@ -183,9 +203,8 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
 {
     __shared__ __attribute__((aligned(16))) unsigned char smem[words_lds_bytes<NW>()];
     __shared__ double wsum[4];
-    unsigned short *As = reinterpret_cast<unsigned short *>(smem);          // [NW][BM][SK2]
-    unsigned short *Bs = As + NW * BM * SK2;                                 // [NW][BM][SK2]
-    float *Cs = reinterpret_cast<float *>(smem);                             // [BM][CST] after the loop
+    unsigned short *Ls = reinterpret_cast<unsigned short *>(smem);   // [2 operands][NW][BM][BK]
+    float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
 
     const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
@@ -222,15 +241,24 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
 
-    // staging: a K step is 64 k = 128 B per tile column and word plane, i.e. eight
-    // 16-B chunks.  Chunk q*256 + tid (q = 0..3) is column 32 q + tid/8, part tid%8:
-    // eight consecutive lanes read one full cache line.
-    const int part = tid & 7;
-    const int col8 = tid >> 3;
-    const unsigned short *pa = xin + gd.off + (int64_t)(ti * BM + col8) * ld + part * 8;
-    const unsigned short *pb = bin + gd.off + (int64_t)(tj * BM + col8) * ld + part * 8;
-    const int64_t col_stride = (int64_t)32 * ld;       // 32 columns further
+    // Loads: one wave instruction fills 1 KB of LDS = 16 columns x 64 B; lane l
+    // fills slot l % 4 of column (wave + 4 q) * 16 + l / 4 with chunk
+    // (slot ^ swz(column)) of that column.  Columns beyond ld and the chunk
+    // offsets of a K step beyond ld read any valid address instead (their
+    // products only reach discarded outputs, or are not issued).
+    constexpr int PH = BM * BK;         // halves per operand-plane region
+    const unsigned short *srcA[2], *srcB[2];
+    int kcoff[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int cl = (wave + 4 * q) * 16 + lane / CPC;
+        kcoff[q] = ((lane % CPC) ^ swz(cl)) * 8;
+        srcA[q] = xin + gd.off + (int64_t)(ti * BM + cl < ld ? ti * BM + cl : 0) * ld;
+        srcB[q] = bin + gd.off + (int64_t)(tj * BM + cl < ld ? tj * BM + cl : 0) * ld;
+    }
 
     const int row_w = ti * BM + wr * 64, col_w = tj * BM + wc * 64;
     const bool wave_live = (row_w < ld) && (col_w < ld) && !(ti == tj && wr < wc);
@@ -241,75 +269,53 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    u16x8 ra[NW][4], rb[NW][4];
-    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    auto gload = [&](int k0) {
-        // ld is a multiple of 32: in the last step the parts beyond ld read as zero
-        const bool kv = k0 + part * 8 < ld;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const bool ca = kv && (ti * BM + 32 * q + col8 < ld);
-            const bool cb = kv && (tj * BM + 32 * q + col8 < ld);
-#pragma unroll
-            for (int w = 0; w < NW; w++) {
-                ra[w][q] = ca ? *reinterpret_cast<const u16x8 *>(pa + w * plane + q * col_stride + k0) : z8;
-                rb[w][q] = cb ? *reinterpret_cast<const u16x8 *>(pb + w * plane + q * col_stride + k0) : z8;
-            }
-        }
-    };
-    auto sstore = [&]() {
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-            for (int w = 0; w < NW; w++) {
-                *reinterpret_cast<u16x8 *>(&As[(w * BM + 32 * q + col8) * SK2 + part * 8]) = ra[w][q];
-                *reinterpret_cast<u16x8 *>(&Bs[(w * BM + 32 * q + col8) * SK2 + part * 8]) = rb[w][q];
-            }
-    };
-
-    const int nk = (ld + BK2 - 1) / BK2;
-    const int li = lane & 15;
-    const int lq = (lane >> 4) * 8;     // k offset of this lane's 8 operand values
-    gload(0);
+    const int nk = ld / BK;             // ld is a multiple of 32
     for (int kt = 0; kt < nk; kt++) {
-        __syncthreads();                // previous step's LDS reads are done
-        sstore();
-        __syncthreads();
-        const int nsub = (ld - kt * BK2) >= BK2 ? 2 : 1;
-        if (kt + 1 < nk) gload((kt + 1) * BK2);
+        const int k0 = kt * BK;
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                unsigned short *dA = Ls + (0 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
+                unsigned short *dB = Ls + (1 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(srcA[q] + w * plane + k0 + kcoff[q]),
+                    (__attribute__((address_space(3))) void *)dA, 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(srcB[q] + w * plane + k0 + kcoff[q]),
+                    (__attribute__((address_space(3))) void *)dB, 16, 0, 0);
+            }
+        wait_vm0();
+        lds_barrier();                  // every wave's loads of this step are in LDS
         if (wave_live) {
-            for (int sub = 0; sub < nsub; sub++) {
-                u16x8 av[4][NW], bv[4][NW];
+            u16x8 bv[4][NW];
 #pragma unroll
-                for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) {
+                const int cb = wc * 64 + j * 16 + li;
 #pragma unroll
-                    for (int w = 0; w < NW; w++) {
-                        av[i][w] = *reinterpret_cast<const u16x8 *>(&As[(w * BM + wr * 64 + i * 16 + li) * SK2 + sub * 32 + lq]);
-                        bv[i][w] = *reinterpret_cast<const u16x8 *>(&Bs[(w * BM + wc * 64 + i * 16 + li) * SK2 + sub * 32 + lq]);
-                    }
+                for (int w = 0; w < NW; w++)
+                    bv[j][w] = *reinterpret_cast<const u16x8 *>(Ls + (1 * NW + w) * PH + cb * BK + ((lg ^ swz(cb)) * 8));
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int ca = wr * 64 + i * 16 + li;
+                u16x8 av[NW];
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    av[w] = *reinterpret_cast<const u16x8 *>(Ls + (0 * NW + w) * PH + ca * BK + ((lg ^ swz(ca)) * 8));
 #pragma unroll
                 for (int pr = npairs<NW>() - 1; pr >= 0; pr--)      // least significant products first
 #pragma unroll
-                    for (int i = 0; i < 4; i++)
-#pragma unroll
-                        for (int j = 0; j < 4; j++)
-                            acc[i][j] = mfma16<FMT>(av[i][pair_p(pr)], bv[j][pair_q(pr)], acc[i][j]);
+                    for (int j = 0; j < 4; j++)
+                        acc[i][j] = mfma16<FMT>(av[pair_p(pr)], bv[j][pair_q(pr)], acc[i][j]);
             }
         }
+        lds_barrier();                  // every wave is done reading before the next loads land
     }
 
-    // ---- epilogue: FP32 tile into LDS (lane l, register v of block (i, j) holds
-    // row 4*(l/16) + v, column l%16), then column-wise word stores.
-    __syncthreads();
-    if (wave_live) {
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                *reinterpret_cast<f4 *>(&Cs[(wc * 64 + j * 16 + li) * CST + wr * 64 + i * 16 + (lane >> 4) * 4]) = acc[i][j];
-    }
-    __syncthreads();
-
+    // ---- epilogue, in two rounds over the column halves h of the tile (the
+    // waves with wc == h hold them).  Lane l, register v of block (i, j) holds
+    // row 16 i + 4 (l / 16) + v and column 16 j + l % 16 of the wave's tile.
     constexpr float inv_s2 = (float)(1.0 / (word_scale<FMT>() * word_scale<FMT>()));
     constexpr float sc = (float)word_scale<FMT>();
     const int n = gd.n;
@@ -320,72 +326,88 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     auto value = [&](float t, int r, int c) -> float {
         return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
     };
-    {
-        // direct tile: thread = (column, half of the rows); 8-row groups above
-        // the diagonal of a diagonal tile are left to the mirror pass
-        const int cl = tid >> 1, rh = (tid & 1) * 64;
-        const int c = tj * BM + cl;
-        if (c < ld) {
-#pragma unroll 2
-            for (int q = 0; q < 8; q++) {
-                const int rl = rh + q * 8;
-                const int r0 = ti * BM + rl;
-                if (r0 >= ld) break;
-                if (diag && r0 + 7 < c) continue;
-                float v[8];
-                const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rl]);
-                const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rl + 4]);
-                v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-                v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+    for (int h = 0; h < 2; h++) {
+        if (wave_live && wc == h) {
 #pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    const int r = r0 + e;
-                    const float t = v[e] * inv_s2;
-                    if (MODE == 0 && r < n && c < n && r >= c) {
-                        float d = fabsf(t - (r == c ? 1.f : 0.f));
-                        if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
-                        rmax = fmaxf(rmax, d);
-                        if (r == c) dsum += 1.0 - (double)t;
-                    }
-                    v[e] = value(t, r, c) * sc;
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    *reinterpret_cast<f4 *>(&Cs[(j * 16 + li) * CST + wr * 64 + i * 16 + lg * 4]) = acc[i][j];
+        }
+        __syncthreads();
+        // the tile's own positions: unit (column cl of the half, 8-row chunk rc);
+        // 8-row chunks above the diagonal of a diagonal tile are the mirror's
+#pragma unroll 2
+        for (int q = 0; q < 4; q++) {
+            const int u = tid + 256 * q;
+            const int rc = u & 15, cl = u >> 4;
+            const int c = tj * BM + h * 64 + cl, r0 = ti * BM + rc * 8;
+            if (c >= ld || r0 >= ld) continue;
+            if (diag && r0 + 7 < c) continue;
+            float v[8];
+            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8]);
+            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8 + 4]);
+            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int r = r0 + e;
+                const float t = v[e] * inv_s2;
+                if (MODE == 0 && r < n && c < n && r >= c) {
+                    float d = fabsf(t - (r == c ? 1.f : 0.f));
+                    if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
+                    rmax = fmaxf(rmax, d);
+                    if (r == c) dsum += 1.0 - (double)t;
                 }
-                u16x8 wv[NW];
-                split8<FMT, NW>(v, wv);
+                v[e] = value(t, r, c) * sc;
+            }
+            u16x8 wv[NW];
+            split8<FMT, NW>(v, wv);
+#pragma unroll
+            for (int w = 0; w < NW; w++)
+                *reinterpret_cast<u16x8 *>(og + w * plane + r0 + (int64_t)c * ld) = wv[w];
+        }
+        __syncthreads();                // Cs reads done; direct stores precede the mirror's
+        if (wave_live && wc == h) {
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++)
+                        Cs[(wr * 64 + i * 16 + lg * 4 + v) * CSTH + j * 16 + li] = acc[i][j][v];
+        }
+        __syncthreads();
+        // mirror: tile element (rl, cl) goes to (cl, rl) of the matrix; unit (tile
+        // row rl, 8-column chunk cc); in a diagonal tile only positions above
+        // the diagonal
+#pragma unroll 2
+        for (int q = 0; q < 4; q++) {
+            const int u = tid + 256 * q;
+            const int cc = u & 7, rl = u >> 3;
+            const int r = ti * BM + rl, c0 = tj * BM + h * 64 + cc * 8;
+            if (r >= ld || c0 >= ld) continue;
+            if (diag && c0 >= r) continue;
+            float v[8];
+            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8]);
+            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8 + 4]);
+            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = value(v[e] * inv_s2, r, c0 + e) * sc;
+            u16x8 wv[NW];
+            split8<FMT, NW>(v, wv);
+            if (!diag || c0 + 8 <= r) {
 #pragma unroll
                 for (int w = 0; w < NW; w++)
-                    *reinterpret_cast<u16x8 *>(og + w * plane + r0 + (int64_t)c * ld) = wv[w];
+                    *reinterpret_cast<u16x8 *>(og + w * plane + c0 + (int64_t)r * ld) = wv[w];
+            } else {
+                for (int e = 0; c0 + e < r; e++)
+#pragma unroll
+                    for (int w = 0; w < NW; w++) og[w * plane + c0 + e + (int64_t)r * ld] = wv[w][e];
             }
         }
-    }
-    __syncthreads();                    // direct stores precede the mirror stores that overlap them
-    {
-        // mirror: element (r, c) of the tile is stored at (c, r); thread = (tile row r,
-        // half of the tile columns); in a diagonal tile only r > c
-        const int rl = tid >> 1, chh = (tid & 1) * 64;
-        const int r = ti * BM + rl;
-        if (r < ld) {
-#pragma unroll 2
-            for (int q = 0; q < 8; q++) {
-                const int cl0 = chh + q * 8;
-                const int c0 = tj * BM + cl0;
-                if (c0 >= ld) break;
-                if (diag && c0 >= r) continue;
-                float v[8];
-#pragma unroll
-                for (int e = 0; e < 8; e++) v[e] = value(Cs[(cl0 + e) * CST + rl] * inv_s2, r, c0 + e) * sc;
-                u16x8 wv[NW];
-                split8<FMT, NW>(v, wv);
-                if (!diag || c0 + 8 <= r) {
-#pragma unroll
-                    for (int w = 0; w < NW; w++)
-                        *reinterpret_cast<u16x8 *>(og + w * plane + c0 + (int64_t)r * ld) = wv[w];
-                } else {
-                    for (int e = 0; c0 + e < r; e++)
-#pragma unroll
-                        for (int w = 0; w < NW; w++) og[w * plane + c0 + e + (int64_t)r * ld] = wv[w][e];
-                }
-            }
-        }
+        __syncthreads();
     }
 
     if (MODE == 0) {
