@@ -157,8 +157,11 @@ int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
  * of X_k, all of which lie in [-1, 1]), or until tau_k stops falling
  * (tau_k >= tau_{k-1}, or tau_k < 0.1 and tau_k > tau_{k-1}/2), or for at
  * most max_iter - n_polish
- * steps, and is followed by n_polish FP64 steps (>= 1); the last of them is
- * computed on the group's own columns only, since only those enter D.
+ * steps, and is followed by n_polish FP64 steps (1 <= n_polish <= 4 in these
+ * modes), computed on the group's own columns only, since only those enter D:
+ * X_{k+n_polish} E (E the own-column selector) is a polynomial of degree
+ * 3^n_polish in the bulk result X_k, evaluated by 3^n_polish - 1 FP64 products
+ * of X_k with n_g x m_own blocks.
  * Defaults: tol 1e-12, max_iter 100, n_polish 2, switch_tol 1e-3.
  */
 int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
@@ -168,8 +171,8 @@ int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
  * Device work space.  The dense submatrices are processed in waves of
  * consecutive groups; all groups of a wave are resident together (three FP64
  * n_pad x n_pad slabs per group, the reduced-precision word planes laid over
- * two of them, 26 bytes per element, plus 24 n_pad m_own bytes of own-column
- * buffers), and the waves reuse one arena.  bytes = 0 (the default) sizes the
+ * two of them, 26 bytes per element, plus 72 n_pad m_own bytes of own-column
+ * blocks), and the waves reuse one arena.  bytes = 0 (the default) sizes the
  * waves to the free device memory at plan time, less the plan's tables and
  * 1 GiB, and at most 3/4 of the device; bytes > 0 caps the arena and forces
  * more waves.  A group that does
@@ -220,8 +223,8 @@ int32_t smx_get_group_info(smx_ctx ctx, int32_t *n_g, int32_t *iters,
  *             (needs a loaded K; uses the current groups and mu);
  *   what = 1: the sign S_g of the last evaluation (the whole submatrix,
  *             not only the group's own columns); in the reduced-precision
- *             modes the last full FP64 iterate, one step before the final
- *             (own-column) step.
+ *             modes the bulk's last iterate in FP64, before the polish
+ *             (which is computed on the own columns only).
  * n_out (nullable) receives n_g.  With out == NULL only n_g is returned.
  * Synchronises.  what = 0 overwrites scratch that what = 1 does not read.
  */

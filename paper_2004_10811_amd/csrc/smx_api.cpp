@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -81,6 +82,10 @@ struct Plan {
 // i.e. 26 bytes per element with three BF16 words.
 constexpr int64_t kArenaBytesPerElem = 26;
 
+// Largest n_polish of the reduced-precision modes (the own-column polish
+// evaluates a degree-3^n_polish polynomial by 3^n_polish - 1 thin products).
+constexpr int32_t kMaxPolishMixed = 4;
+
 }  // namespace
 
 struct smx_context {
@@ -135,7 +140,7 @@ struct smx_context {
     DevBuf<int4> d_contrib;
     DevBuf<double> d_adj, d_dk, d_dmu;
     bool contrib_ready = false;
-    DevBuf<double> d_t0, d_t1, d_t2;             // own-column buffers of the last polish step
+    DevBuf<double> d_tpool;                      // own-column blocks of the FP64 polish (2 n_polish + 1)
     DevBuf<int64_t> d_plist;
 
     // host polling / timing
@@ -314,10 +319,10 @@ int32_t build_plan(smx_ctx c)
 }
 
 // Device bytes one group adds to a wave: its share of the arena and of the
-// three own-column buffers of the last polish step.
+// own-column blocks of the FP64 polish (2 n_polish + 1 <= 9 of them).
 int64_t group_bytes(const GroupDesc &d)
 {
-    return kArenaBytesPerElem * (int64_t)d.npad * d.npad + 3 * 8 * (int64_t)d.npad * d.m_own;
+    return kArenaBytesPerElem * (int64_t)d.npad * d.npad + (2 * kMaxPolishMixed + 1) * 8 * (int64_t)d.npad * d.m_own;
 }
 
 // Split the groups into consecutive waves of at most `budget` bytes each
@@ -483,9 +488,7 @@ int32_t ensure_plan(smx_ctx c)
     // left after the plan's tables (with 1 GiB held back, and no more than
     // 3/4 of the device)
     c->d_arena.release();
-    c->d_t0.release();
-    c->d_t1.release();
-    c->d_t2.release();
+    c->d_tpool.release();
     c->d_tx0.release();
     c->d_tx1.release();
     c->d_adj.release();
@@ -577,6 +580,72 @@ int32_t need_sync_results(smx_ctx c)
     return SMX_OK;
 }
 
+// FP64 polish of the reduced-precision modes on the own columns.  With
+// A_0(Z) = X Z (X the bulk result, FP64) and A_j(Z) = X_{k+j} Z =
+// 1.5 A_{j-1}(Z) - 0.5 A_{j-1}(A_{j-1}(A_{j-1}(Z))), the own columns of the
+// p-times polished sign are A_p(E), E the own-column selector (A_0(E) is a
+// gather).  Thin blocks come from a pool of 2p + 1; the residual
+// max|X_{k+p-1}^2 E - E| is taken on the innermost square of the last step.
+int32_t own_polish(smx_ctx c, int32_t g0, int32_t wng, const double *x, const IterState &it, int32_t *result)
+{
+    const Plan &P = c->plan;
+    hipStream_t st = c->stream;
+    const int32_t nbuf = 2 * c->n_polish + 1;
+    std::vector<char> used((size_t)nbuf, 0);
+    auto buf = [&](int i) { return c->d_tpool.p + (size_t)i * (size_t)P.thin_elems; };
+    auto take = [&]() -> int {
+        for (int i = 0; i < nbuf; i++)
+            if (!used[i]) {
+                used[i] = 1;
+                return i;
+            }
+        return -1;
+    };
+    const int slot = c->max_iter + c->n_polish;
+    hipError_t herr = hipSuccess;
+    std::function<int(int, int, bool)> apply = [&](int j, int zi, bool top) -> int {
+        if (herr != hipSuccess) return -1;
+        if (j == 1) {
+            const int a = take();
+            if (a < 0) return -1;
+            herr = zi < 0 ? launch_own_gather(st, g0, wng, P.max_npad, c->d_gd.p, c->d_own.p, x, buf(a))
+                          : launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(zi), nullptr, buf(a));
+            const int b = take();
+            if (b < 0) return -1;
+            if (herr == hipSuccess)
+                herr = launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(a), nullptr, buf(b));
+            if (top && herr == hipSuccess)
+                herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(b), it, slot);
+            const int out = take();
+            if (out < 0) return -1;
+            if (herr == hipSuccess)
+                herr = launch_thin_mul(st, 1, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(b), buf(a), buf(out));
+            used[a] = used[b] = 0;
+            return out;
+        }
+        const int aa = apply(j - 1, zi, false);
+        if (aa < 0) return -1;
+        const int bb = apply(j - 1, aa, false);
+        if (bb < 0) return -1;
+        if (top && herr == hipSuccess)
+            herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(bb), it, slot);
+        const int cc = apply(j - 1, bb, false);
+        if (cc < 0) return -1;
+        used[bb] = 0;
+        if (herr == hipSuccess)
+            herr = launch_thin_combine(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, buf(aa), buf(cc));
+        used[aa] = 0;
+        return cc;
+    };
+    const int r = apply(c->n_polish, -1, true);
+    if (herr != hipSuccess)
+        return fail(c, herr == hipErrorOutOfMemory ? SMX_E_NOMEM : SMX_E_HIP,
+                    std::string("own-column polish: ") + hipGetErrorString(herr));
+    if (r < 0) return fail(c, SMX_E_INVALID, "internal: own-column polish ran out of buffers");
+    *result = r;
+    return SMX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -653,9 +722,7 @@ int32_t smx_destroy(smx_ctx c)
     c->d_adj.release();
     c->d_dk.release();
     c->d_dmu.release();
-    c->d_t0.release();
-    c->d_t1.release();
-    c->d_t2.release();
+    c->d_tpool.release();
     if (c->h_ndone) (void)hipHostFree(c->h_ndone);
     for (hipEvent_t ev : c->ev_poll) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->ev_launch) (void)hipEventDestroy(ev);
@@ -854,6 +921,10 @@ int32_t smx_evaluate(smx_ctx c)
         return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) runs in SMX_FP64 only");
     if (mixed && c->max_iter <= c->n_polish)
         return fail(c, SMX_E_INVALID, "max_iter must exceed n_polish in reduced-precision modes");
+    if (mixed && c->n_polish > kMaxPolishMixed)
+        return fail(c, SMX_E_INVALID, "n_polish above " + std::to_string(kMaxPolishMixed) +
+                                          " in a reduced-precision mode (the own-column polish costs 3^n_polish - 1 "
+                                          "passes over each submatrix)");
     if (int32_t st = set_device(c)) return st;
     c->evaluated = false;
     if (int32_t st = ensure_plan(c)) return st;
@@ -876,10 +947,7 @@ int32_t smx_evaluate(smx_ctx c)
         c->ev_poll.push_back(ev);
     }
     if (mixed) {
-        const size_t thin = (size_t)std::max<int64_t>(P.thin_elems, 1);
-        HIP_TRY(c, c->d_t0.ensure(thin));
-        HIP_TRY(c, c->d_t1.ensure(thin));
-        HIP_TRY(c, c->d_t2.ensure(thin));
+        HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1)));
         // word planes from byte 8E to 8E + 6 nw E of the arena
         const size_t need = (size_t)((8 * P.work_elems + 6 * (int64_t)nw * P.work_elems + 7) / 8);
         if (c->d_arena.cap < need) HIP_TRY(c, c->d_arena.ensure(need));
@@ -952,6 +1020,7 @@ int32_t smx_evaluate(smx_ctx c)
     unsigned short *wb[2] = {wbase, wbase + (size_t)nw * plane};
     unsigned short *wwp = wbase + (size_t)2 * nw * plane;
     double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
+    double *thin_result = nullptr;
     const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
     int32_t launched = 0;
     // waves run one after the other through the same arena; every group's
@@ -996,26 +1065,18 @@ int32_t smx_evaluate(smx_ctx c)
             }
         }
         if (mixed) {
-            // FP64 polish: n_polish - 1 full steps, then the last step on the own columns only
+            // FP64 polish on the own columns: X_{k+p} E from the bulk result X
             HIP_TRY(c, launch_from_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, wb[0], wb[1], it.kfinal, plane,
                                          xb[0]));
-            int cur = 0;
-            for (int32_t q = 0; q + 1 < c->n_polish; q++) {
-                const int slot = c->max_iter + 1 + q;
-                HIP_TRY(c, timed(4, slot, [&] { return launch_ns_f64(st, 0, ntiles, tl, c->d_gd.p, xb[cur], xb[cur],
-                                                                     wslab, it, slot, c->tol, c->max_iter, 1); }));
-                HIP_TRY(c, timed(5, slot, [&] { return launch_ns_f64(st, 1, ntiles, tl, c->d_gd.p, xb[cur], wslab,
-                                                                     xb[cur ^ 1], it, slot, c->tol, c->max_iter, 1); }));
-                cur ^= 1;
-            }
-            HIP_TRY(c, launch_own_polish(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, xb[cur], c->d_t0.p,
-                                         c->d_t1.p, c->d_t2.p, it, c->max_iter + c->n_polish));
+            int32_t res = -1;
+            if (int32_t e = own_polish(c, g0, wng, xb[0], it, &res)) return e;
+            thin_result = c->d_tpool.p + (size_t)res * (size_t)P.thin_elems;
         }
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
         const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
         const int64_t *pl = nwave > 1 ? c->d_plist.p + P.plist_beg[wave] : nullptr;
         if (mixed)
-            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, c->d_t2.p, nullptr, it,
+            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, thin_result, nullptr, it,
                                       c->d_k.p, c->d_d.p, c->d_pe.p, c->d_pn.p, 1));
         else
             HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, xb[0], xb[1], it, c->d_k.p,
@@ -1107,8 +1168,8 @@ int32_t smx_get_group_info(smx_ctx c, int32_t *n_g, int32_t *iters, double *scal
     for (int32_t g = 0; g < ng; g++) {
         if (n_g) n_g[g] = c->plan.gd[g].n;
         if (iters) iters[g] = kf[g] + c->last_polish;
-        // FP64 mode: residual of the returned X_k; reduced-precision modes: residual of
-        // the last full FP64 iterate on the own columns (the final step is own-column only)
+        // FP64 mode: residual of the returned X_k; reduced-precision modes:
+        // max|X_{k+p-1}^2 E - E| on the own columns, one step before the result
         const size_t slot = c->last_polish ? (size_t)(c->last_max_iter + c->last_polish) : (size_t)kf[g];
         double s, r;
         std::memcpy(&s, &sb[g], sizeof s);
@@ -1164,9 +1225,9 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
             if (c->last_polish == 0) {
                 exec += per * (2.0 * kb + 1.0);
             } else {
+                // bulk word products, then 3^p - 1 thin FP64 products of the own-column polish
                 exec += per * npairs * (2.0 * kb + 1.0);
-                exec += per * 2.0 * (c->last_polish - 1);
-                exec += 2.0 * 2.0 * (double)d.n * d.n * d.m_own;
+                exec += (std::pow(3.0, c->last_polish) - 1.0) * 2.0 * (double)d.n * d.n * d.m_own;
             }
         }
     }
@@ -1189,8 +1250,7 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_t0, c->ev_t3));
     s.time_total_ms = ms;
     double ws = 0;
-    for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_arena.bytes(), c->d_t0.bytes(), c->d_t1.bytes(),
-                     c->d_t2.bytes(), c->d_tx0.bytes(), c->d_tx1.bytes(), c->d_adj.bytes(), c->d_bmap.bytes(),
+    for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_arena.bytes(), c->d_tpool.bytes(), c->d_tx0.bytes(), c->d_tx1.bytes(), c->d_adj.bytes(), c->d_bmap.bytes(),
                      c->d_rinfo.bytes(), c->d_scat.bytes(), c->d_resid.bytes(), c->d_tiles.bytes(),
                      c->d_tiles_full.bytes(), c->d_plist.bytes()})
         ws += (double)b;
@@ -1267,10 +1327,10 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         dch.release();
         src = slab(c, 2) + d.off;
     } else if (c->last_polish) {
-        // reduced-precision modes: the last full FP64 iterate (the final step
-        // is computed on the own columns only)
+        // reduced-precision modes: the bulk's last iterate in FP64 (the
+        // polish steps are computed on the own columns only)
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        src = slab(c, (c->last_polish - 1) & 1) + d.off;
+        src = slab(c, 0) + d.off;
     } else {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         int32_t kf = 0;

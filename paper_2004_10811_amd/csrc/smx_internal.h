@@ -117,8 +117,16 @@ hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroup
 
 // Last polish step restricted to the own columns (FP64, vector ALU):
 //   O = P[:, own];  Y = P O (residual of P^2 on the own columns -> slot);  F = 1.5 O - 0.5 P Y.
-hipError_t launch_own_polish(hipStream_t st, int g0, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
-                             const int32_t *own_list, const double *p, double *o, double *y, double *f,
+// Own-column polish: out = X[:, own]; y = X z (mode 0) or 1.5 o - 0.5 X z (mode 1);
+// c = 1.5 a - 0.5 c; max |b - E| into the residual slot.
+hipError_t launch_own_gather(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
+                             const int32_t *own_list, const double *x, double *out);
+hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
+                           const GroupDesc *groups, const double *x, const double *z, const double *o, double *y);
+hipError_t launch_thin_combine(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
+                               const GroupDesc *groups, const double *a, double *c);
+hipError_t launch_thin_resid(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
+                             const GroupDesc *groups, const int32_t *own_list, const double *b,
                              const IterState &it, int slot);
 
 // from_thin = 0: S_g = a X_kfinal (full matrices x0 / x1 by step parity);

@@ -140,11 +140,13 @@ void scatter_kernel(int64_t nblocks, const int64_t *__restrict__ plist, const Sc
 }
 
 // ---------------------------------------------------------------------------
-// Last FP64 polish step on the own columns only.  The scatter needs only the
-// group's own columns of X_{k+1} = X_k (3I - X_k^2) / 2, which equal
-// 1.5 X_k[:, own] - 0.5 X_k (X_k X_k[:, own]): two thin products instead of
-// two dense ones.  One thread per row, up to 32 own columns per pass, the
-// thin operand staged through LDS in steps of 64 rows.
+// FP64 polish on the own columns only.  D needs only the group's own columns
+// of the polished sign, X_{k+p}[:, own] = X_{k+p} E (E selects the own
+// columns), and every polished iterate is a polynomial in the bulk result X:
+// X_{j+1} = 1.5 X_j - 0.5 X_j^3.  The driver evaluates X_{k+p} E by thin
+// products Y = X Z with n_pad x m_own blocks Z (column-major, leading
+// dimension n_pad), so the p FP64 steps cost 3^p - 1 passes over X instead
+// of 2p dense products.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256)
 void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
@@ -157,66 +159,115 @@ void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__re
         o[gd.thin_off + r + (int64_t)c * gd.npad] = p[gd.off + r + (int64_t)own_list[gd.own_off + c] * gd.npad];
 }
 
-// MODE 0: y = P b, residual max|y - I[:, own]| -> slot.  MODE 1: y = 1.5 o - 0.5 P b.
-template <int MODE>
+// MODE 0: y = X z.  MODE 1: y = 1.5 o - 0.5 X z.  X is symmetric; a lane owns
+// two consecutive rows (16-B loads, 64 lanes = 128 rows = one contiguous 1-KB
+// segment of a column of X per k) and MW accumulator columns per pass; z is
+// staged in LDS 64 rows at a time, row-major, so that one broadcast 16-B read
+// gives two columns.  Rows k >= n of X and z are not needed: X[r, k] = 0 for
+// r < n <= k, and rows r >= n of the result are exactly zero.
+template <int MODE, int MW>
 __global__ __launch_bounds__(256)
-void thin_mul_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
-                     const double *__restrict__ p, const double *__restrict__ b, const double *__restrict__ o,
-                     double *__restrict__ y, IterState it, int slot, int g0)
+void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ x,
+                     const double *__restrict__ z, const double *__restrict__ o, double *__restrict__ y, int g0)
 {
-    __shared__ double bs[64][33];
-    const int g = g0 + blockIdx.y;
-    const GroupDesc gd = groups[g];
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x * 256 >= gd.npad) return;          // whole block beyond this group
-    const bool live = r < gd.npad;
-    const double *pg = p + gd.off;
-    double rmax = 0.0;
-    for (int c0 = 0; c0 < gd.m_own; c0 += 32) {
-        const int nc = min(32, gd.m_own - c0);
-        double acc[32];
+    __shared__ __attribute__((aligned(16))) double zs[64][MW + 2];
+    const GroupDesc gd = groups[g0 + blockIdx.y];
+    const int npad = gd.npad;
+    const int row0 = blockIdx.x * 512;
+    if (row0 >= npad) return;                         // whole block beyond this group
+    const int r = row0 + 2 * (int)threadIdx.x;        // rows r, r + 1 (npad is even)
+    const bool live = r < npad;
+    const double *xg = x + gd.off;
+    for (int c0 = 0; c0 < gd.m_own; c0 += MW) {
+        const int nc = min(MW, gd.m_own - c0);
+        double2 acc[MW];
 #pragma unroll
-        for (int c = 0; c < 32; c++) acc[c] = 0.0;
+        for (int c = 0; c < MW; c++) acc[c] = double2{0.0, 0.0};
         for (int k0 = 0; k0 < gd.n; k0 += 64) {
             __syncthreads();
-            for (int t = threadIdx.x; t < 64 * 32; t += 256) {
+            for (int t = threadIdx.x; t < 64 * MW; t += 256) {
                 const int kk = t & 63, cc = t >> 6;
                 const int kr = k0 + kk;
-                bs[kk][cc] = (kr < gd.n && cc < nc) ? b[gd.thin_off + kr + (int64_t)(c0 + cc) * gd.npad] : 0.0;
+                zs[kk][cc] = (kr < gd.n && cc < nc) ? z[gd.thin_off + kr + (int64_t)(c0 + cc) * npad] : 0.0;
             }
             __syncthreads();
             const int kend = min(64, gd.n - k0);
             if (live) {
-                for (int kk = 0; kk < kend; kk++) {
-                    const double pv = pg[r + (int64_t)(k0 + kk) * gd.npad];
+                int kk = 0;
+                for (; kk + 4 <= kend; kk += 4) {
+                    double2 xv[4];
 #pragma unroll
-                    for (int c = 0; c < 32; c++) acc[c] = fma(pv, bs[kk][c], acc[c]);
+                    for (int u = 0; u < 4; u++)
+                        xv[u] = *reinterpret_cast<const double2 *>(xg + r + (int64_t)(k0 + kk + u) * npad);
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+#pragma unroll
+                        for (int c = 0; c < MW; c += 2) {
+                            const double2 zv = *reinterpret_cast<const double2 *>(&zs[kk + u][c]);
+                            acc[c].x = fma(xv[u].x, zv.x, acc[c].x);
+                            acc[c].y = fma(xv[u].y, zv.x, acc[c].y);
+                            acc[c + 1].x = fma(xv[u].x, zv.y, acc[c + 1].x);
+                            acc[c + 1].y = fma(xv[u].y, zv.y, acc[c + 1].y);
+                        }
+                }
+                for (; kk < kend; kk++) {
+                    const double2 xv = *reinterpret_cast<const double2 *>(xg + r + (int64_t)(k0 + kk) * npad);
+#pragma unroll
+                    for (int c = 0; c < MW; c += 2) {
+                        const double2 zv = *reinterpret_cast<const double2 *>(&zs[kk][c]);
+                        acc[c].x = fma(xv.x, zv.x, acc[c].x);
+                        acc[c].y = fma(xv.y, zv.x, acc[c].y);
+                        acc[c + 1].x = fma(xv.x, zv.y, acc[c + 1].x);
+                        acc[c + 1].y = fma(xv.y, zv.y, acc[c + 1].y);
+                    }
                 }
             }
         }
         if (live) {
 #pragma unroll
-            for (int c = 0; c < 32; c++) {
+            for (int c = 0; c < MW; c++) {
                 if (c >= nc) break;
-                const int64_t idx = gd.thin_off + r + (int64_t)(c0 + c) * gd.npad;
-                if (MODE == 0) {
-                    y[idx] = acc[c];
-                    if (r < gd.n) {
-                        double d = fabs(acc[c] - (r == own_list[gd.own_off + c0 + c] ? 1.0 : 0.0));
-                        if (!(d <= 1.7976931348623157e308)) d = __builtin_huge_val();
-                        rmax = fmax(rmax, d);
-                    }
-                } else {
-                    y[idx] = 1.5 * o[idx] - 0.5 * acc[c];
+                const int64_t idx = gd.thin_off + r + (int64_t)(c0 + c) * npad;
+                double2 v = acc[c];
+                if (MODE == 1) {
+                    const double2 ov = *reinterpret_cast<const double2 *>(o + idx);
+                    v = double2{1.5 * ov.x - 0.5 * v.x, 1.5 * ov.y - 0.5 * v.y};
                 }
+                *reinterpret_cast<double2 *>(y + idx) = v;
             }
         }
     }
-    if (MODE == 0) {
-        rmax = wave_max(rmax);
-        if ((threadIdx.x & 63) == 0)
-            atomic_max_nonneg(it.resid_bits + (int64_t)g * it.resid_stride + slot, rmax);
+}
+
+// a <- 1.5 a - 0.5 c on the own-column blocks (in place in c: c = 1.5 a - 0.5 c).
+__global__ __launch_bounds__(256)
+void thin_combine_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ a,
+                         double *__restrict__ c, int g0)
+{
+    const GroupDesc gd = groups[g0 + blockIdx.y];
+    const int64_t tot = (int64_t)gd.npad * gd.m_own;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        c[gd.thin_off + e] = 1.5 * a[gd.thin_off + e] - 0.5 * c[gd.thin_off + e];
+}
+
+// max |b - E| over the true rows and the own columns -> residual slot of the group.
+__global__ __launch_bounds__(256)
+void thin_resid_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
+                       const double *__restrict__ b, IterState it, int slot, int g0)
+{
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
+    double rmax = 0.0;
+    const int64_t tot = (int64_t)gd.npad * gd.m_own;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int r = (int)(e % gd.npad), c = (int)(e / gd.npad);
+        if (r >= gd.n) continue;
+        double d = fabs(b[gd.thin_off + e] - (r == own_list[gd.own_off + c] ? 1.0 : 0.0));
+        if (!(d <= 1.7976931348623157e308)) d = __builtin_huge_val();
+        rmax = fmax(rmax, d);
     }
+    rmax = wave_max(rmax);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(it.resid_bits + (int64_t)g * it.resid_stride + slot, rmax);
 }
 
 // Fixed-order sum of the per-block partials (one workgroup): deterministic.
@@ -367,15 +418,49 @@ hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const int64_t *plist,
     return hipGetLastError();
 }
 
-hipError_t launch_own_polish(hipStream_t st, int g0, int ngroups, int max_npad, int max_own, const GroupDesc *groups,
-                             const int32_t *own_list, const double *p, double *o, double *y, double *f,
+hipError_t launch_own_gather(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
+                             const int32_t *own_list, const double *x, double *out)
+{
+    if (ngroups <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_npad + 255) / 256), (unsigned)ngroups);
+    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, x, out, g0);
+    return hipGetLastError();
+}
+
+hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
+                           const GroupDesc *groups, const double *x, const double *z, const double *o, double *y)
+{
+    if (ngroups <= 0 || max_own <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_npad + 511) / 512), (unsigned)ngroups);
+#define SMX_TM(M, W) hipLaunchKernelGGL((thin_mul_kernel<M, W>), grid, dim3(256), 0, st, groups, x, z, o, y, g0)
+    const int mw = max_own <= 8 ? 8 : (max_own <= 16 ? 16 : (max_own <= 24 ? 24 : 32));
+    if (mode == 0) {
+        if (mw == 8) SMX_TM(0, 8); else if (mw == 16) SMX_TM(0, 16); else if (mw == 24) SMX_TM(0, 24); else SMX_TM(0, 32);
+    } else {
+        if (mw == 8) SMX_TM(1, 8); else if (mw == 16) SMX_TM(1, 16); else if (mw == 24) SMX_TM(1, 24); else SMX_TM(1, 32);
+    }
+#undef SMX_TM
+    return hipGetLastError();
+}
+
+hipError_t launch_thin_combine(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
+                               const GroupDesc *groups, const double *a, double *c)
+{
+    if (ngroups <= 0 || max_own <= 0) return hipSuccess;
+    const int64_t tot = (int64_t)max_npad * max_own;
+    const dim3 grid((unsigned)std::min<int64_t>((tot + 1023) / 1024, 1024), (unsigned)ngroups);
+    hipLaunchKernelGGL(thin_combine_kernel, grid, dim3(256), 0, st, groups, a, c, g0);
+    return hipGetLastError();
+}
+
+hipError_t launch_thin_resid(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
+                             const GroupDesc *groups, const int32_t *own_list, const double *b,
                              const IterState &it, int slot)
 {
     if (ngroups <= 0 || max_own <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((max_npad + 255) / 256), (unsigned)ngroups);
-    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, p, o, g0);
-    hipLaunchKernelGGL(thin_mul_kernel<0>, grid, dim3(256), 0, st, groups, own_list, p, o, o, y, it, slot, g0);
-    hipLaunchKernelGGL(thin_mul_kernel<1>, grid, dim3(256), 0, st, groups, own_list, p, y, o, f, it, slot, g0);
+    const int64_t tot = (int64_t)max_npad * max_own;
+    const dim3 grid((unsigned)std::min<int64_t>((tot + 1023) / 1024, 1024), (unsigned)ngroups);
+    hipLaunchKernelGGL(thin_resid_kernel, grid, dim3(256), 0, st, groups, own_list, b, it, slot, g0);
     return hipGetLastError();
 }
 

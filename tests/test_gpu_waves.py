@@ -22,9 +22,9 @@ def smx():
 
 
 def group_bytes(n, m_own):
-    """Work space one group adds to a wave (26 B per slab element + own-column buffers)."""
+    """Work space one group adds to a wave (26 B per slab element + own-column blocks)."""
     npad = -(-n // 32) * 32
-    return 26 * npad * npad + 24 * npad * m_own
+    return 26 * npad * npad + 72 * npad * m_own
 
 
 def own_widths(s):
