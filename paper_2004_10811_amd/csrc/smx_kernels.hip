@@ -9,6 +9,8 @@ namespace smx {
 
 namespace {
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 __device__ inline void atomic_max_nonneg(unsigned long long *addr, double v)
 {
     // For non-negative doubles the IEEE bit patterns order like the values;
@@ -161,16 +163,18 @@ void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__re
 
 // MODE 0: y = X z.  MODE 1: y = 1.5 o - 0.5 X z.  X is symmetric; a lane owns
 // two consecutive rows (16-B loads, 64 lanes = 128 rows = one contiguous 1-KB
-// segment of a column of X per k) and MW accumulator columns per pass; z is
-// staged in LDS 64 rows at a time, row-major, so that one broadcast 16-B read
-// gives two columns.  Rows k >= n of X and z are not needed: X[r, k] = 0 for
+// segment of a column of X per k, eight k in flight) and MW accumulator
+// columns per pass; z is staged in LDS 128 rows at a time, row-major, so that
+// one broadcast 16-B read gives two columns.  Rows k >= n of X and z are not needed: X[r, k] = 0 for
 // r < n <= k, and rows r >= n of the result are exactly zero.
 template <int MODE, int MW>
 __global__ __launch_bounds__(256)
 void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ x,
                      const double *__restrict__ z, const double *__restrict__ o, double *__restrict__ y, int g0)
 {
-    __shared__ __attribute__((aligned(16))) double zs[64][MW + 2];
+    constexpr int KC = 128;                           // rows of z per LDS stage
+    constexpr int U = 8;                              // rows of X in flight per lane
+    __shared__ __attribute__((aligned(16))) double zs[KC][MW + 2];
     const GroupDesc gd = groups[g0 + blockIdx.y];
     const int npad = gd.npad;
     const int row0 = blockIdx.x * 512;
@@ -180,30 +184,31 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restr
     const double *xg = x + gd.off;
     for (int c0 = 0; c0 < gd.m_own; c0 += MW) {
         const int nc = min(MW, gd.m_own - c0);
-        double2 acc[MW];
+        d2v acc[MW];
 #pragma unroll
-        for (int c = 0; c < MW; c++) acc[c] = double2{0.0, 0.0};
-        for (int k0 = 0; k0 < gd.n; k0 += 64) {
+        for (int c = 0; c < MW; c++) acc[c] = d2v{0.0, 0.0};
+        for (int k0 = 0; k0 < gd.n; k0 += KC) {
             __syncthreads();
-            for (int t = threadIdx.x; t < 64 * MW; t += 256) {
-                const int kk = t & 63, cc = t >> 6;
+            for (int t = threadIdx.x; t < KC * MW; t += 256) {
+                const int kk = t % KC, cc = t / KC;
                 const int kr = k0 + kk;
                 zs[kk][cc] = (kr < gd.n && cc < nc) ? z[gd.thin_off + kr + (int64_t)(c0 + cc) * npad] : 0.0;
             }
             __syncthreads();
-            const int kend = min(64, gd.n - k0);
+            const int kend = min(KC, gd.n - k0);
             if (live) {
+                const double *xp = xg + r + (int64_t)k0 * npad;
                 int kk = 0;
-                for (; kk + 4 <= kend; kk += 4) {
-                    double2 xv[4];
+                for (; kk + U <= kend; kk += U) {
+                    d2v xv[U];
 #pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        xv[u] = *reinterpret_cast<const double2 *>(xg + r + (int64_t)(k0 + kk + u) * npad);
+                    for (int u = 0; u < U; u++)
+                        xv[u] = *reinterpret_cast<const d2v *>(xp + (int64_t)(kk + u) * npad);
 #pragma unroll
-                    for (int u = 0; u < 4; u++)
+                    for (int u = 0; u < U; u++)
 #pragma unroll
                         for (int c = 0; c < MW; c += 2) {
-                            const double2 zv = *reinterpret_cast<const double2 *>(&zs[kk + u][c]);
+                            const d2v zv = *reinterpret_cast<const d2v *>(&zs[kk + u][c]);
                             acc[c].x = fma(xv[u].x, zv.x, acc[c].x);
                             acc[c].y = fma(xv[u].y, zv.x, acc[c].y);
                             acc[c + 1].x = fma(xv[u].x, zv.y, acc[c + 1].x);
@@ -211,10 +216,10 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restr
                         }
                 }
                 for (; kk < kend; kk++) {
-                    const double2 xv = *reinterpret_cast<const double2 *>(xg + r + (int64_t)(k0 + kk) * npad);
+                    const d2v xv = *reinterpret_cast<const d2v *>(xp + (int64_t)kk * npad);
 #pragma unroll
                     for (int c = 0; c < MW; c += 2) {
-                        const double2 zv = *reinterpret_cast<const double2 *>(&zs[kk][c]);
+                        const d2v zv = *reinterpret_cast<const d2v *>(&zs[kk][c]);
                         acc[c].x = fma(xv.x, zv.x, acc[c].x);
                         acc[c].y = fma(xv.y, zv.x, acc[c].y);
                         acc[c + 1].x = fma(xv.x, zv.y, acc[c + 1].x);
@@ -226,14 +231,14 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restr
         if (live) {
 #pragma unroll
             for (int c = 0; c < MW; c++) {
-                if (c >= nc) break;
+                if (c >= nc) continue;
                 const int64_t idx = gd.thin_off + r + (int64_t)(c0 + c) * npad;
-                double2 v = acc[c];
+                d2v v = acc[c];
                 if (MODE == 1) {
-                    const double2 ov = *reinterpret_cast<const double2 *>(o + idx);
-                    v = double2{1.5 * ov.x - 0.5 * v.x, 1.5 * ov.y - 0.5 * v.y};
+                    const d2v ov = *reinterpret_cast<const d2v *>(o + idx);
+                    v = d2v{1.5 * ov.x - 0.5 * v.x, 1.5 * ov.y - 0.5 * v.y};
                 }
-                *reinterpret_cast<double2 *>(y + idx) = v;
+                *reinterpret_cast<d2v *>(y + idx) = v;
             }
         }
     }
