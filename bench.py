@@ -72,10 +72,14 @@ def cpu_baseline(system, gpu_d, stats_iters, n_g, nthreads, n_sample, seed=2024)
     }, err, pick
 
 
-def run_path(smx, ctx, precision, steps, warmup, d_out):
-    """Warm up, then time exactly `steps` evaluations; returns timings and stats."""
+def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
+    """Warm up, then time exactly `steps` evaluations; returns timings and stats.
+
+    With graph_steps > 0 the step launches are replayed from HIP graphs, which
+    record no per-launch events; the per-launch profile then comes from one
+    direct evaluation after the timed region."""
     import torch
-    ctx.configure(precision=precision)
+    ctx.configure(precision=precision, graph_steps=graph_steps)
 
     def step():
         smx.smx_evaluate(ctx.handle)
@@ -105,6 +109,16 @@ def run_path(smx, ctx, precision, steps, warmup, d_out):
     stats = ctx.stats()
     info = ctx.group_info()
     smx.smx_get_d(ctx.handle, d_out)
+    if graph_steps:
+        ctx.configure(precision=precision, graph_steps=0)
+        step()
+        ms, fl, kd = ctx.launch_profile()
+        for m, f, k in zip(ms, fl, kd):
+            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else "ns_words_kernel"
+            e = prof.setdefault(key, [0.0, 0.0, 0])
+            e[0] += m
+            e[1] += f
+            e[2] += 1
     return dict(ms_per_step=wall / steps * 1e3, dev_ms=dev_ms, prof=prof, stats=stats, info=info,
                 n_elec=smx.smx_trace(ctx.handle), energy=smx.smx_energy(ctx.handle))
 
@@ -149,6 +163,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="groups in the CPU oracle sample (default: one per thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="replay the Newton-Schulz steps from HIP graphs of this many steps (0: direct launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiler run) and exit")
@@ -185,12 +201,13 @@ def main():
 
     # FP64 path first: the reference D and the iteration counts k_g of the
     # effective-TFLOP/s numerator (the same numerator for every precision)
-    r64 = run_path(smx, ctx, "fp64", args.steps if args.precision == "fp64" else 2, 1, d64)
+    r64 = run_path(smx, ctx, "fp64", args.steps if args.precision == "fp64" else 2, 1, d64,
+                   args.graph_steps if args.precision == "fp64" else 0)
     algo = r64["stats"]["algo_flops"]
     run = r64
     d_out = d64
     if args.precision != "fp64":
-        run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix)
+        run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, args.graph_steps)
         d_out = d_mix
     ctx.close()
 
@@ -244,6 +261,7 @@ def main():
             "fp64_ns_steps_mean": round(r64["stats"]["iters_mean"], 2),
             "tol": 1e-12,
             "waves": int(stats["nwaves"]),
+            "graph_steps": args.graph_steps,
         },
         "device_ms_per_D_median": float(np.median(run["dev_ms"])),
         "phase_ms": {"gather": stats["time_gather_ms"], "iterate": stats["time_iterate_ms"],

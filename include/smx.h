@@ -168,6 +168,21 @@ int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
                             int32_t n_polish, double switch_tol);
 
 /*
+ * Step graphs.  With
+ * steps_per_graph = S > 0 the Newton-Schulz step launches of each wave are
+ * captured once into HIP graphs of S consecutive steps (all groups of the
+ * wave, two product launches per step, three when frozen) and replayed;
+ * groups that have converged skip on the device as before, and the host
+ * polls the finished-group counter once per graph.  The graphs are kept
+ * while the plan, buffers, precision and convergence settings stay the
+ * same, and are captured again otherwise.  S = 0 (the default) launches
+ * every product directly and records the per-launch profile
+ * (smx_get_launch_profile reports no launches for graph replays).  Results
+ * are bitwise the same either way.  SMX_E_INVALID unless 0 <= S <= 64.
+ */
+int32_t smx_set_graph(smx_ctx ctx, int32_t steps_per_graph);
+
+/*
  * Device work space.  The dense submatrices are processed in waves of
  * consecutive groups; all groups of a wave are resident together (three FP64
  * n_pad x n_pad slabs per group, the reduced-precision word planes laid over

@@ -65,6 +65,7 @@ SIGNATURES = {
     "smx_set_precision": (_i32, [_vp, _i32]),
     "smx_set_convergence": (_i32, [_vp, _f64, _i32, _i32, _f64]),
     "smx_set_workspace_limit": (_i32, [_vp, _i64]),
+    "smx_set_graph": (_i32, [_vp, _i32]),
     "smx_evaluate": (_i32, [_vp]),
     "smx_wait": (_i32, [_vp]),
     "smx_get_d": (_i32, [_vp, _vp, _i32]),
@@ -209,6 +210,10 @@ def smx_set_convergence(ctx, tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-
 
 def smx_set_workspace_limit(ctx, nbytes=0):
     return _check(ctx, load_library().smx_set_workspace_limit(ctx, int(nbytes)))
+
+
+def smx_set_graph(ctx, steps_per_graph=0):
+    return _check(ctx, load_library().smx_set_graph(ctx, int(steps_per_graph)))
 
 
 def smx_evaluate(ctx):
@@ -357,8 +362,10 @@ class Context:
         return self
 
     def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
-                  mu=None, kT=None, workspace_limit=None):
+                  mu=None, kT=None, workspace_limit=None, graph_steps=None):
         smx_set_precision(self.handle, precision)
+        if graph_steps is not None:
+            smx_set_graph(self.handle, graph_steps)
         if workspace_limit is not None:
             smx_set_workspace_limit(self.handle, workspace_limit)
         smx_set_convergence(self.handle, tol, max_iter, n_polish, switch_tol)

@@ -164,6 +164,13 @@ struct smx_context {
     bool use_kfix = false, use_sfix = false;  // frozen step counts / scales
     bool have_tangent = false;                 // last evaluation computed dN/dmu
     bool last_sfix = false;                    // last evaluation ran on the frozen scales
+
+    // step graphs (smx_set_graph)
+    int32_t graph_steps = 0;                   // steps per graph; 0: direct launches
+    uint64_t plan_gen = 0;                     // bumped whenever the plan is rebuilt
+    hipStream_t cap_stream = nullptr;          // private stream for graph capture
+    std::vector<hipGraphExec_t> graphs;        // [wave][chunk], captured on first use
+    std::vector<uint64_t> graph_sig;
 };
 
 namespace {
@@ -175,6 +182,14 @@ int32_t fail(smx_ctx c, int32_t code, const std::string &msg)
 }
 
 std::string g_create_err;
+
+void drop_graphs(smx_ctx c)
+{
+    for (hipGraphExec_t &g : c->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    c->graphs.clear();
+    c->graph_sig.clear();
+}
 
 #define HIP_TRY(ctx, expr)                                                                   \
     do {                                                                                     \
@@ -535,6 +550,7 @@ int32_t ensure_plan(smx_ctx c)
     HIP_TRY(c, c->d_ne.ensure(2));
     HIP_TRY(c, hipStreamSynchronize(c->stream));   // host vectors may change after return
     c->plan_dirty = false;
+    c->plan_gen++;
     return SMX_OK;
 }
 
@@ -723,6 +739,8 @@ int32_t smx_destroy(smx_ctx c)
     c->d_dk.release();
     c->d_dmu.release();
     c->d_tpool.release();
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_ndone) (void)hipHostFree(c->h_ndone);
     for (hipEvent_t ev : c->ev_poll) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->ev_launch) (void)hipEventDestroy(ev);
@@ -890,6 +908,16 @@ int32_t smx_set_convergence(smx_ctx c, double tol, int32_t max_iter, int32_t n_p
     return SMX_OK;
 }
 
+int32_t smx_set_graph(smx_ctx c, int32_t steps_per_graph)
+{
+    if (!c) return SMX_E_INVALID;
+    if (steps_per_graph < 0 || steps_per_graph > 64) return fail(c, SMX_E_INVALID, "steps_per_graph must be 0..64");
+    if (int32_t st = set_device(c)) return st;
+    if (steps_per_graph != c->graph_steps) drop_graphs(c);
+    c->graph_steps = steps_per_graph;
+    return SMX_OK;
+}
+
 int32_t smx_set_workspace_limit(smx_ctx c, int64_t bytes)
 {
     if (!c) return SMX_E_INVALID;
@@ -1023,6 +1051,24 @@ int32_t smx_evaluate(smx_ctx c)
     double *thin_result = nullptr;
     const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
     int32_t launched = 0;
+    if (c->graph_steps > 0) {
+        // replayable step graphs: valid while everything baked into their
+        // launches (plan, buffers, mode and convergence settings) is unchanged
+        if (!c->cap_stream) HIP_TRY(c, hipStreamCreate(&c->cap_stream));
+        const std::vector<uint64_t> sig = {
+            c->plan_gen, (uint64_t)c->precision, (uint64_t)c->max_iter, (uint64_t)c->n_polish,
+            (uint64_t)c->graph_steps, (uint64_t)tangent, (uint64_t)c->use_sfix, (uint64_t)c->use_kfix,
+            (uint64_t)(uintptr_t)c->d_arena.p, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
+            (uint64_t)(uintptr_t)c->d_resid.p, (uint64_t)(uintptr_t)c->d_tau_parts.p, (uint64_t)(uintptr_t)c->d_tau_hist.p,
+            (uint64_t)(uintptr_t)c->d_sfix.p, (uint64_t)(uintptr_t)c->d_kfix.p,
+            __builtin_bit_cast(uint64_t, c->tol), __builtin_bit_cast(uint64_t, c->switch_tol)};
+        const size_t ngraph = (size_t)nwave * (size_t)(kmax / c->graph_steps + 1);
+        if (sig != c->graph_sig || c->graphs.size() != ngraph) {
+            drop_graphs(c);
+            c->graph_sig = sig;
+            c->graphs.assign(ngraph, nullptr);
+        }
+    }
     // waves run one after the other through the same arena; every group's
     // arithmetic is independent of the wave it falls in
     for (wave = 0; wave < nwave; wave++) {
@@ -1038,30 +1084,61 @@ int32_t smx_evaluate(smx_ctx c)
         if (mixed)
             HIP_TRY(c, launch_to_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, xb[0], it.scale_bits, wb[0], plane));
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
-        // bulk steps: every group iterates until its own stopping rule; the
-        // host polls the wave's finished-group counter one step behind the device
-        for (int32_t k = 0; k <= kmax; k++) {
+        // one Newton-Schulz step of the wave on stream s (timed: HIP events around
+        // each product launch; not inside a graph capture)
+        auto step = [&](hipStream_t s, int32_t k, bool time_it) -> hipError_t {
+            auto run = [&](int kind, auto &&launch) -> hipError_t { return time_it ? timed(kind, k, launch) : launch(); };
+            hipError_t e;
             if (!mixed) {
-                HIP_TRY(c, timed(0, k, [&] { return launch_ns_f64(st, 0, ntiles, tl, c->d_gd.p, xb[k & 1], xb[k & 1],
-                                                                  wslab, it, k, c->tol, c->max_iter, 0); }));
-                HIP_TRY(c, timed(1, k, [&] { return launch_ns_f64(st, 1, ntiles, tl, c->d_gd.p, xb[k & 1], wslab,
-                                                                  xb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
-                if (tangent)
-                    HIP_TRY(c, timed(6, k, [&] { return launch_ns_f64(st, 2, ntiles, tl, c->d_gd.p, tb[k & 1], wslab,
-                                                                      tb[(k + 1) & 1], it, k, c->tol, c->max_iter, 0); }));
+                e = run(0, [&] { return launch_ns_f64(s, 0, ntiles, tl, c->d_gd.p, xb[k & 1], xb[k & 1], wslab, it, k,
+                                                      c->tol, c->max_iter, 0); });
+                if (e == hipSuccess)
+                    e = run(1, [&] { return launch_ns_f64(s, 1, ntiles, tl, c->d_gd.p, xb[k & 1], wslab, xb[(k + 1) & 1],
+                                                          it, k, c->tol, c->max_iter, 0); });
+                if (e == hipSuccess && tangent)
+                    e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, c->d_gd.p, tb[k & 1], wslab, tb[(k + 1) & 1],
+                                                          it, k, c->tol, c->max_iter, 0); });
             } else {
-                HIP_TRY(c, timed(2, k, [&] { return launch_ns_words(st, fmt, nw, 0, ntiles, tl, c->d_gd.p, wb[k & 1],
-                                                                    wb[k & 1], wwp, plane, it, k, c->switch_tol, kmax); }));
-                HIP_TRY(c, timed(3, k, [&] { return launch_ns_words(st, fmt, nw, 1, ntiles, tl, c->d_gd.p, wb[k & 1],
-                                                                    wwp, wb[(k + 1) & 1], plane, it, k, c->switch_tol,
-                                                                    kmax); }));
+                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, ntiles, tl, c->d_gd.p, wb[k & 1], wb[k & 1], wwp,
+                                                        plane, it, k, c->switch_tol, kmax); });
+                if (e == hipSuccess)
+                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, ntiles, tl, c->d_gd.p, wb[k & 1], wwp,
+                                                            wb[(k + 1) & 1], plane, it, k, c->switch_tol, kmax); });
             }
-            launched = std::max(launched, k + 1);
-            HIP_TRY(c, hipMemcpyAsync(c->h_ndone + k, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            HIP_TRY(c, hipEventRecord(c->ev_poll[k], st));
-            if (k >= 1) {
-                HIP_TRY(c, hipEventSynchronize(c->ev_poll[k - 1]));
-                if (c->h_ndone[k - 1] >= wng) break;
+            return e;
+        };
+        // bulk steps: every group iterates until its own stopping rule; the
+        // host polls the wave's finished-group counter one step (or one graph
+        // of graph_steps steps) behind the device
+        const int32_t S = c->graph_steps > 0 ? c->graph_steps : 1;
+        const int32_t nchunk = kmax / S + 1;
+        for (int32_t ch = 0; ch < nchunk; ch++) {
+            const int32_t k0 = ch * S, k1 = std::min(k0 + S - 1, kmax);
+            if (c->graph_steps > 0) {
+                hipGraphExec_t &ex = c->graphs[(size_t)wave * nchunk + ch];
+                if (!ex) {
+                    // capture on the private stream (capture does not run anything)
+                    hipGraph_t gr = nullptr;
+                    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                    hipError_t e = hipSuccess;
+                    for (int32_t k = k0; k <= k1 && e == hipSuccess; k++) e = step(c->cap_stream, k, false);
+                    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+                    HIP_TRY(c, e);
+                    HIP_TRY(c, e2);
+                    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    HIP_TRY(c, e);
+                }
+                HIP_TRY(c, hipGraphLaunch(ex, st));
+            } else {
+                HIP_TRY(c, step(st, k0, true));
+            }
+            launched = std::max(launched, k1 + 1);
+            HIP_TRY(c, hipMemcpyAsync(c->h_ndone + ch, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipEventRecord(c->ev_poll[ch], st));
+            if (ch >= 1) {
+                HIP_TRY(c, hipEventSynchronize(c->ev_poll[ch - 1]));
+                if (c->h_ndone[ch - 1] >= wng) break;
             }
         }
         if (mixed) {
