@@ -183,6 +183,27 @@ int32_t smx_set_convergence(smx_ctx ctx, double tol, int32_t max_iter,
 int32_t smx_set_graph(smx_ctx ctx, int32_t steps_per_graph);
 
 /*
+ * Launch order of the product tiles: 0 (default) deals each group's tiles to
+ * one XCD (its L2), groups balanced over the 8 XCDs by work; 1 launches the
+ * tiles group by group.  Takes effect at the next plan build.
+ */
+int32_t smx_set_tile_order(smx_ctx ctx, int32_t order);
+
+/*
+ * Autotuner.  Times whole evaluations of the loaded problem (current
+ * precision, groups and mu) for every candidate launch configuration, the
+ * tile launch order (smx_set_tile_order) x steps per graph (0, 2, 8;
+ * smx_set_graph): one untimed run per candidate, then the minimum device time
+ * of `reps` runs.  It applies the fastest and returns it (outputs nullable).
+ * If the environment variable SMX_TUNE_CACHE names a file, the choice is
+ * appended there as "key graph_steps tile_order ms", keyed by device
+ * architecture, precision and the batch shape.  With use_cache != 0 a matching
+ * record is applied without timing.  Invalidates results.
+ */
+int32_t smx_autotune(smx_ctx ctx, int32_t reps, int32_t use_cache, int32_t *graph_steps_out,
+                     int32_t *tile_order_out, double *best_ms_out);
+
+/*
  * Device work space.  The dense submatrices are processed in waves of
  * consecutive groups; all groups of a wave are resident together (three FP64
  * n_pad x n_pad slabs per group, the reduced-precision word planes laid over

@@ -66,6 +66,8 @@ SIGNATURES = {
     "smx_set_convergence": (_i32, [_vp, _f64, _i32, _i32, _f64]),
     "smx_set_workspace_limit": (_i32, [_vp, _i64]),
     "smx_set_graph": (_i32, [_vp, _i32]),
+    "smx_set_tile_order": (_i32, [_vp, _i32]),
+    "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
     "smx_wait": (_i32, [_vp]),
     "smx_get_d": (_i32, [_vp, _vp, _i32]),
@@ -214,6 +216,18 @@ def smx_set_workspace_limit(ctx, nbytes=0):
 
 def smx_set_graph(ctx, steps_per_graph=0):
     return _check(ctx, load_library().smx_set_graph(ctx, int(steps_per_graph)))
+
+
+def smx_set_tile_order(ctx, order=0):
+    return _check(ctx, load_library().smx_set_tile_order(ctx, int(order)))
+
+
+def smx_autotune(ctx, reps=3, use_cache=True):
+    """Time the candidate launch configurations; returns (graph_steps, tile_order, best_ms)."""
+    g, o, ms = _i32(), _i32(), _f64()
+    _check(ctx, load_library().smx_autotune(ctx, int(reps), int(bool(use_cache)), ctypes.byref(g),
+                                            ctypes.byref(o), ctypes.byref(ms)))
+    return g.value, o.value, ms.value
 
 
 def smx_evaluate(ctx):

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <new>
@@ -125,6 +126,7 @@ struct smx_context {
     // device: work
     DevBuf<double> d_arena;                 // one wave's slabs (see kArenaBytesPerElem)
     int64_t ws_limit = 0;                   // arena byte limit (0: from free device memory)
+    int32_t tile_order = 0;                 // 0: XCD-aware launch order, 1: group by group
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
@@ -395,7 +397,7 @@ int32_t partition_waves(smx_ctx c, int64_t budget)
         }
         P.work_elems = std::max(P.work_elems, e);
         P.thin_elems = std::max(P.thin_elems, t);
-        xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
+        if (c->tile_order == 0) xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
         P.tiles.insert(P.tiles.end(), tl.begin(), tl.end());
         P.tile_beg.push_back((int64_t)P.tiles.size());
         while (ch < P.chunks.size() && P.chunks[ch].x < P.wave_g[w + 1]) ch++;
@@ -915,6 +917,19 @@ int32_t smx_set_graph(smx_ctx c, int32_t steps_per_graph)
     if (int32_t st = set_device(c)) return st;
     if (steps_per_graph != c->graph_steps) drop_graphs(c);
     c->graph_steps = steps_per_graph;
+    return SMX_OK;
+}
+
+int32_t smx_set_tile_order(smx_ctx c, int32_t order)
+{
+    if (!c) return SMX_E_INVALID;
+    if (order != 0 && order != 1) return fail(c, SMX_E_INVALID, "order must be 0 (XCD-aware) or 1 (group by group)");
+    if (order != c->tile_order) {
+        c->tile_order = order;
+        c->plan_dirty = true;
+        c->evaluated = false;
+        c->contrib_ready = false;
+    }
     return SMX_OK;
 }
 
@@ -1460,6 +1475,100 @@ int32_t smx_dn_dmu(smx_ctx c, double *out)
     double v[2];
     HIP_TRY(c, hipMemcpy(v, c->d_dn.p, sizeof v, hipMemcpyDeviceToHost));
     *out = -0.5 * v[0];
+    return SMX_OK;
+}
+
+// Key of a tuning record: device, precision and the shape of the batch
+// (groups, waves, sum and maximum of n_pad, work sum n_pad^3).
+static std::string tune_key(smx_ctx c)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "gpu";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+    for (char &ch : dev)
+        if (ch == ' ' || ch == ':') ch = '_';
+    const Plan &P = c->plan;
+    double s1 = 0, s3 = 0;
+    for (const GroupDesc &d : P.gd) {
+        s1 += d.npad;
+        s3 += (double)d.npad * d.npad * d.npad;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|p%d|g%d|w%d|n%.0f|m%d|c%.4e", dev.c_str(), c->precision, P.ngroups, P.nwaves(),
+                  s1, P.max_npad, s3);
+    return buf;
+}
+
+int32_t smx_autotune(smx_ctx c, int32_t reps, int32_t use_cache, int32_t *graph_steps_out, int32_t *tile_order_out,
+                     double *best_ms_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (reps < 1 || reps > 100) return fail(c, SMX_E_INVALID, "reps must be 1..100");
+    if (int32_t st = set_device(c)) return st;
+    if (int32_t st = ensure_plan(c)) return st;
+    const char *path = std::getenv("SMX_TUNE_CACHE");
+    std::string key = tune_key(c);
+    int32_t best_g = -1, best_o = -1;
+    double best = INFINITY;
+    if (use_cache && path) {
+        if (FILE *f = std::fopen(path, "r")) {
+            char line[512];
+            while (std::fgets(line, sizeof line, f)) {
+                char k[320];
+                int g, o;
+                double ms;
+                if (std::sscanf(line, "%319s %d %d %lf", k, &g, &o, &ms) == 4 && key == k && g >= 0 && g <= 64 &&
+                    (o == 0 || o == 1)) {
+                    best_g = g;
+                    best_o = o;
+                    best = ms;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    const bool from_cache = best_g >= 0;
+    if (!from_cache) {
+        // candidates: launch order x step graphs; each timed by device time of whole evaluations
+        const int32_t orders[2] = {0, 1};
+        const int32_t graphs[3] = {0, 2, 8};
+        const int32_t keep_g = c->graph_steps, keep_o = c->tile_order;
+        for (int32_t o : orders)
+            for (int32_t g : graphs) {
+                if (int32_t st = smx_set_tile_order(c, o)) return st;
+                if (int32_t st = smx_set_graph(c, g)) return st;
+                double tmin = INFINITY;
+                for (int32_t r = 0; r <= reps; r++) {      // the first run captures graphs / warms up
+                    int32_t st = smx_evaluate(c);
+                    if (st == SMX_OK) st = smx_wait(c);
+                    if (st != SMX_OK && st != SMX_E_NOT_CONVERGED) {
+                        (void)smx_set_tile_order(c, keep_o);
+                        (void)smx_set_graph(c, keep_g);
+                        return st;
+                    }
+                    smx_stats sst;
+                    if (int32_t e = smx_get_stats(c, &sst)) return e;
+                    if (r > 0) tmin = std::min(tmin, sst.time_total_ms);
+                }
+                if (tmin < best) {
+                    best = tmin;
+                    best_g = g;
+                    best_o = o;
+                }
+            }
+        if (path)
+            if (FILE *f = std::fopen(path, "a")) {
+                std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), best_g, best_o, best);
+                std::fclose(f);
+            }
+    }
+    if (int32_t st = smx_set_tile_order(c, best_o)) return st;
+    if (int32_t st = smx_set_graph(c, best_g)) return st;
+    c->evaluated = false;
+    if (graph_steps_out) *graph_steps_out = best_g;
+    if (tile_order_out) *tile_order_out = best_o;
+    if (best_ms_out) *best_ms_out = best;
     return SMX_OK;
 }
 

@@ -82,3 +82,38 @@ def test_graph_with_waves_and_mu_search(smx):
         ctx.close()
     same(res[0][0], res[1][0])
     assert res[0][1] == res[1][1]
+
+
+def test_tile_order_does_not_change_results(smx):
+    s = random_block_system(14, [17, 9, 31, 4, 22, 13, 8, 27, 19, 11, 6, 25, 14], density=0.6,
+                            coupling=0.04, groups="pairs", mu=0.01)
+    out = []
+    for order in (0, 1):
+        ctx = smx.Context(0).load(s).configure(precision="fp16x2")
+        smx.smx_set_tile_order(ctx.handle, order)
+        out.append(evaluate(ctx))
+        ctx.close()
+    same(out[0], out[1])
+
+
+def test_autotune_picks_a_configuration_and_caches_it(smx, tmp_path, monkeypatch):
+    cache = tmp_path / "smx_tune.txt"
+    monkeypatch.setenv("SMX_TUNE_CACHE", str(cache))
+    s = water_config("water16")
+    ref_ctx = smx.Context(0).load(s).configure(precision="fp64")
+    ref = evaluate(ref_ctx)
+    ref_ctx.close()
+    ctx = smx.Context(0).load(s).configure(precision="fp64")
+    g, o, ms = smx.smx_autotune(ctx.handle, reps=2, use_cache=False)
+    print(f"water16 fp64 autotune: graph_steps {g}, tile order {o}, {ms:.3f} ms")
+    assert g in (0, 2, 8) and o in (0, 1) and ms > 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:3] == [str(g), str(o)]
+    same(evaluate(ctx), ref)
+    # a second context reads the record instead of timing again
+    ctx2 = smx.Context(0).load(s).configure(precision="fp64")
+    assert smx.smx_autotune(ctx2.handle, reps=2, use_cache=True)[:2] == (g, o)
+    assert len(cache.read_text().splitlines()) == 1
+    same(evaluate(ctx2), ref)
+    ctx.close()
+    ctx2.close()
