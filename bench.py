@@ -96,7 +96,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
         step()
         ms, fl, kd = ctx.launch_profile()
         for m, f, k in zip(ms, fl, kd):
-            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else "ns_words_kernel"
+            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else ("ns_f32_kernel" if precision == "fp32" else "ns_words_kernel")
             e = prof.setdefault(key, [0.0, 0.0, 0])
             e[0] += m
             e[1] += f
@@ -114,7 +114,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
         step()
         ms, fl, kd = ctx.launch_profile()
         for m, f, k in zip(ms, fl, kd):
-            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else "ns_words_kernel"
+            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else ("ns_f32_kernel" if precision == "fp32" else "ns_words_kernel")
             e = prof.setdefault(key, [0.0, 0.0, 0])
             e[0] += m
             e[1] += f
@@ -125,8 +125,10 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
 
 DTYPES = {"fp64": "f64", "fp16x2": "f16x2 words, f32 accumulation; f64 polish",
           "bf16x3": "bf16x3 words, f32 accumulation; f64 polish",
-          "bf16": "bf16 words, f32 accumulation; f64 polish"}
-PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf16", 2516.6)}
+          "bf16": "bf16 words, f32 accumulation; f64 polish",
+          "fp32": "f32, f32 accumulation; f64 polish"}
+PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf16", 2516.6),
+                  "ns_f32_kernel": ("fp32", 157.3)}
 
 # HBM bytes per launch of the dominant kernel on water1024, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the

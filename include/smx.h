@@ -72,8 +72,8 @@ extern "C" {
                              products, FP32 accumulation), then FP64 polish     */
 #define SMX_BF16_1W   2   /* bulk products in plain BF16 (FP32 accumulation),
                              then FP64 polish                                    */
-#define SMX_FP32      3   /* bulk products in FP32 (MFMA f32), then FP64 polish
-                             (not implemented on the GPU path: SMX_E_UNSUPPORTED) */
+#define SMX_FP32      3   /* bulk products in FP32 (MFMA f32 16x16x4, FP32
+                             accumulation), then FP64 polish                    */
 #define SMX_FP16_2W   4   /* bulk products as 2-word FP16 splits (3 MFMA f16
                              products, FP32 accumulation), then FP64 polish     */
 
@@ -146,7 +146,7 @@ int32_t smx_set_mu(smx_ctx ctx, double mu);
  * implemented on the GPU; kT > 0 makes smx_evaluate return SMX_E_UNSUPPORTED. */
 int32_t smx_set_temperature(smx_ctx ctx, double kT);
 
-/* One of SMX_FP64, SMX_BF16_3W, SMX_BF16_1W, SMX_FP32. */
+/* One of SMX_FP64, SMX_BF16_3W, SMX_BF16_1W, SMX_FP32, SMX_FP16_2W. */
 int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
 
 /*

@@ -956,6 +956,7 @@ int32_t smx_evaluate(smx_ctx c)
     case SMX_FP16_2W: fmt = 0; nw = 2; break;
     case SMX_BF16_3W: fmt = 1; nw = 3; break;
     case SMX_BF16_1W: fmt = 1; nw = 1; break;
+    case SMX_FP32: fmt = 2; nw = 2; break;       // one FP32 value = two 16-bit storage units
     default: return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented on the GPU path");
     }
     const bool mixed = fmt >= 0;

@@ -425,6 +425,233 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     }
 }
 
+// FP32 products (v_mfma_f32_16x16x4_f32, FP32 accumulation): the iterate is
+// held as one FP32 value per element.  Same tiling, symmetry use, LDS loads
+// (32 k = 128 B per column and step, chunks swizzled over eight positions),
+// stopping rule and epilogue as the word products.
+__device__ inline int swz8(int col) { return (col >> 1) & 7; }
+
+__host__ __device__ constexpr int f32_lds_bytes()
+{
+    return (2 * BM * BK * 4) > (BM * CSTH * 4) ? (2 * BM * BK * 4) : (BM * CSTH * 4);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256, 2)
+void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
+                   const float *__restrict__ xin, const float *__restrict__ bin,
+                   float *__restrict__ out, IterState it, int k, double switch_tol, int kmax)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char smem[f32_lds_bytes()];
+    __shared__ double wsum[4];
+    float *Ls = reinterpret_cast<float *>(smem);                     // [2 operands][BM][BK]
+    float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
+
+    const TileDesc td = tiles[blockIdx.x];
+    const int g = td.x;
+    if (g < 0) return;                  // idle slot of the launch order
+    if (it.done[g]) return;
+    const int ti = td.y >> 16, tj = td.y & 0xffff;
+    const GroupDesc gd = groups[g];
+    const int ld = gd.npad;
+
+    if (MODE == 1) {
+        const int64_t base = (int64_t)g * it.resid_stride;
+        const double rk = __longlong_as_double((long long)it.resid_bits[base + k]);
+        const int nt = (ld + BM - 1) / BM;
+        double tau = 0.0;
+        for (int t = 0; t < nt; t++) tau += it.tau_parts[(int64_t)g * it.tau_nt + t];
+        const double tp = k > 0 ? it.tau_hist[base + k - 1] : __builtin_huge_val();
+        const bool finite = (rk <= 1.7976931348623157e308) && (fabs(tau) <= 1.7976931348623157e308);
+        // floor of the word format: tau stops halving in the quadratic phase, or
+        // stops falling at all (in the linear phase every 1 - x_i^2 shrinks)
+        const bool stall = ((tau < 0.1) && (tau > 0.5 * tp)) || (tau >= tp);
+        if (ti == 0 && tj == 0 && threadIdx.x == 0) it.tau_hist[base + k] = tau;
+        if (tau <= switch_tol || stall || k >= kmax || !finite) {
+            if (ti == 0 && tj == 0 && threadIdx.x == 0) {
+                it.done[g] = 1;
+                it.kfinal[g] = k;
+                it.flags[g] = finite ? 0 : 2;
+                atomicAdd(it.ndone, 1);
+            }
+            return;
+        }
+    }
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+
+    // Loads: one wave instruction fills 1 KB of LDS = 8 columns x 128 B (32
+    // floats); lane l fills slot l % 8 of column (wave + 4 q) * 8 + l / 8 with
+    // chunk (slot ^ swz8(column)) of that column.  Columns beyond ld read any
+    // valid address instead (their products only reach discarded outputs).
+    constexpr int PH = BM * BK;         // floats per operand region
+    const float *srcA[4], *srcB[4];
+    int kcoff[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int cl = (wave + 4 * q) * 8 + lane / 8;
+        kcoff[q] = ((lane % 8) ^ swz8(cl)) * 4;
+        srcA[q] = xin + gd.off + (int64_t)(ti * BM + cl < ld ? ti * BM + cl : 0) * ld;
+        srcB[q] = bin + gd.off + (int64_t)(tj * BM + cl < ld ? tj * BM + cl : 0) * ld;
+    }
+
+    const int row_w = ti * BM + wr * 64, col_w = tj * BM + wc * 64;
+    const bool wave_live = (row_w < ld) && (col_w < ld) && !(ti == tj && wr < wc);
+
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = ld / BK;             // ld is a multiple of 32
+    for (int kt = 0; kt < nk; kt++) {
+        const int k0 = kt * BK;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            float *dA = Ls + 0 * PH + (wave + 4 * q) * 8 * BK;
+            float *dB = Ls + 1 * PH + (wave + 4 * q) * 8 * BK;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(srcA[q] + k0 + kcoff[q]),
+                                             (__attribute__((address_space(3))) void *)dA, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(srcB[q] + k0 + kcoff[q]),
+                                             (__attribute__((address_space(3))) void *)dB, 16, 0, 0);
+        }
+        wait_vm0();
+        lds_barrier();                  // every wave's loads of this step are in LDS
+        if (wave_live) {
+            // two halves of 16 k; lane group lg holds k = 16 h + 4 lg + (0..3), and
+            // product j takes component j: the same permutation of k on both sides
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                f4 bv[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) {
+                    const int cb = wc * 64 + jj * 16 + li;
+                    bv[jj] = *reinterpret_cast<const f4 *>(Ls + 1 * PH + cb * BK + (((h * 4 + lg) ^ swz8(cb)) * 4));
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int ca = wr * 64 + i * 16 + li;
+                    const f4 av = *reinterpret_cast<const f4 *>(Ls + 0 * PH + ca * BK + (((h * 4 + lg) ^ swz8(ca)) * 4));
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+#pragma unroll
+                        for (int jj = 0; jj < 4; jj++)
+                            acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[jj][j], acc[i][jj], 0, 0, 0);
+                }
+            }
+        }
+        lds_barrier();                  // every wave is done reading before the next loads land
+    }
+
+    // ---- epilogue, in two rounds over the column halves h of the tile (the
+    // waves with wc == h hold them).  Lane l, register v of block (i, j) holds
+    // row 16 i + 4 (l / 16) + v and column 16 j + l % 16 of the wave's tile.
+    const int n = gd.n;
+    const bool diag = (ti == tj);
+    float *og = out + gd.off;
+    float rmax = 0.f;
+    double dsum = 0.0;
+    auto value = [&](float t, int r, int c) -> float {
+        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
+    };
+    for (int h = 0; h < 2; h++) {
+        if (wave_live && wc == h) {
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    *reinterpret_cast<f4 *>(&Cs[(j * 16 + li) * CST + wr * 64 + i * 16 + lg * 4]) = acc[i][j];
+        }
+        __syncthreads();
+        // the tile's own positions: unit (column cl of the half, 8-row chunk rc);
+        // 8-row chunks above the diagonal of a diagonal tile are the mirror's
+#pragma unroll 2
+        for (int q = 0; q < 4; q++) {
+            const int u = tid + 256 * q;
+            const int rc = u & 15, cl = u >> 4;
+            const int c = tj * BM + h * 64 + cl, r0 = ti * BM + rc * 8;
+            if (c >= ld || r0 >= ld) continue;
+            if (diag && r0 + 7 < c) continue;
+            float v[8];
+            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8]);
+            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8 + 4]);
+            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int r = r0 + e;
+                const float t = v[e];
+                if (MODE == 0 && r < n && c < n && r >= c) {
+                    float d = fabsf(t - (r == c ? 1.f : 0.f));
+                    if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
+                    rmax = fmaxf(rmax, d);
+                    if (r == c) dsum += 1.0 - (double)t;
+                }
+                v[e] = value(t, r, c);
+            }
+            *reinterpret_cast<f4 *>(og + r0 + (int64_t)c * ld) = f4{v[0], v[1], v[2], v[3]};
+            *reinterpret_cast<f4 *>(og + r0 + 4 + (int64_t)c * ld) = f4{v[4], v[5], v[6], v[7]};
+        }
+        __syncthreads();                // Cs reads done; direct stores precede the mirror's
+        if (wave_live && wc == h) {
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++)
+                        Cs[(wr * 64 + i * 16 + lg * 4 + v) * CSTH + j * 16 + li] = acc[i][j][v];
+        }
+        __syncthreads();
+        // mirror: tile element (rl, cl) goes to (cl, rl) of the matrix; unit (tile
+        // row rl, 8-column chunk cc); in a diagonal tile only positions above
+        // the diagonal
+#pragma unroll 2
+        for (int q = 0; q < 4; q++) {
+            const int u = tid + 256 * q;
+            const int cc = u & 7, rl = u >> 3;
+            const int r = ti * BM + rl, c0 = tj * BM + h * 64 + cc * 8;
+            if (r >= ld || c0 >= ld) continue;
+            if (diag && c0 >= r) continue;
+            float v[8];
+            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8]);
+            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8 + 4]);
+            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = value(v[e], r, c0 + e);
+            if (!diag || c0 + 8 <= r) {
+                *reinterpret_cast<f4 *>(og + c0 + (int64_t)r * ld) = f4{v[0], v[1], v[2], v[3]};
+                *reinterpret_cast<f4 *>(og + c0 + 4 + (int64_t)r * ld) = f4{v[4], v[5], v[6], v[7]};
+            } else {
+                for (int e = 0; c0 + e < r; e++) og[c0 + e + (int64_t)r * ld] = v[e];
+            }
+        }
+        __syncthreads();
+    }
+
+    if (MODE == 0) {
+        double rm = (double)rmax;
+        rm = wave_max(rm);
+        if (lane == 0)
+            atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
+        if (diag) {
+            // fixed-order reduction of the diagonal partials: lanes, then waves
+            for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+            if (lane == 0) wsum[wave] = dsum;
+            __syncthreads();
+            if (tid == 0) it.tau_parts[(int64_t)g * it.tau_nt + ti] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+        }
+    }
+}
+
+
 // X_0 words = split(a A), a = 1/s_g (the Gershgorin prescaling), one group per blockIdx.y.
 template <int FMT, int NW>
 __global__ __launch_bounds__(256)
@@ -460,6 +687,33 @@ void words_to_f64_kernel(const GroupDesc *__restrict__ groups, const unsigned sh
     }
 }
 
+// X_0 in FP32 = a A, a = 1/s_g; and the FP64 copy of the FP32 bulk result.
+__global__ __launch_bounds__(256)
+void f64_to_f32_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ src,
+                       const unsigned long long *__restrict__ scale_bits, float *__restrict__ dst, int g0)
+{
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
+    const int64_t tot = (int64_t)gd.npad * gd.npad;
+    const double s = __longlong_as_double((long long)scale_bits[g]);
+    const double a = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        dst[gd.off + e] = (float)(a * src[gd.off + e]);
+}
+
+__global__ __launch_bounds__(256)
+void f32_to_f64_kernel(const GroupDesc *__restrict__ groups, const float *__restrict__ x0,
+                       const float *__restrict__ x1, const int32_t *__restrict__ kfinal, double *__restrict__ dst,
+                       int g0)
+{
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
+    const int64_t tot = (int64_t)gd.npad * gd.npad;
+    const float *src = ((kfinal[g] & 1) ? x1 : x0) + gd.off;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        dst[gd.off + e] = (double)src[e];
+}
+
 template <int FMT, int NW>
 hipError_t launch_words_t(hipStream_t st, int mode, int ntiles, const TileDesc *tiles, const GroupDesc *groups,
                           const unsigned short *x, const unsigned short *b, unsigned short *out, int64_t plane,
@@ -482,6 +736,17 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
                            int kmax)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (fmt == 2) {
+        const float *xf = reinterpret_cast<const float *>(x), *bf = reinterpret_cast<const float *>(b);
+        float *of = reinterpret_cast<float *>(out);
+        if (mode == 0)
+            hipLaunchKernelGGL(ns_f32_kernel<0>, dim3(ntiles), dim3(256), 0, st, tiles, groups, xf, bf, of, it, k,
+                               switch_tol, kmax);
+        else
+            hipLaunchKernelGGL(ns_f32_kernel<1>, dim3(ntiles), dim3(256), 0, st, tiles, groups, xf, bf, of, it, k,
+                               switch_tol, kmax);
+        return hipGetLastError();
+    }
     if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
     if (fmt == 0 && nw == 2) return launch_words_t<0, 2>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
     if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
@@ -496,7 +761,10 @@ hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups,
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
 #define SMX_TW(F, N) hipLaunchKernelGGL((f64_to_words_kernel<F, N>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane, g0)
-    if (fmt == 0 && nw == 1) SMX_TW(0, 1);
+    if (fmt == 2)
+        hipLaunchKernelGGL(f64_to_f32_kernel, grid, dim3(256), 0, st, groups, src, scale_bits,
+                           reinterpret_cast<float *>(dst), g0);
+    else if (fmt == 0 && nw == 1) SMX_TW(0, 1);
     else if (fmt == 0 && nw == 2) SMX_TW(0, 2);
     else if (fmt == 1 && nw == 1) SMX_TW(1, 1);
     else if (fmt == 1 && nw == 3) SMX_TW(1, 3);
@@ -513,7 +781,10 @@ hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroup
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
 #define SMX_FW(F, N) hipLaunchKernelGGL((words_to_f64_kernel<F, N>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst, g0)
-    if (fmt == 0 && nw == 1) SMX_FW(0, 1);
+    if (fmt == 2)
+        hipLaunchKernelGGL(f32_to_f64_kernel, grid, dim3(256), 0, st, groups, reinterpret_cast<const float *>(x0),
+                           reinterpret_cast<const float *>(x1), kfinal, dst, g0);
+    else if (fmt == 0 && nw == 1) SMX_FW(0, 1);
     else if (fmt == 0 && nw == 2) SMX_FW(0, 2);
     else if (fmt == 1 && nw == 1) SMX_FW(1, 1);
     else if (fmt == 1 && nw == 3) SMX_FW(1, 3);

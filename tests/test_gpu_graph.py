@@ -34,7 +34,7 @@ def same(a, b):
     np.testing.assert_array_equal(ia["resid"], ib["resid"])
 
 
-@pytest.mark.parametrize("precision,steps", [("fp64", 1), ("fp64", 4), ("fp16x2", 3), ("bf16x3", 5)])
+@pytest.mark.parametrize("precision,steps", [("fp64", 1), ("fp64", 4), ("fp16x2", 3), ("bf16x3", 5), ("fp32", 2)])
 def test_graph_replays_equal_direct_launches(smx, oracle_lib, precision, steps):
     s = water_config("water16")
     direct = smx.Context(0).load(s).configure(precision=precision)

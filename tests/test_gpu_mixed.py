@@ -1,7 +1,7 @@
 """GPU parity of the reduced-precision paths against the FP64 CPU oracle.
 
 Bar: max|D_gpu - D_oracle| <= 1e-6 for the modes meant to meet it (2-word
-FP16 and 3-word BF16 bulk, FP64 polish).  The tolerance follows from the
+FP16, 3-word BF16 and FP32 bulk, FP64 polish).  The tolerance follows from the
 arithmetic: FP32 accumulation of exact word products injects ~1e-7 relative
 noise per product; the occupied-virtual part of that noise is not removed by
 later steps (it is amplified by up to 1.5 per step while the eigenvalues near
@@ -42,7 +42,7 @@ def max_err(res, ref):
     return float(np.abs(res.d_values[ok] - ref.d_values[ok]).max())
 
 
-@pytest.mark.parametrize("precision", ["fp16x2", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp16x2", "bf16x3", "fp32"])
 def test_water16_mixed_matches_oracle(smx, oracle_lib, precision):
     s = water_config("water16")
     res, info, stats = run(smx, s, precision)
@@ -78,9 +78,10 @@ def test_water16_bf16_single_word_is_reported(smx, oracle_lib):
 ])
 def test_random_systems_mixed(smx, oracle_lib, seed, sizes, dens, groups):
     s = random_block_system(seed, sizes, density=dens, coupling=0.04, groups=groups, mu=0.01)
-    res, _, _ = run(smx, s, "fp16x2")
     ref = oracle_lib.submatrix(s)
-    assert max_err(res, ref) <= TOL_MIXED
+    for precision in ("fp16x2", "fp32"):
+        res, _, _ = run(smx, s, precision)
+        assert max_err(res, ref) <= TOL_MIXED, precision
 
 
 def test_mixed_polish_count_and_determinism(smx, oracle_lib):
