@@ -226,11 +226,17 @@ class GroupSpectra:
     """Eigenpairs of every group's unshifted submatrix K[R(g), R(g)] and the
     own-column weights w_gl = sum_{c in own(g)} Q_cl^2 of Algorithm 1."""
 
-    def __init__(self, s, groups=None, values=None):
+    def __init__(self, s, groups=None, values=None, nthreads=1):
         self.groups = list(range(s.ngroups)) if groups is None else list(groups)
         self.lam, self.w, self.q, self.rows = [], [], [], []
-        for g in self.groups:
-            rows, lam, q, _ = group_eig(s, g, mu=0.0, values=values)
+        if nthreads > 1:
+            # independent groups; the C calls release the GIL
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(nthreads) as ex:
+                eigs = list(ex.map(lambda g: group_eig(s, g, mu=0.0, values=values), self.groups))
+        else:
+            eigs = [group_eig(s, g, mu=0.0, values=values) for g in self.groups]
+        for g, (rows, lam, q, _) in zip(self.groups, eigs):
             sizes = s.blk_size[rows]
             off = np.concatenate([[0], np.cumsum(sizes)])
             pos = {int(b): off[t] for t, b in enumerate(rows)}

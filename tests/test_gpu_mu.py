@@ -81,3 +81,27 @@ def test_find_mu_reaches_target(smx, oracle_lib):
     n_or = spec.n_frozen(mu, info["iters"], info["scale"])
     print(f"water16 mu search: mu* = {mu:.10f} in {steps} evaluations; oracle N_k(mu*) - N_e = {n_or - target:.2e}")
     assert abs(n_or - target) <= 1e-8 + 1e-9
+
+
+@pytest.mark.timeout(300)
+def test_find_mu_water256(smx):
+    """The 256-molecule system: mu search to N_e = n/2 within 1e-8 on the
+    frozen map.  The oracle pin of N_k(mu*) is the water16 case above (the
+    Jacobi eigenpairs of all 256 groups take minutes); here the search's frozen
+    map is evaluated again at mu*, its slope must be positive, and central
+    differences of it must match that slope."""
+    s = water_config("water256")
+    ctx = smx.Context(0).load(s).configure(precision="fp64")
+    target = s.n / 2
+    mu, steps = smx.smx_find_mu(ctx.handle, target, 1e-8, 60)
+    # the search's last evaluation ran the frozen map at mu*: freeze it again
+    smx.smx_set_frozen(ctx.handle, True)
+    n0, d0 = n_and_slope(smx, ctx, mu)
+    h = 1e-5
+    fd = (n_and_slope(smx, ctx, mu + h)[0] - n_and_slope(smx, ctx, mu - h)[0]) / (2 * h)
+    ctx.close()
+    print(f"water256 mu search: mu* = {mu:.10f} in {steps} evaluations; N_k(mu*) - N_e = {n0 - target:.2e}, "
+          f"dN/dmu = {d0:.6f} (central difference {fd:.6f})")
+    assert d0 > 0
+    assert abs(fd - d0) <= 1e-5 * abs(d0)
+    assert abs(n0 - target) <= 1e-8 + 1e-9
