@@ -134,9 +134,9 @@ PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf1
 # counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the
 # figure is valid only while the kernel's sources hash to the recorded value.
 TRAFFIC = {
-    ("water1024", "ns_words_kernel"): (8.702e9, ("smx_ns_words.hip", "smx_internal.h"), "3cf0730487e0c8de",
+    ("water1024", "ns_words_kernel"): (8.419e9, ("smx_ns_words.hip", "smx_internal.h"), "f7fa8eef4a4bc764",
                                        "profiles/ns_words_kernel_water1024_fp16x2.md"),
-    ("water1024", "ns_f64_kernel"): (17.527e9, ("smx_ns_f64.hip", "smx_internal.h"), "bedb4ed27e5f1da5",
+    ("water1024", "ns_f64_kernel"): (17.477e9, ("smx_ns_f64.hip", "smx_internal.h"), "223b690c5455152d",
                                      "profiles/ns_f64_kernel_water1024_fp64.md"),
 }
 
