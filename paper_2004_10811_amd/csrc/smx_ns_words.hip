@@ -163,7 +163,7 @@ __device__ inline void split8(const float *v, u16x8 *wv)
 // no register staging) in K steps of 32: per operand and word plane a
 // [128 columns][32] halves region, 64 B per column, whose four 16-B chunks are
 // XOR-swizzled by column so that the matrix-core operand reads (16 columns x
-// one chunk) hit all 64 banks.  One stage per workgroup: the operand traffic
+// one chunk) are free of bank conflicts.  One stage per workgroup: the operand traffic
 // of one workgroup overlaps the products of the others on the CU.  The
 // epilogue stages half of the FP32 tile at a time in LDS, column-major for
 // the tile itself and row-major for its mirror, so that 16 consecutive lanes
@@ -173,7 +173,11 @@ constexpr int CPC = BK / 8;        // 16-B chunks per column, word plane and K s
 constexpr int CST = 132;           // column-major staging: 528-B columns (conflict-free f4 stores)
 constexpr int CSTH = 68;           // row-major staging of a 64-column half
 
-__device__ inline int swz(int col) { return (col >> 2) & 3; }
+// Slot of chunk 0 of a column: every 8 consecutive columns, and the even and
+// the odd columns of every 16, get distinct slots, so a 16-B operand read of
+// 16 consecutive columns is free of bank conflicts whether the LDS serves
+// 8 lanes per cycle from 32 banks or 16 lanes from 64.
+__device__ inline int swz(int col) { return (col ^ (col >> 2)) & 3; }
 
 // s_waitcnt vmcnt(0) (the gfx9 encoding with expcnt and lgkmcnt left at their maxima)
 __device__ inline void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -186,6 +190,18 @@ __device__ inline void lds_barrier()
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
+}
+
+// Eight staged floats as two 16-B reads; lanes 4-7 of every 8 read their
+// second half first, so the first read of 8 lanes covers 32 distinct banks.
+__device__ inline void load8(const float *p, int swap, float *v)
+{
+    const int o = swap ? 4 : 0;
+    const f4 a = *reinterpret_cast<const f4 *>(p + o);
+    const f4 b = *reinterpret_cast<const f4 *>(p + (4 - o));
+    const f4 lo = swap ? b : a, hi = swap ? a : b;
+    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
 }
 
 template <int NW>
@@ -345,10 +361,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (c >= ld || r0 >= ld) continue;
             if (diag && r0 + 7 < c) continue;
             float v[8];
-            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8]);
-            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8 + 4]);
-            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            load8(&Cs[cl * CST + rc * 8], rc & 4, v);
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int r = r0 + e;
@@ -389,10 +402,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (r >= ld || c0 >= ld) continue;
             if (diag && c0 >= r) continue;
             float v[8];
-            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8]);
-            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8 + 4]);
-            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            load8(&Cs[rl * CSTH + cc * 8], cc & 4, v);
 #pragma unroll
             for (int e = 0; e < 8; e++) v[e] = value(v[e] * inv_s2, r, c0 + e) * sc;
             u16x8 wv[NW];
@@ -429,7 +439,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
 // held as one FP32 value per element.  Same tiling, symmetry use, LDS loads
 // (32 k = 128 B per column and step, chunks swizzled over eight positions),
 // stopping rule and epilogue as the word products.
-__device__ inline int swz8(int col) { return (col >> 1) & 7; }
+__device__ inline int swz8(int col) { return (col ^ (col >> 3)) & 7; }
 
 __host__ __device__ constexpr int f32_lds_bytes()
 {
@@ -579,10 +589,7 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             if (c >= ld || r0 >= ld) continue;
             if (diag && r0 + 7 < c) continue;
             float v[8];
-            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8]);
-            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[cl * CST + rc * 8 + 4]);
-            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            load8(&Cs[cl * CST + rc * 8], rc & 4, v);
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int r = r0 + e;
@@ -620,10 +627,7 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             if (r >= ld || c0 >= ld) continue;
             if (diag && c0 >= r) continue;
             float v[8];
-            const f4 v0 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8]);
-            const f4 v1 = *reinterpret_cast<const f4 *>(&Cs[rl * CSTH + cc * 8 + 4]);
-            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            load8(&Cs[rl * CSTH + cc * 8], cc & 4, v);
 #pragma unroll
             for (int e = 0; e < 8; e++) v[e] = value(v[e], r, c0 + e);
             if (!diag || c0 + 8 <= r) {
