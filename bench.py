@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--full-sign", action="store_true",
                     help="also report the error against the exact sign of the whole K (dense eigendecomposition; "
                          "done by default up to 8000 basis functions)")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the Newton-Schulz steps from HIP graphs of this many steps (0: direct launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -239,6 +241,24 @@ def main():
     if args.precision != "fp64":
         run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, args.graph_steps)
         d_out = d_mix
+    backward = None
+    if args.backward:
+        # dE/dK through the frozen map of one evaluation in the timed precision
+        ctx.configure(precision=args.precision, graph_steps=0)
+        smx.smx_evaluate(ctx.handle)
+        smx.smx_wait(ctx.handle)
+        dk = torch.empty(ctx.nvalues, dtype=torch.float64, device="cuda")
+        smx.smx_backward(ctx.handle, 1.0, 0.0, None, dk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            smx.smx_backward(ctx.handle, 1.0, 0.0, None, dk)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t0) / args.steps * 1e3
+        backward = {"what": "dE/dK and dE/dmu, FP64 adjoint through the frozen map (checkpoints every 8 steps)",
+                    "ms_per_backward": bms, "backward_over_forward": bms / run["ms_per_step"],
+                    "max_abs_dK": float(dk.abs().max().item())}
+        progress(f"backward: {bms:.1f} ms per call")
     ctx.close()
 
     stats = run["stats"]
@@ -304,6 +324,8 @@ def main():
         "E_band": run["energy"],
         "roofline": roofline,
     }
+    if backward is not None:
+        out["backward"] = backward
 
     if args.full_sign or system.n <= 8000:
         progress(f"exact sign of the whole K ({system.n} x {system.n})")
