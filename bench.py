@@ -158,26 +158,50 @@ PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf1
 # HBM bytes per launch of the dominant kernel on water1024, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the
 # figure is valid only while the kernel's sources hash to the recorded value.
+# The same runs give the matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES
+# over 1024 SIMDs x 2.4 GHz x kernel time).
 TRAFFIC = {
     ("water1024", "ns_words_kernel"): (8.419e9, ("smx_ns_words.hip", "smx_internal.h"), "f7fa8eef4a4bc764",
-                                       "profiles/ns_words_kernel_water1024_fp16x2.md"),
+                                       "profiles/ns_words_kernel_water1024_fp16x2.md", 0.272),
     ("water1024", "ns_f64_kernel"): (17.477e9, ("smx_ns_f64.hip", "smx_internal.h"), "223b690c5455152d",
-                                     "profiles/ns_f64_kernel_water1024_fp64.md"),
+                                     "profiles/ns_f64_kernel_water1024_fp64.md", 0.678),
 }
 
 
 def measured_traffic(workload, kernel):
-    """Counter-measured HBM bytes per launch, or None if absent or the kernel changed since."""
+    """Counter-measured (HBM bytes per launch, source, MFMA busy fraction), or Nones if
+    absent or the kernel changed since the counters were taken."""
     import hashlib
     ent = TRAFFIC.get((workload, kernel))
     if ent is None:
-        return None, None
-    nbytes, files, digest, src = ent
+        return None, None, None
+    nbytes, files, digest, src, busy = ent
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2004_10811_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return (nbytes, src) if h.hexdigest()[:16] == digest else (None, None)
+    return (nbytes, src, busy) if h.hexdigest()[:16] == digest else (None, None, None)
+
+
+def d_asymmetry(system, d_values):
+    """max |D_IJ - D_JI^T| over the stored blocks (D is not symmetrised)."""
+    bs = system.blk_size.astype(np.int64)
+    cols = np.repeat(np.arange(system.nblk), np.diff(system.col_ptr))
+    rows = system.row_idx.astype(np.int64)
+    voff = system.val_off()
+    key = rows * system.nblk + cols
+    order = np.argsort(key)
+    mirror = order[np.searchsorted(key[order], cols * system.nblk + rows)]
+    worst = 0.0
+    for bi in np.unique(bs):
+        for bj in np.unique(bs):
+            sel = np.nonzero((bs[rows] == bi) & (bs[cols] == bj))[0]
+            if sel.size == 0:
+                continue
+            a = d_values[voff[sel][:, None] + np.arange(bi * bj)[None, :]].reshape(-1, bj, bi)
+            m = d_values[voff[mirror[sel]][:, None] + np.arange(bi * bj)[None, :]].reshape(-1, bi, bj)
+            worst = max(worst, float(np.abs(a - m.transpose(0, 2, 1)).max()))
+    return worst
 
 
 def main():
@@ -268,7 +292,7 @@ def main():
     kname, (kms, kfl, kn) = max(run["prof"].items(), key=lambda kv: kv[1][0])
     pdt, peak = PEAK_BY_KERNEL[kname]
     achieved = kfl / (kms * 1e-3) / 1e12
-    traffic, traffic_src = measured_traffic(args.workload, kname)
+    traffic, traffic_src, busy = measured_traffic(args.workload, kname)
     roofline = {
         "bound": "mfma",
         "achieved": achieved,
@@ -278,6 +302,7 @@ def main():
         "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-calibrated)",
         "traffic_source": traffic_src,
+        "mfma_busy_counter": busy,
         "kernel": kname,
         "peak_dtype": pdt,
         "launches": kn,
@@ -327,9 +352,11 @@ def main():
     if backward is not None:
         out["backward"] = backward
 
+    d_host = d_out.cpu().numpy()
+    out["max_abs_D_minus_DT"] = d_asymmetry(system, d_host)
     if args.full_sign or system.n <= 8000:
         progress(f"exact sign of the whole K ({system.n} x {system.n})")
-        out["vs_full_matrix_sign"] = full_sign_report(system, d_out.cpu().numpy(), run["n_elec"], run["energy"])
+        out["vs_full_matrix_sign"] = full_sign_report(system, d_host, run["n_elec"], run["energy"])
     else:
         out["vs_full_matrix_sign"] = f"not computed: dense eigendecomposition of a {system.n} x {system.n} matrix " \
                                      "(use --full-sign)"
