@@ -197,3 +197,35 @@ def test_water1024_sampled_groups_match_oracle(smx, oracle_lib):
     assert abs(res.n_elec - s.n / 2) < 0.05 * s.ngroups
     print(f"water1024 sampled {sorted(pick)}: max|dD| = {err:.2e}; "
           f"iters {stats['iters_min']}-{stats['iters_max']}; time {stats['time_total_ms']:.1f} ms")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp16x2", 1e-6), ("fp32", 1e-6)])
+def test_large_single_submatrix_dimerized_chain(smx, precision, tol):
+    """One group holding every block column of a dense-pattern K: the submatrix is
+    K itself (n = 2600, 21 tile rows, ragged last tile), so D is the exact density
+    matrix, here from a dense LAPACK eigendecomposition.  A dimerized chain
+    (hoppings -1.0 / -0.6) has the gap [-0.4, 0.4] at mu = 0, so the 1e-6 bar of
+    the reduced-precision modes applies."""
+    from waterbox import dense_to_bsc
+    n, blk = 2600, 26
+    h = np.zeros((n, n))
+    hop = np.where(np.arange(n - 1) % 2 == 0, -1.0, -0.6)
+    h[np.arange(n - 1), np.arange(1, n)] = hop
+    h[np.arange(1, n), np.arange(n - 1)] = hop
+    nb = n // blk
+    s = dense_to_bsc(h, [blk] * nb, np.ones((nb, nb), dtype=bool), groups=[list(range(nb))], mu=0.0)
+    lam, q = np.linalg.eigh(h)
+    d_exact = q[:, lam < 0] @ q[:, lam < 0].T
+    ctx = smx.Context(0).load(s).configure(precision=precision)
+    res = ctx.evaluate()
+    ctx.close()
+    voff = s.val_off()
+    err = 0.0
+    for j in range(nb):
+        for p in range(int(s.col_ptr[j]), int(s.col_ptr[j + 1])):
+            i = int(s.row_idx[p])
+            blk_ref = d_exact[i * blk:(i + 1) * blk, j * blk:(j + 1) * blk].T.reshape(-1)
+            err = max(err, float(np.abs(res.d_values[voff[p]:voff[p + 1]] - blk_ref).max()))
+    print(f"dimerized chain n = {n}, {precision}: max|dD| = {err:.2e}, N = {res.n_elec:.10f}")
+    assert err <= tol
+    assert abs(res.n_elec - n / 2) <= tol * n
