@@ -163,6 +163,7 @@ struct smx_context {
     int32_t last_stride = 0;
     int32_t last_polish = 0;             // FP64 polish steps after the bulk (0 in FP64 mode)
     int32_t last_max_iter = 0;
+    int32_t last_fmt = -1, last_nw = 0;        // storage of the reduced-precision bulk
     bool use_kfix = false, use_sfix = false;  // frozen step counts / scales
     bool have_tangent = false;                 // last evaluation computed dN/dmu
     bool last_sfix = false;                    // last evaluation ran on the frozen scales
@@ -604,7 +605,7 @@ int32_t need_sync_results(smx_ctx c)
 // p-times polished sign are A_p(E), E the own-column selector (A_0(E) is a
 // gather).  Thin blocks come from a pool of 2p + 1; the residual
 // max|X_{k+p-1}^2 E - E| is taken on the innermost square of the last step.
-int32_t own_polish(smx_ctx c, int32_t g0, int32_t wng, const double *x, const IterState &it, int32_t *result)
+int32_t own_polish(smx_ctx c, int32_t g0, int32_t wng, const XSource &x, const IterState &it, int32_t *result)
 {
     const Plan &P = c->plan;
     hipStream_t st = c->stream;
@@ -1158,11 +1159,11 @@ int32_t smx_evaluate(smx_ctx c)
             }
         }
         if (mixed) {
-            // FP64 polish on the own columns: X_{k+p} E from the bulk result X
-            HIP_TRY(c, launch_from_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, wb[0], wb[1], it.kfinal, plane,
-                                         xb[0]));
+            // FP64 polish on the own columns: X_{k+p} E from the bulk result X,
+            // read from its words (converted exactly on the fly)
+            const XSource xs{nullptr, wb[0], wb[1], it.kfinal, plane, fmt, nw};
             int32_t res = -1;
-            if (int32_t e = own_polish(c, g0, wng, xb[0], it, &res)) return e;
+            if (int32_t e = own_polish(c, g0, wng, xs, it, &res)) return e;
             thin_result = c->d_tpool.p + (size_t)res * (size_t)P.thin_elems;
         }
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
@@ -1187,6 +1188,8 @@ int32_t smx_evaluate(smx_ctx c)
     c->last_precision = c->precision;
     c->last_stride = stride;
     c->last_polish = mixed ? c->n_polish : 0;
+    c->last_fmt = fmt;
+    c->last_nw = nw;
     c->last_max_iter = c->max_iter;
     c->evaluated = true;
     return SMX_OK;
@@ -1420,8 +1423,13 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         dch.release();
         src = slab(c, 2) + d.off;
     } else if (c->last_polish) {
-        // reduced-precision modes: the bulk's last iterate in FP64 (the
-        // polish steps are computed on the own columns only)
+        // reduced-precision modes: the bulk's last iterate, converted to FP64
+        // from its words (the polish steps are computed on the own columns only)
+        const int64_t plane = P.work_elems;
+        const unsigned short *w0 = reinterpret_cast<const unsigned short *>(slab(c, 1));
+        const unsigned short *w1 = w0 + (size_t)c->last_nw * plane;
+        HIP_TRY(c, launch_from_words(c->stream, c->last_fmt, c->last_nw, g, 1, d.npad, c->d_gd.p, w0, w1,
+                                     c->d_kfinal.p, plane, slab(c, 0)));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         src = slab(c, 0) + d.off;
     } else {

@@ -117,12 +117,24 @@ hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroup
 
 // Last polish step restricted to the own columns (FP64, vector ALU):
 //   O = P[:, own];  Y = P O (residual of P^2 on the own columns -> slot);  F = 1.5 O - 0.5 P Y.
+// Where the own-column polish reads the bulk result X of each group: an FP64
+// slab (fmt < 0), or the storage of the reduced-precision bulk (fmt 0 FP16 /
+// 1 BF16 words, nw of them; fmt 2 one FP32 value) in the buffer of the group's
+// final step: w1 when kfinal[g] is odd, else w0 (plane = elements per word plane).
+struct XSource {
+    const double *f64;
+    const unsigned short *w0, *w1;
+    const int32_t *kfinal;
+    int64_t plane;
+    int fmt, nw;
+};
+
 // Own-column polish: out = X[:, own]; y = X z (mode 0) or 1.5 o - 0.5 X z (mode 1);
 // c = 1.5 a - 0.5 c; max |b - E| into the residual slot.
 hipError_t launch_own_gather(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                             const int32_t *own_list, const double *x, double *out);
+                             const int32_t *own_list, const XSource &xs, double *out);
 hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
-                           const GroupDesc *groups, const double *x, const double *z, const double *o, double *y);
+                           const GroupDesc *groups, const XSource &xs, const double *z, const double *o, double *y);
 hipError_t launch_thin_combine(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
                                const GroupDesc *groups, const double *a, double *c);
 hipError_t launch_thin_resid(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,

@@ -150,15 +150,68 @@ void scatter_kernel(int64_t nblocks, const int64_t *__restrict__ plist, const Sc
 // dimension n_pad), so the p FP64 steps cost 3^p - 1 passes over X instead
 // of 2p dense products.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256)
-void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list,
-                       const double *__restrict__ p, double *__restrict__ o, int g0)
+// The polish reads the bulk result X where the bulk left it: an FP64 slab, or
+// the word planes (FP16 / BF16 words, or FP32 values) of the group's final
+// bulk step, converted on the fly to exactly the FP64 value the words stand
+// for (sum of the words over the power-of-two scale).
+enum XKind { X_F64 = 0, X_F16x2 = 1, X_BF16x3 = 2, X_BF16x1 = 3, X_F32 = 4 };
+
+__device__ inline double f16w(unsigned short w) { return (double)(float)__builtin_bit_cast(_Float16, w); }
+__device__ inline double bf16w(unsigned short w) { return (double)__builtin_bit_cast(float, ((unsigned int)w) << 16); }
+
+// Base of group g's bulk result, in elements of the storage type.
+template <int K>
+__device__ inline const void *x_base(const XSource &xs, const GroupDesc &gd, int g)
 {
-    const GroupDesc gd = groups[g0 + blockIdx.y];
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    if constexpr (K == X_F64) {
+        return xs.f64 + gd.off;
+    } else if constexpr (K == X_F32) {
+        const unsigned short *w = (xs.kfinal[g] & 1) ? xs.w1 : xs.w0;
+        return reinterpret_cast<const float *>(w) + gd.off;
+    } else {
+        return ((xs.kfinal[g] & 1) ? xs.w1 : xs.w0) + gd.off;
+    }
+}
+
+// X[e] and X[e + 1] (e even: two consecutive rows of one column).
+template <int K>
+__device__ inline d2v x_pair(const void *base, int64_t plane, int64_t e)
+{
+    if constexpr (K == X_F64) {
+        return *reinterpret_cast<const d2v *>(reinterpret_cast<const double *>(base) + e);
+    } else if constexpr (K == X_F32) {
+        const float2 f = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(base) + e);
+        return d2v{(double)f.x, (double)f.y};
+    } else {
+        const unsigned short *w = reinterpret_cast<const unsigned short *>(base);
+        constexpr int NW = K == X_F16x2 ? 2 : (K == X_BF16x3 ? 3 : 1);
+        d2v v = {0.0, 0.0};
+#pragma unroll
+        for (int q = NW - 1; q >= 0; q--) {
+            const unsigned int u = *reinterpret_cast<const unsigned int *>(w + q * plane + e);
+            const unsigned short lo = (unsigned short)(u & 0xffffu), hi = (unsigned short)(u >> 16);
+            v.x += K == X_F16x2 ? f16w(lo) : bf16w(lo);
+            v.y += K == X_F16x2 ? f16w(hi) : bf16w(hi);
+        }
+        if constexpr (K == X_F16x2) v *= (1.0 / 32768.0);
+        return v;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256)
+void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__restrict__ own_list, XSource xs,
+                       double *__restrict__ o, int g0)
+{
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
+    const int r = 2 * (blockIdx.x * 256 + threadIdx.x);
     if (r >= gd.npad) return;
-    for (int c = 0; c < gd.m_own; c++)
-        o[gd.thin_off + r + (int64_t)c * gd.npad] = p[gd.off + r + (int64_t)own_list[gd.own_off + c] * gd.npad];
+    const void *xb = x_base<K>(xs, gd, g);
+    for (int c = 0; c < gd.m_own; c++) {
+        const d2v v = x_pair<K>(xb, xs.plane, r + (int64_t)own_list[gd.own_off + c] * gd.npad);
+        *reinterpret_cast<d2v *>(o + gd.thin_off + r + (int64_t)c * gd.npad) = v;
+    }
 }
 
 // MODE 0: y = X z.  MODE 1: y = 1.5 o - 0.5 X z.  X is symmetric; a lane owns
@@ -167,21 +220,22 @@ void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__re
 // columns per pass; z is staged in LDS 128 rows at a time, row-major, so that
 // one broadcast 16-B read gives two columns.  Rows k >= n of X and z are not needed: X[r, k] = 0 for
 // r < n <= k, and rows r >= n of the result are exactly zero.
-template <int MODE, int MW>
+template <int MODE, int MW, int K>
 __global__ __launch_bounds__(256)
-void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ x,
+void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                      const double *__restrict__ z, const double *__restrict__ o, double *__restrict__ y, int g0)
 {
     constexpr int KC = 128;                           // rows of z per LDS stage
     constexpr int U = 8;                              // rows of X in flight per lane
     __shared__ __attribute__((aligned(16))) double zs[KC][MW + 2];
-    const GroupDesc gd = groups[g0 + blockIdx.y];
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
     const int npad = gd.npad;
     const int row0 = blockIdx.x * 512;
     if (row0 >= npad) return;                         // whole block beyond this group
     const int r = row0 + 2 * (int)threadIdx.x;        // rows r, r + 1 (npad is even)
     const bool live = r < npad;
-    const double *xg = x + gd.off;
+    const void *xg = x_base<K>(xs, gd, g);
     for (int c0 = 0; c0 < gd.m_own; c0 += MW) {
         const int nc = min(MW, gd.m_own - c0);
         d2v acc[MW];
@@ -197,13 +251,12 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restr
             __syncthreads();
             const int kend = min(KC, gd.n - k0);
             if (live) {
-                const double *xp = xg + r + (int64_t)k0 * npad;
+                const int64_t e0 = r + (int64_t)k0 * npad;
                 int kk = 0;
                 for (; kk + U <= kend; kk += U) {
                     d2v xv[U];
 #pragma unroll
-                    for (int u = 0; u < U; u++)
-                        xv[u] = *reinterpret_cast<const d2v *>(xp + (int64_t)(kk + u) * npad);
+                    for (int u = 0; u < U; u++) xv[u] = x_pair<K>(xg, xs.plane, e0 + (int64_t)(kk + u) * npad);
 #pragma unroll
                     for (int u = 0; u < U; u++)
 #pragma unroll
@@ -216,7 +269,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, const double *__restr
                         }
                 }
                 for (; kk < kend; kk++) {
-                    const d2v xv = *reinterpret_cast<const d2v *>(xp + (int64_t)kk * npad);
+                    const d2v xv = x_pair<K>(xg, xs.plane, e0 + (int64_t)kk * npad);
 #pragma unroll
                     for (int c = 0; c < MW; c += 2) {
                         const d2v zv = *reinterpret_cast<const d2v *>(&zs[kk][c]);
@@ -423,22 +476,39 @@ hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const int64_t *plist,
     return hipGetLastError();
 }
 
+static int x_kind(const XSource &xs)
+{
+    if (xs.fmt < 0) return X_F64;
+    if (xs.fmt == 2) return X_F32;
+    if (xs.fmt == 0 && xs.nw == 2) return X_F16x2;
+    if (xs.fmt == 1 && xs.nw == 3) return X_BF16x3;
+    if (xs.fmt == 1 && xs.nw == 1) return X_BF16x1;
+    return -1;
+}
+
 hipError_t launch_own_gather(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                             const int32_t *own_list, const double *x, double *out)
+                             const int32_t *own_list, const XSource &xs, double *out)
 {
     if (ngroups <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((max_npad + 255) / 256), (unsigned)ngroups);
-    hipLaunchKernelGGL(own_gather_kernel, grid, dim3(256), 0, st, groups, own_list, x, out, g0);
+    const dim3 grid((unsigned)((max_npad / 2 + 255) / 256), (unsigned)ngroups);
+#define SMX_OG(K) hipLaunchKernelGGL((own_gather_kernel<K>), grid, dim3(256), 0, st, groups, own_list, xs, out, g0)
+    switch (x_kind(xs)) {
+    case X_F64: SMX_OG(X_F64); break;
+    case X_F16x2: SMX_OG(X_F16x2); break;
+    case X_BF16x3: SMX_OG(X_BF16x3); break;
+    case X_BF16x1: SMX_OG(X_BF16x1); break;
+    case X_F32: SMX_OG(X_F32); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_OG
     return hipGetLastError();
 }
 
-hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
-                           const GroupDesc *groups, const double *x, const double *z, const double *o, double *y)
+template <int K>
+static hipError_t thin_mul_k(hipStream_t st, int mode, int mw, dim3 grid, int g0, const GroupDesc *groups,
+                             const XSource &xs, const double *z, const double *o, double *y)
 {
-    if (ngroups <= 0 || max_own <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((max_npad + 511) / 512), (unsigned)ngroups);
-#define SMX_TM(M, W) hipLaunchKernelGGL((thin_mul_kernel<M, W>), grid, dim3(256), 0, st, groups, x, z, o, y, g0)
-    const int mw = max_own <= 8 ? 8 : (max_own <= 16 ? 16 : (max_own <= 24 ? 24 : 32));
+#define SMX_TM(M, W) hipLaunchKernelGGL((thin_mul_kernel<M, W, K>), grid, dim3(256), 0, st, groups, xs, z, o, y, g0)
     if (mode == 0) {
         if (mw == 8) SMX_TM(0, 8); else if (mw == 16) SMX_TM(0, 16); else if (mw == 24) SMX_TM(0, 24); else SMX_TM(0, 32);
     } else {
@@ -446,6 +516,22 @@ hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int ma
     }
 #undef SMX_TM
     return hipGetLastError();
+}
+
+hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
+                           const GroupDesc *groups, const XSource &xs, const double *z, const double *o, double *y)
+{
+    if (ngroups <= 0 || max_own <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_npad + 511) / 512), (unsigned)ngroups);
+    const int mw = max_own <= 8 ? 8 : (max_own <= 16 ? 16 : (max_own <= 24 ? 24 : 32));
+    switch (x_kind(xs)) {
+    case X_F64: return thin_mul_k<X_F64>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    case X_F16x2: return thin_mul_k<X_F16x2>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    case X_BF16x3: return thin_mul_k<X_BF16x3>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    case X_BF16x1: return thin_mul_k<X_BF16x1>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    case X_F32: return thin_mul_k<X_F32>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_thin_combine(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
