@@ -161,10 +161,10 @@ PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf1
 # The same runs give the matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES
 # over 1024 SIMDs x 2.4 GHz x kernel time).
 TRAFFIC = {
-    ("water1024", "ns_words_kernel"): (8.419e9, ("smx_ns_words.hip", "smx_internal.h"), "f7fa8eef4a4bc764",
-                                       "profiles/ns_words_kernel_water1024_fp16x2.md", 0.272),
-    ("water1024", "ns_f64_kernel"): (17.477e9, ("smx_ns_f64.hip", "smx_internal.h"), "223b690c5455152d",
-                                     "profiles/ns_f64_kernel_water1024_fp64.md", 0.678),
+    ("water1024", "ns_words_kernel"): (8.403e9, ("smx_ns_words.hip", "smx_internal.h"), "43f5fce2346d2657",
+                                       "profiles/ns_words_kernel_water1024_fp16x2.md", 0.275),
+    ("water1024", "ns_f64_kernel"): (17.439e9, ("smx_ns_f64.hip", "smx_internal.h"), "af0a3896c1ca0e75",
+                                     "profiles/ns_f64_kernel_water1024_fp64.md", 0.684),
 }
 
 
