@@ -1099,7 +1099,7 @@ int32_t smx_evaluate(smx_ctx c)
                                  xb[0], gather_scale));
         if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, c->d_gd.p, it.scale_bits, tb[0]));
         if (mixed)
-            HIP_TRY(c, launch_to_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, xb[0], it.scale_bits, wb[0], plane));
+            HIP_TRY(c, launch_to_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, xb[0], it.scale_bits, wb[0]));
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
         // one Newton-Schulz step of the wave on stream s (timed: HIP events around
         // each product launch; not inside a graph capture)
@@ -1117,10 +1117,10 @@ int32_t smx_evaluate(smx_ctx c)
                                                           it, k, c->tol, c->max_iter, 0); });
             } else {
                 e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, ntiles, tl, c->d_gd.p, wb[k & 1], wb[k & 1], wwp,
-                                                        plane, it, k, c->switch_tol, kmax); });
+                                                        it, k, c->switch_tol, kmax); });
                 if (e == hipSuccess)
                     e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, ntiles, tl, c->d_gd.p, wb[k & 1], wwp,
-                                                            wb[(k + 1) & 1], plane, it, k, c->switch_tol, kmax); });
+                                                            wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
             }
             return e;
         };
@@ -1161,7 +1161,7 @@ int32_t smx_evaluate(smx_ctx c)
         if (mixed) {
             // FP64 polish on the own columns: X_{k+p} E from the bulk result X,
             // read from its words (converted exactly on the fly)
-            const XSource xs{nullptr, wb[0], wb[1], it.kfinal, plane, fmt, nw};
+            const XSource xs{nullptr, wb[0], wb[1], it.kfinal, fmt, nw};
             int32_t res = -1;
             if (int32_t e = own_polish(c, g0, wng, xs, it, &res)) return e;
             thin_result = c->d_tpool.p + (size_t)res * (size_t)P.thin_elems;
@@ -1429,7 +1429,7 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         const unsigned short *w0 = reinterpret_cast<const unsigned short *>(slab(c, 1));
         const unsigned short *w1 = w0 + (size_t)c->last_nw * plane;
         HIP_TRY(c, launch_from_words(c->stream, c->last_fmt, c->last_nw, g, 1, d.npad, c->d_gd.p, w0, w1,
-                                     c->d_kfinal.p, plane, slab(c, 0)));
+                                     c->d_kfinal.p, slab(c, 0)));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         src = slab(c, 0) + d.off;
     } else {

@@ -102,30 +102,38 @@ hipError_t launch_gather_t(hipStream_t st, int64_t nblocks, const int64_t *cptr,
 hipError_t launch_diag_part(hipStream_t st, int ngroups, const GroupDesc *groups,
                             const unsigned long long *scale_bits, const double *xb, double *part);
 
-// Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value).
+// Word storage of the reduced-precision iterates (nw 16-bit words per value):
+// group g's words start at element nw * off of an operand buffer; inside them
+// column c holds its 32-row blocks one after another, and a block holds word 0
+// of its 32 rows, then word 1, ...  So one K step of 32 of a product reads the
+// nw words of a column as one contiguous nw * 64-B run (a whole 128-B line for
+// two FP16 words).  Position of word 0 of element (r, c); word w is 32 w further.
+__host__ __device__ inline int64_t word_pos(int nw, int ld, int r, int c)
+{
+    return (int64_t)c * ld * nw + (int64_t)(r >> 5) * (32 * nw) + (r & 31);
+}
+
+// Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value;
+// fmt 2 = one FP32 value per element, column-major like the FP64 slabs).
 hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
-                           unsigned short *out, int64_t plane, const IterState &it, int k, double switch_tol,
-                           int kmax);
+                           unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
 // Group-walking launchers take the first group g0 and the count ngroups (a wave).
 hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                           const double *src, const unsigned long long *scale_bits, unsigned short *dst,
-                           int64_t plane);
+                           const double *src, const unsigned long long *scale_bits, unsigned short *dst);
 hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                             const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal,
-                             int64_t plane, double *dst);
+                             const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal, double *dst);
 
 // Last polish step restricted to the own columns (FP64, vector ALU):
 //   O = P[:, own];  Y = P O (residual of P^2 on the own columns -> slot);  F = 1.5 O - 0.5 P Y.
 // Where the own-column polish reads the bulk result X of each group: an FP64
 // slab (fmt < 0), or the storage of the reduced-precision bulk (fmt 0 FP16 /
 // 1 BF16 words, nw of them; fmt 2 one FP32 value) in the buffer of the group's
-// final step: w1 when kfinal[g] is odd, else w0 (plane = elements per word plane).
+// final step: w1 when kfinal[g] is odd, else w0.
 struct XSource {
     const double *f64;
     const unsigned short *w0, *w1;
     const int32_t *kfinal;
-    int64_t plane;
     int fmt, nw;
 };
 

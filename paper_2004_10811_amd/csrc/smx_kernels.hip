@@ -159,6 +159,9 @@ enum XKind { X_F64 = 0, X_F16x2 = 1, X_BF16x3 = 2, X_BF16x1 = 3, X_F32 = 4 };
 __device__ inline double f16w(unsigned short w) { return (double)(float)__builtin_bit_cast(_Float16, w); }
 __device__ inline double bf16w(unsigned short w) { return (double)__builtin_bit_cast(float, ((unsigned int)w) << 16); }
 
+template <int K>
+__device__ constexpr int x_nw() { return K == X_F16x2 ? 2 : (K == X_BF16x3 ? 3 : 1); }
+
 // Base of group g's bulk result, in elements of the storage type.
 template <int K>
 __device__ inline const void *x_base(const XSource &xs, const GroupDesc &gd, int g)
@@ -169,13 +172,28 @@ __device__ inline const void *x_base(const XSource &xs, const GroupDesc &gd, int
         const unsigned short *w = (xs.kfinal[g] & 1) ? xs.w1 : xs.w0;
         return reinterpret_cast<const float *>(w) + gd.off;
     } else {
-        return ((xs.kfinal[g] & 1) ? xs.w1 : xs.w0) + gd.off;
+        return ((xs.kfinal[g] & 1) ? xs.w1 : xs.w0) + (int64_t)x_nw<K>() * gd.off;
     }
 }
 
-// X[e] and X[e + 1] (e even: two consecutive rows of one column).
+// Offset of element (r, c) = x_row(r) + c * x_col_stride(ld) from the group's base.
 template <int K>
-__device__ inline d2v x_pair(const void *base, int64_t plane, int64_t e)
+__device__ inline int64_t x_row(int r)
+{
+    if constexpr (K == X_F64 || K == X_F32)
+        return r;
+    else
+        return (int64_t)(r >> 5) * (32 * x_nw<K>()) + (r & 31);
+}
+template <int K>
+__device__ inline int64_t x_col_stride(int ld)
+{
+    return (int64_t)ld * ((K == X_F64 || K == X_F32) ? 1 : x_nw<K>());
+}
+
+// X[r, c] and X[r + 1, c] (r even) at offset e = x_row(r) + c * x_col_stride(ld).
+template <int K>
+__device__ inline d2v x_pair(const void *base, int64_t e)
 {
     if constexpr (K == X_F64) {
         return *reinterpret_cast<const d2v *>(reinterpret_cast<const double *>(base) + e);
@@ -184,11 +202,11 @@ __device__ inline d2v x_pair(const void *base, int64_t plane, int64_t e)
         return d2v{(double)f.x, (double)f.y};
     } else {
         const unsigned short *w = reinterpret_cast<const unsigned short *>(base);
-        constexpr int NW = K == X_F16x2 ? 2 : (K == X_BF16x3 ? 3 : 1);
+        constexpr int NW = x_nw<K>();
         d2v v = {0.0, 0.0};
 #pragma unroll
         for (int q = NW - 1; q >= 0; q--) {
-            const unsigned int u = *reinterpret_cast<const unsigned int *>(w + q * plane + e);
+            const unsigned int u = *reinterpret_cast<const unsigned int *>(w + 32 * q + e);
             const unsigned short lo = (unsigned short)(u & 0xffffu), hi = (unsigned short)(u >> 16);
             v.x += K == X_F16x2 ? f16w(lo) : bf16w(lo);
             v.y += K == X_F16x2 ? f16w(hi) : bf16w(hi);
@@ -208,8 +226,9 @@ void own_gather_kernel(const GroupDesc *__restrict__ groups, const int32_t *__re
     const int r = 2 * (blockIdx.x * 256 + threadIdx.x);
     if (r >= gd.npad) return;
     const void *xb = x_base<K>(xs, gd, g);
+    const int64_t rp = x_row<K>(r), cs = x_col_stride<K>(gd.npad);
     for (int c = 0; c < gd.m_own; c++) {
-        const d2v v = x_pair<K>(xb, xs.plane, r + (int64_t)own_list[gd.own_off + c] * gd.npad);
+        const d2v v = x_pair<K>(xb, rp + (int64_t)own_list[gd.own_off + c] * cs);
         *reinterpret_cast<d2v *>(o + gd.thin_off + r + (int64_t)c * gd.npad) = v;
     }
 }
@@ -236,6 +255,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
     const int r = row0 + 2 * (int)threadIdx.x;        // rows r, r + 1 (npad is even)
     const bool live = r < npad;
     const void *xg = x_base<K>(xs, gd, g);
+    const int64_t rp = x_row<K>(r), cs = x_col_stride<K>(npad);
     for (int c0 = 0; c0 < gd.m_own; c0 += MW) {
         const int nc = min(MW, gd.m_own - c0);
         d2v acc[MW];
@@ -251,12 +271,12 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
             __syncthreads();
             const int kend = min(KC, gd.n - k0);
             if (live) {
-                const int64_t e0 = r + (int64_t)k0 * npad;
+                const int64_t e0 = rp + (int64_t)k0 * cs;
                 int kk = 0;
                 for (; kk + U <= kend; kk += U) {
                     d2v xv[U];
 #pragma unroll
-                    for (int u = 0; u < U; u++) xv[u] = x_pair<K>(xg, xs.plane, e0 + (int64_t)(kk + u) * npad);
+                    for (int u = 0; u < U; u++) xv[u] = x_pair<K>(xg, e0 + (int64_t)(kk + u) * cs);
 #pragma unroll
                     for (int u = 0; u < U; u++)
 #pragma unroll
@@ -269,7 +289,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                         }
                 }
                 for (; kk < kend; kk++) {
-                    const d2v xv = x_pair<K>(xg, xs.plane, e0 + (int64_t)kk * npad);
+                    const d2v xv = x_pair<K>(xg, e0 + (int64_t)kk * cs);
 #pragma unroll
                     for (int c = 0; c < MW; c += 2) {
                         const d2v zv = *reinterpret_cast<const d2v *>(&zs[kk][c]);

@@ -101,13 +101,13 @@ __host__ __device__ constexpr int pair_p(int i) { return i == 2 || i == 3 ? 1 : 
 __host__ __device__ constexpr int pair_q(int i) { return i == 1 || i == 3 ? 1 : (i == 4 ? 2 : 0); }
 
 template <int FMT, int NW>
-__device__ inline void split_store(unsigned short *o, int64_t plane, int64_t idx, double v)
+__device__ inline void split_store(unsigned short *o, double v)
 {
     double rem = v;
 #pragma unroll
     for (int w = 0; w < NW; w++) {
         const unsigned short u = to_word<FMT>(rem);
-        o[w * plane + idx] = u;
+        o[32 * w] = u;
         rem -= from_word<FMT>(u);
     }
 }
@@ -214,7 +214,7 @@ template <int FMT, int NW, int MODE>
 __global__ __launch_bounds__(256, 2)
 void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
                      const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
-                     unsigned short *__restrict__ out, int64_t plane, IterState it, int k,
+                     unsigned short *__restrict__ out, IterState it, int k,
                      double switch_tol, int kmax)
 {
     __shared__ __attribute__((aligned(16))) unsigned char smem[words_lds_bytes<NW>()];
@@ -272,8 +272,8 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     for (int q = 0; q < 2; q++) {
         const int cl = (wave + 4 * q) * 16 + lane / CPC;
         kcoff[q] = ((lane % CPC) ^ swz(cl)) * 8;
-        srcA[q] = xin + gd.off + (int64_t)(ti * BM + cl < ld ? ti * BM + cl : 0) * ld;
-        srcB[q] = bin + gd.off + (int64_t)(tj * BM + cl < ld ? tj * BM + cl : 0) * ld;
+        srcA[q] = xin + NW * gd.off + word_pos(NW, ld, 0, ti * BM + cl < ld ? ti * BM + cl : 0);
+        srcB[q] = bin + NW * gd.off + word_pos(NW, ld, 0, tj * BM + cl < ld ? tj * BM + cl : 0);
     }
 
     const int row_w = ti * BM + wr * 64, col_w = tj * BM + wc * 64;
@@ -295,10 +295,10 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                 unsigned short *dA = Ls + (0 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
                 unsigned short *dB = Ls + (1 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
                 __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(srcA[q] + w * plane + k0 + kcoff[q]),
+                    (const __attribute__((address_space(1))) void *)(srcA[q] + NW * k0 + 32 * w + kcoff[q]),
                     (__attribute__((address_space(3))) void *)dA, 16, 0, 0);
                 __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(srcB[q] + w * plane + k0 + kcoff[q]),
+                    (const __attribute__((address_space(1))) void *)(srcB[q] + NW * k0 + 32 * w + kcoff[q]),
                     (__attribute__((address_space(3))) void *)dB, 16, 0, 0);
             }
         wait_vm0();
@@ -336,7 +336,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     constexpr float sc = (float)word_scale<FMT>();
     const int n = gd.n;
     const bool diag = (ti == tj);
-    unsigned short *og = out + gd.off;
+    unsigned short *og = out + NW * gd.off;
     float rmax = 0.f;
     double dsum = 0.0;
     auto value = [&](float t, int r, int c) -> float {
@@ -378,7 +378,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             split8<FMT, NW>(v, wv);
 #pragma unroll
             for (int w = 0; w < NW; w++)
-                *reinterpret_cast<u16x8 *>(og + w * plane + r0 + (int64_t)c * ld) = wv[w];
+                *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, r0, c) + 32 * w) = wv[w];
         }
         __syncthreads();                // Cs reads done; direct stores precede the mirror's
         if (wave_live && wc == h) {
@@ -410,11 +410,11 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (!diag || c0 + 8 <= r) {
 #pragma unroll
                 for (int w = 0; w < NW; w++)
-                    *reinterpret_cast<u16x8 *>(og + w * plane + c0 + (int64_t)r * ld) = wv[w];
+                    *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, c0, r) + 32 * w) = wv[w];
             } else {
                 for (int e = 0; c0 + e < r; e++)
 #pragma unroll
-                    for (int w = 0; w < NW; w++) og[w * plane + c0 + e + (int64_t)r * ld] = wv[w][e];
+                    for (int w = 0; w < NW; w++) og[word_pos(NW, ld, c0, r) + 32 * w + e] = wv[w][e];
             }
         }
         __syncthreads();
@@ -656,39 +656,43 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
 }
 
 
-// X_0 words = split(a A), a = 1/s_g (the Gershgorin prescaling), one group per blockIdx.y.
+// X_0 words = split(a A), a = 1/s_g (the Gershgorin prescaling), one group per
+// blockIdx.y, columns over blockIdx.x, rows over the threads.
 template <int FMT, int NW>
 __global__ __launch_bounds__(256)
 void f64_to_words_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ src,
-                         const unsigned long long *__restrict__ scale_bits, unsigned short *__restrict__ dst,
-                         int64_t plane, int g0)
+                         const unsigned long long *__restrict__ scale_bits, unsigned short *__restrict__ dst, int g0)
 {
     const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
-    const int64_t tot = (int64_t)gd.npad * gd.npad;
+    const int ld = gd.npad;
     const double s = __longlong_as_double((long long)scale_bits[g]);
     const double a = s > 0.0 ? 1.0 / s : 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
-        split_store<FMT, NW>(dst + gd.off, plane, e, a * src[gd.off + e] * word_scale<FMT>());
+    unsigned short *d = dst + NW * gd.off;
+    for (int c = blockIdx.x; c < ld; c += gridDim.x)
+        for (int r = threadIdx.x; r < ld; r += 256)
+            split_store<FMT, NW>(d + word_pos(NW, ld, r, c), a * src[gd.off + r + (int64_t)c * ld] * word_scale<FMT>());
 }
 
-// fp64 copy of the bulk result X_kfinal (sum of its words), for the FP64 polish.
+// fp64 copy of the bulk result X_kfinal (sum of its words).
 template <int FMT, int NW>
 __global__ __launch_bounds__(256)
 void words_to_f64_kernel(const GroupDesc *__restrict__ groups, const unsigned short *__restrict__ x0,
                          const unsigned short *__restrict__ x1, const int32_t *__restrict__ kfinal,
-                         int64_t plane, double *__restrict__ dst, int g0)
+                         double *__restrict__ dst, int g0)
 {
     const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
-    const int64_t tot = (int64_t)gd.npad * gd.npad;
-    const unsigned short *src = ((kfinal[g] & 1) ? x1 : x0) + gd.off;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
-        double v = 0.0;
+    const int ld = gd.npad;
+    const unsigned short *src = ((kfinal[g] & 1) ? x1 : x0) + NW * gd.off;
+    for (int c = blockIdx.x; c < ld; c += gridDim.x)
+        for (int r = threadIdx.x; r < ld; r += 256) {
+            const unsigned short *p = src + word_pos(NW, ld, r, c);
+            double v = 0.0;
 #pragma unroll
-        for (int w = NW - 1; w >= 0; w--) v += from_word<FMT>(src[w * plane + e]);
-        dst[gd.off + e] = v * (1.0 / word_scale<FMT>());
-    }
+            for (int w = NW - 1; w >= 0; w--) v += from_word<FMT>(p[32 * w]);
+            dst[gd.off + r + (int64_t)c * ld] = v * (1.0 / word_scale<FMT>());
+        }
 }
 
 // X_0 in FP32 = a A, a = 1/s_g; and the FP64 copy of the FP32 bulk result.
@@ -720,15 +724,15 @@ void f32_to_f64_kernel(const GroupDesc *__restrict__ groups, const float *__rest
 
 template <int FMT, int NW>
 hipError_t launch_words_t(hipStream_t st, int mode, int ntiles, const TileDesc *tiles, const GroupDesc *groups,
-                          const unsigned short *x, const unsigned short *b, unsigned short *out, int64_t plane,
+                          const unsigned short *x, const unsigned short *b, unsigned short *out,
                           const IterState &it, int k, double switch_tol, int kmax)
 {
     if (mode == 0)
         hipLaunchKernelGGL((ns_words_kernel<FMT, NW, 0>), dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b, out,
-                           plane, it, k, switch_tol, kmax);
+                           it, k, switch_tol, kmax);
     else
         hipLaunchKernelGGL((ns_words_kernel<FMT, NW, 1>), dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b, out,
-                           plane, it, k, switch_tol, kmax);
+                           it, k, switch_tol, kmax);
     return hipGetLastError();
 }
 
@@ -736,8 +740,7 @@ hipError_t launch_words_t(hipStream_t st, int mode, int ntiles, const TileDesc *
 
 hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
-                           unsigned short *out, int64_t plane, const IterState &it, int k, double switch_tol,
-                           int kmax)
+                           unsigned short *out, const IterState &it, int k, double switch_tol, int kmax)
 {
     if (ntiles <= 0) return hipSuccess;
     if (fmt == 2) {
@@ -751,20 +754,21 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
                                switch_tol, kmax);
         return hipGetLastError();
     }
-    if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
-    if (fmt == 0 && nw == 2) return launch_words_t<0, 2>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
-    if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
-    if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, ntiles, tiles, groups, x, b, out, plane, it, k, switch_tol, kmax);
+    if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 0 && nw == 2) return launch_words_t<0, 2>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                           const double *src, const unsigned long long *scale_bits, unsigned short *dst, int64_t plane)
+                           const double *src, const unsigned long long *scale_bits, unsigned short *dst)
 {
     if (ngroups <= 0) return hipSuccess;
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-#define SMX_TW(F, N) hipLaunchKernelGGL((f64_to_words_kernel<F, N>), grid, dim3(256), 0, st, groups, src, scale_bits, dst, plane, g0)
+    const dim3 gridc((unsigned)std::min(max_npad, 4096), (unsigned)ngroups);   // one column per block
+#define SMX_TW(F, N) hipLaunchKernelGGL((f64_to_words_kernel<F, N>), gridc, dim3(256), 0, st, groups, src, scale_bits, dst, g0)
     if (fmt == 2)
         hipLaunchKernelGGL(f64_to_f32_kernel, grid, dim3(256), 0, st, groups, src, scale_bits,
                            reinterpret_cast<float *>(dst), g0);
@@ -778,13 +782,13 @@ hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups,
 }
 
 hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                             const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal, int64_t plane,
-                             double *dst)
+                             const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal, double *dst)
 {
     if (ngroups <= 0) return hipSuccess;
     const int64_t tot = (int64_t)max_npad * max_npad;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-#define SMX_FW(F, N) hipLaunchKernelGGL((words_to_f64_kernel<F, N>), grid, dim3(256), 0, st, groups, x0, x1, kfinal, plane, dst, g0)
+    const dim3 gridc((unsigned)std::min(max_npad, 4096), (unsigned)ngroups);   // one column per block
+#define SMX_FW(F, N) hipLaunchKernelGGL((words_to_f64_kernel<F, N>), gridc, dim3(256), 0, st, groups, x0, x1, kfinal, dst, g0)
     if (fmt == 2)
         hipLaunchKernelGGL(f32_to_f64_kernel, grid, dim3(256), 0, st, groups, reinterpret_cast<const float *>(x0),
                            reinterpret_cast<const float *>(x1), kfinal, dst, g0);
