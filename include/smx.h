@@ -206,7 +206,7 @@ int32_t smx_autotune(smx_ctx ctx, int32_t reps, int32_t use_cache, int32_t *grap
 /*
  * Device work space.  The dense submatrices are processed in waves of
  * consecutive groups; all groups of a wave are resident together (three FP64
- * n_pad x n_pad slabs per group, the reduced-precision word planes laid over
+ * n_pad x n_pad slabs per group, the reduced-precision words laid over
  * two of them, 26 bytes per element, plus 72 n_pad m_own bytes of own-column
  * blocks), and the waves reuse one arena.  bytes = 0 (the default) sizes the
  * waves to the free device memory at plan time, less the plan's tables and
