@@ -38,6 +38,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = kTile;   // 128
 
@@ -342,6 +343,97 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     auto value = [&](float t, int r, int c) -> float {
         return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
     };
+    if constexpr (NW <= 2) {
+        // One conversion per element: the pass over the tile's own positions
+        // splits every staged value into its words and writes them back in
+        // place, one 32-bit (w0 | w1 << 16) per element; the mirror pass then
+        // reads those words across the staging columns.  Staging is
+        // column-major with the row index XOR-swizzled in 16-B steps by column
+        // group of 8, so that the mirror's reads (8 rows x 8 columns per wave
+        // instruction) fall on 64 distinct banks.
+        auto cpos = [](int col, int row) { return col * CST + (row ^ (((col >> 3) & 7) << 2)); };
+        unsigned int *Cw = reinterpret_cast<unsigned int *>(Cs);
+        for (int h = 0; h < 2; h++) {
+            if (tj * BM + h * 64 >= ld) break;      // the half lies beyond the matrix
+            if (wave_live && wc == h) {
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        *reinterpret_cast<f4 *>(&Cs[cpos(j * 16 + li, wr * 64 + i * 16 + lg * 4)]) = acc[i][j];
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int q = 0; q < 4; q++) {
+                const int u = tid + 256 * q;
+                const int rc = u & 15, cl = u >> 4;
+                const int c = tj * BM + h * 64 + cl, r0 = ti * BM + rc * 8;
+                if (c >= ld || r0 >= ld) continue;
+                if (diag && r0 + 7 < c) continue;
+                // rows rc*8 .. +3 and +4 .. +7: two 16-B slots; lanes with rc & 4 read the second first
+                const int p0 = cpos(cl, rc * 8), p1 = cpos(cl, rc * 8 + 4);
+                const int sw = rc & 4;
+                const f4 fa = *reinterpret_cast<const f4 *>(Cs + (sw ? p1 : p0));
+                const f4 fb = *reinterpret_cast<const f4 *>(Cs + (sw ? p0 : p1));
+                const f4 lo = sw ? fb : fa, hi = sw ? fa : fb;
+                float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int r = r0 + e;
+                    const float t = v[e] * inv_s2;
+                    if (MODE == 0 && r < n && c < n && r >= c) {
+                        float d = fabsf(t - (r == c ? 1.f : 0.f));
+                        if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
+                        rmax = fmaxf(rmax, d);
+                        if (r == c) dsum += 1.0 - (double)t;
+                    }
+                    v[e] = value(t, r, c) * sc;
+                }
+                u16x8 wv[NW];
+                split8<FMT, NW>(v, wv);
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, r0, c) + 32 * w) = wv[w];
+                u4 pa, pb;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    pa[e] = (unsigned int)wv[0][e] | (NW == 2 ? ((unsigned int)wv[NW - 1][e] << 16) : 0u);
+                    pb[e] = (unsigned int)wv[0][e + 4] | (NW == 2 ? ((unsigned int)wv[NW - 1][e + 4] << 16) : 0u);
+                }
+                *reinterpret_cast<u4 *>(Cw + p0) = pa;
+                *reinterpret_cast<u4 *>(Cw + p1) = pb;
+            }
+            __syncthreads();                        // every element's words are staged
+            // mirror: tile element (rl, cl) goes to (cl, rl) of the matrix; unit (tile
+            // row rl, 8-column chunk cc); in a diagonal tile only positions above
+            // the diagonal
+#pragma unroll 2
+            for (int q = 0; q < 4; q++) {
+                const int u = tid + 256 * q;
+                const int cc = u & 7, rl = u >> 3;
+                const int r = ti * BM + rl, c0 = tj * BM + h * 64 + cc * 8;
+                if (r >= ld || c0 >= ld) continue;
+                if (diag && c0 >= r) continue;
+                u16x8 wv[NW];
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const unsigned int pk = Cw[cpos(cc * 8 + e, rl)];
+                    wv[0][e] = (unsigned short)(pk & 0xffffu);
+                    if constexpr (NW == 2) wv[NW - 1][e] = (unsigned short)(pk >> 16);
+                }
+                if (!diag || c0 + 8 <= r) {
+#pragma unroll
+                    for (int w = 0; w < NW; w++)
+                        *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, c0, r) + 32 * w) = wv[w];
+                } else {
+                    for (int e = 0; c0 + e < r; e++)
+#pragma unroll
+                        for (int w = 0; w < NW; w++) og[word_pos(NW, ld, c0, r) + 32 * w + e] = wv[w][e];
+                }
+            }
+            __syncthreads();                        // staging is free for the next half
+        }
+    } else
     for (int h = 0; h < 2; h++) {
         if (wave_live && wc == h) {
 #pragma unroll
