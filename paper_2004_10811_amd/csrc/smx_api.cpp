@@ -78,8 +78,8 @@ struct Plan {
 };
 
 // Arena of one wave: three FP64 slabs X_a | X_b | W (24 bytes per element);
-// in the reduced-precision modes the word planes of X_a, X_b and W start at
-// byte 8E (over X_b and W, dead during the bulk) and reach 8E + 6 nw E bytes,
+// in the reduced-precision modes the words of X_a, X_b and W (nw E 16-bit
+// words each) start at byte 8E (over X_b and W, dead during the bulk) and reach 8E + 6 nw E bytes,
 // i.e. 26 bytes per element with three BF16 words.
 constexpr int64_t kArenaBytesPerElem = 26;
 
@@ -993,7 +993,7 @@ int32_t smx_evaluate(smx_ctx c)
     }
     if (mixed) {
         HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1)));
-        // word planes from byte 8E to 8E + 6 nw E of the arena
+        // words of X_a, X_b and W from byte 8E to 8E + 6 nw E of the arena
         const size_t need = (size_t)((8 * P.work_elems + 6 * (int64_t)nw * P.work_elems + 7) / 8);
         if (c->d_arena.cap < need) HIP_TRY(c, c->d_arena.ensure(need));
     }
@@ -1058,12 +1058,12 @@ int32_t smx_evaluate(smx_ctx c)
         c->launch_wave.push_back(wave);
         return e;
     };
-    const int64_t plane = P.work_elems;
+    const int64_t welems = P.work_elems;        // an operand's words take nw * welems 16-bit units
     double *xb[2] = {slab(c, 0), slab(c, 1)};
     double *wslab = slab(c, 2);
     unsigned short *wbase = reinterpret_cast<unsigned short *>(slab(c, 1));
-    unsigned short *wb[2] = {wbase, wbase + (size_t)nw * plane};
-    unsigned short *wwp = wbase + (size_t)2 * nw * plane;
+    unsigned short *wb[2] = {wbase, wbase + (size_t)nw * welems};
+    unsigned short *wwp = wbase + (size_t)2 * nw * welems;
     double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
     double *thin_result = nullptr;
     const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
@@ -1425,9 +1425,8 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
     } else if (c->last_polish) {
         // reduced-precision modes: the bulk's last iterate, converted to FP64
         // from its words (the polish steps are computed on the own columns only)
-        const int64_t plane = P.work_elems;
         const unsigned short *w0 = reinterpret_cast<const unsigned short *>(slab(c, 1));
-        const unsigned short *w1 = w0 + (size_t)c->last_nw * plane;
+        const unsigned short *w1 = w0 + (size_t)c->last_nw * P.work_elems;
         HIP_TRY(c, launch_from_words(c->stream, c->last_fmt, c->last_nw, g, 1, d.npad, c->d_gd.p, w0, w1,
                                      c->d_kfinal.p, slab(c, 0)));
         HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -151,7 +151,7 @@ void scatter_kernel(int64_t nblocks, const int64_t *__restrict__ plist, const Sc
 // of 2p dense products.
 // ---------------------------------------------------------------------------
 // The polish reads the bulk result X where the bulk left it: an FP64 slab, or
-// the word planes (FP16 / BF16 words, or FP32 values) of the group's final
+// the words (FP16 / BF16 words, or FP32 values) of the group's final
 // bulk step, converted on the fly to exactly the FP64 value the words stand
 // for (sum of the words over the power-of-two scale).
 enum XKind { X_F64 = 0, X_F16x2 = 1, X_BF16x3 = 2, X_BF16x1 = 3, X_F32 = 4 };

@@ -161,18 +161,19 @@ __device__ inline void split8(const float *v, u16x8 *wv)
 }
 
 // Operands go straight from global memory into LDS (global_load_lds_dwordx4,
-// no register staging) in K steps of 32: per operand and word plane a
+// no register staging) in K steps of 32: per operand and word a
 // [128 columns][32] halves region, 64 B per column, whose four 16-B chunks are
 // XOR-swizzled by column so that the matrix-core operand reads (16 columns x
 // one chunk) are free of bank conflicts.  One stage per workgroup: the operand traffic
 // of one workgroup overlaps the products of the others on the CU.  The
-// epilogue stages half of the FP32 tile at a time in LDS, column-major for
-// the tile itself and row-major for its mirror, so that 16 consecutive lanes
-// write one 128-row column segment (coalesced 16-B stores).
+// epilogue stages half of the FP32 tile at a time in LDS, column-major, so
+// that 16 consecutive lanes write one 128-row column segment (coalesced 16-B
+// stores); the mirror reads the converted words back from the same staging
+// (three words: from a second, row-major staging of the FP32 values).
 constexpr int BK = 32;
-constexpr int CPC = BK / 8;        // 16-B chunks per column, word plane and K step
+constexpr int CPC = BK / 8;        // 16-B chunks per column, word and K step
 constexpr int CST = 132;           // column-major staging: 528-B columns (conflict-free f4 stores)
-constexpr int CSTH = 68;           // row-major staging of a 64-column half
+constexpr int CSTH = 68;           // row-major staging of a 64-column half (three words)
 
 // Slot of chunk 0 of a column: every 8 consecutive columns, and the even and
 // the odd columns of every 16, get distinct slots, so a 16-B operand read of
@@ -266,7 +267,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     // (slot ^ swz(column)) of that column.  Columns beyond ld and the chunk
     // offsets of a K step beyond ld read any valid address instead (their
     // products only reach discarded outputs, or are not issued).
-    constexpr int PH = BM * BK;         // halves per operand-plane region
+    constexpr int PH = BM * BK;         // halves per operand-word region of LDS
     const unsigned short *srcA[2], *srcB[2];
     int kcoff[2];
 #pragma unroll
