@@ -79,9 +79,34 @@ def test_water16_bf16_single_word_is_reported(smx, oracle_lib):
 def test_random_systems_mixed(smx, oracle_lib, seed, sizes, dens, groups):
     s = random_block_system(seed, sizes, density=dens, coupling=0.04, groups=groups, mu=0.01)
     ref = oracle_lib.submatrix(s)
-    for precision in ("fp16x2", "fp32"):
+    for precision in ("fp16x2", "bf16x3", "fp32"):
         res, _, _ = run(smx, s, precision)
         assert max_err(res, ref) <= TOL_MIXED, precision
+
+
+@pytest.mark.parametrize("precision", ["fp16x2", "bf16x3", "bf16", "fp32"])
+def test_bulk_iterate_readback_matches_oracle_sign(smx, oracle_lib, precision):
+    """smx_get_submatrix(what = 1) in the reduced modes converts the bulk's last
+    iterate from its word storage to FP64.  That iterate stops at tau_k =
+    Tr(I - X_k^2) <= 1e-3 (or the word floor), so every eigenvalue is within
+    tau_k / 2 of +-1 and the entries are within about tau_k of the exact sign
+    Q signum(Lambda) Q^T of the oracle's eigendecomposition; the 1-word BF16
+    run stalls at its floor (~1e-2)."""
+    s = water_config("water16")
+    ctx = smx.Context(0).load(s).configure(precision=precision)
+    ctx.evaluate()
+    tol = 2e-2 if precision == "bf16" else 2e-3
+    for g in (0, s.ngroups // 2, s.ngroups - 1):
+        x = ctx.submatrix(g, what=1)
+        _, lam, q, _ = oracle_lib.group_eig(s, g)
+        sign = (q * np.sign(lam)) @ q.T
+        assert x.shape == sign.shape
+        err = float(np.abs(x - sign).max())
+        print(f"water16 {precision} group {g}: max|X_bulk - sign| = {err:.2e}")
+        assert err <= tol, (g, err)
+        # symmetric to the word rounding
+        assert float(np.abs(x - x.T).max()) <= 1e-5
+    ctx.close()
 
 
 def test_mixed_polish_count_and_determinism(smx, oracle_lib):
