@@ -1408,7 +1408,10 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
     const double *src = nullptr;
     double a = 1.0;
     if (what == 0) {
-        // re-gather this group's chunks into the scratch product buffer
+        // re-gather this group's chunks into a slab that what = 1 does not read:
+        // the W slab in FP64 mode; after a reduced-precision evaluation the first
+        // slab (the words of the iterates lie over the second and third)
+        double *dst = (c->evaluated && c->last_polish) ? slab(c, 0) : slab(c, 2);
         std::vector<int2> ch;
         for (const int2 &x : P.chunks)
             if (x.x == g) ch.push_back(x);
@@ -1417,11 +1420,11 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
         HIP_TRY(c, c->d_check.ensure((size_t)std::max(P.ngroups, 2)));
         HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, sizeof(double) * std::max(P.ngroups, 2), c->stream));
         HIP_TRY(c, launch_gather(c->stream, (int)ch.size(), dch.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                                 c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, slab(c, 2),
+                                 c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, dst,
                                  reinterpret_cast<unsigned long long *>(c->d_check.p)));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dch.release();
-        src = slab(c, 2) + d.off;
+        src = dst + d.off;
     } else if (c->last_polish) {
         // reduced-precision modes: the bulk's last iterate, converted to FP64
         // from its words (the polish steps are computed on the own columns only)

@@ -106,6 +106,10 @@ def test_bulk_iterate_readback_matches_oracle_sign(smx, oracle_lib, precision):
         assert err <= tol, (g, err)
         # symmetric to the word rounding
         assert float(np.abs(x - x.T).max()) <= 1e-5
+        # re-gathering A_g (what = 0) leaves the stored iterates alone
+        a = ctx.submatrix(g, what=0)
+        assert a.shape == x.shape
+        np.testing.assert_array_equal(ctx.submatrix(g, what=1), x)
     ctx.close()
 
 
