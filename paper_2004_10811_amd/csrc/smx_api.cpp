@@ -1094,12 +1094,19 @@ int32_t smx_evaluate(smx_ctx c)
         const TileDesc *tl = c->d_tiles.p + P.tile_beg[wave];
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
-        HIP_TRY(c, launch_gather(st, (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]), c->d_chunks.p + P.chunk_beg[wave],
-                                 c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu,
-                                 xb[0], gather_scale));
+        const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
+        const int2 *chs = c->d_chunks.p + P.chunk_beg[wave];
+        if (!mixed) {
+            HIP_TRY(c, launch_gather(st, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p, c->d_valoff.p,
+                                     c->d_k.p, c->mu, xb[0], gather_scale));
+        } else {
+            // bounds first, then X_0 straight into the words (no FP64 copy of A_g)
+            HIP_TRY(c, launch_gather_bound(st, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p,
+                                           c->d_valoff.p, c->d_k.p, c->mu, gather_scale));
+            HIP_TRY(c, launch_gather_words(st, fmt, nw, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p,
+                                           c->d_valoff.p, c->d_k.p, c->mu, it.scale_bits, wb[0]));
+        }
         if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, c->d_gd.p, it.scale_bits, tb[0]));
-        if (mixed)
-            HIP_TRY(c, launch_to_words(st, fmt, nw, g0, wng, P.max_npad, c->d_gd.p, xb[0], it.scale_bits, wb[0]));
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
         // one Newton-Schulz step of the wave on stream s (timed: HIP events around
         // each product launch; not inside a graph capture)

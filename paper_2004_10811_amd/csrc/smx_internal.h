@@ -59,6 +59,43 @@ struct IterState {
     int32_t tau_nt;                   // tile rows of the largest group
 };
 
+// Row r of A_g = K[R(g), R(g)] - mu I over the columns c < n_g (Sec. III-A
+// step 1), block column by block column: emit(c, v) for every column, zero
+// for unstored blocks and padding rows.  Returns sum_c |v| for true rows (the
+// row's term of the Gershgorin bound ||A_g||_inf), 0 for padding rows.
+template <class Emit>
+__device__ inline double gather_row(const GroupDesc &gd, int r, const RowInfo *__restrict__ rinfo,
+                                    const int32_t *__restrict__ bmap, const int32_t *__restrict__ boffs,
+                                    const int64_t *__restrict__ valoff, const double *__restrict__ kvals,
+                                    double mu, Emit &&emit)
+{
+    const bool real = r < gd.n;
+    int lb = 0, rr = 0, br = 0;
+    if (real) {
+        const RowInfo ri = rinfo[gd.rinfo_off + r];
+        lb = ri.x;
+        rr = ri.y & 0xffff;
+        br = ri.y >> 16;
+    }
+    const int32_t *map_row = bmap + gd.map_off + lb;     // + m * column block
+    const int32_t *bo = boffs + gd.boff_off;
+    double rowsum = 0.0;
+    for (int cb = 0; cb < gd.m; cb++) {
+        const int c0 = bo[cb];
+        const int bc = bo[cb + 1] - c0;
+        const int32_t p = real ? map_row[(int64_t)gd.m * cb] : -1;
+        const double *src = (p >= 0) ? kvals + valoff[p] + rr : nullptr;
+        for (int cc = 0; cc < bc; cc++) {
+            const int c = c0 + cc;
+            double v = (p >= 0) ? src[(int64_t)cc * br] : 0.0;
+            if (r == c) v -= mu;
+            rowsum += fabs(v);
+            emit(c, v);
+        }
+    }
+    return real ? rowsum : 0.0;
+}
+
 // ---- launchers (stream-ordered, no synchronisation) -----------------------
 
 hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const GroupDesc *groups,
@@ -119,8 +156,17 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                            unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
 // Group-walking launchers take the first group g0 and the count ngroups (a wave).
-hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                           const double *src, const unsigned long long *scale_bits, unsigned short *dst);
+// Gershgorin bounds only (atomic max of the row sums into scale_bits), no
+// writes of A_g; then X_0 = A_g / s_g gathered straight into the word storage
+// (fmt 0 / 1 with nw words, fmt 2 FP32 values) with the bounds in scale_bits.
+hipError_t launch_gather_bound(hipStream_t st, int nchunks, const int2 *chunks, const GroupDesc *groups,
+                               const RowInfo *rinfo, const int32_t *bmap, const int32_t *boffs,
+                               const int64_t *valoff, const double *kvals, double mu,
+                               unsigned long long *scale_bits);
+hipError_t launch_gather_words(hipStream_t st, int fmt, int nw, int nchunks, const int2 *chunks,
+                               const GroupDesc *groups, const RowInfo *rinfo, const int32_t *bmap,
+                               const int32_t *boffs, const int64_t *valoff, const double *kvals, double mu,
+                               const unsigned long long *scale_bits, unsigned short *dst);
 hipError_t launch_from_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
                              const unsigned short *x0, const unsigned short *x1, const int32_t *kfinal, double *dst);
 

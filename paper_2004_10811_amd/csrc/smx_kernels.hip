@@ -37,6 +37,7 @@ __device__ inline double wave_sum(double v)
 // threads write consecutive rows of one column (coalesced), and the row sum
 // of |A_g| feeds the Gershgorin bound s_g = ||A_g||_inf.
 // ---------------------------------------------------------------------------
+template <bool WRITE>
 __global__ __launch_bounds__(256)
 void gather_shift_kernel(const int2 *__restrict__ chunks, const GroupDesc *__restrict__ groups,
                          const RowInfo *__restrict__ rinfo, const int32_t *__restrict__ bmap,
@@ -49,36 +50,14 @@ void gather_shift_kernel(const int2 *__restrict__ chunks, const GroupDesc *__res
     const int r = ch.y + (int)threadIdx.x;
     const int npad = gd.npad;
     const bool live = r < npad;
-    const bool real = r < gd.n;
-    int lb = 0, rr = 0, br = 0;
-    if (real) {
-        const RowInfo ri = rinfo[gd.rinfo_off + r];
-        lb = ri.x;
-        rr = ri.y & 0xffff;
-        br = ri.y >> 16;
-    }
     double *xg = x0 + gd.off;
-    const int32_t *map_row = bmap + gd.map_off + lb;     // + m * column block
-    const int32_t *bo = boffs + gd.boff_off;
-    double rowsum = 0.0;
-    for (int cb = 0; cb < gd.m; cb++) {
-        const int c0 = bo[cb];
-        const int bc = bo[cb + 1] - c0;
-        const int32_t p = real ? map_row[(int64_t)gd.m * cb] : -1;
-        const double *src = (p >= 0) ? kvals + valoff[p] + rr : nullptr;
-        for (int cc = 0; cc < bc; cc++) {
-            const int c = c0 + cc;
-            double v = (p >= 0) ? src[(int64_t)cc * br] : 0.0;
-            if (r == c) v -= mu;
-            rowsum += fabs(v);
-            if (live) xg[r + (int64_t)c * npad] = v;
-        }
-    }
+    double m = gather_row(gd, r, rinfo, bmap, boffs, valoff, kvals, mu, [&](int c, double v) {
+        if (WRITE && live) xg[r + (int64_t)c * npad] = v;
+    });
     // padding columns: identity on the padded diagonal
-    for (int c = gd.n; c < npad; c++)
-        if (live) xg[r + (int64_t)c * npad] = (r == c) ? 1.0 : 0.0;
-
-    double m = real ? rowsum : 0.0;
+    if (WRITE)
+        for (int c = gd.n; c < npad; c++)
+            if (live) xg[r + (int64_t)c * npad] = (r == c) ? 1.0 : 0.0;
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(scale_bits + ch.x, m);
 }
@@ -475,8 +454,19 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
                          unsigned long long *scale_bits)
 {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_shift_kernel, dim3(nchunks), dim3(256), 0, st, chunks, groups,
+    hipLaunchKernelGGL(gather_shift_kernel<true>, dim3(nchunks), dim3(256), 0, st, chunks, groups,
                        rinfo, bmap, boffs, valoff, kvals, mu, x0, scale_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_bound(hipStream_t st, int nchunks, const int2 *chunks, const GroupDesc *groups,
+                               const RowInfo *rinfo, const int32_t *bmap, const int32_t *boffs,
+                               const int64_t *valoff, const double *kvals, double mu,
+                               unsigned long long *scale_bits)
+{
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_shift_kernel<false>, dim3(nchunks), dim3(256), 0, st, chunks, groups,
+                       rinfo, bmap, boffs, valoff, kvals, mu, nullptr, scale_bits);
     return hipGetLastError();
 }
 

@@ -101,15 +101,15 @@ __host__ __device__ constexpr int npairs() { return NW == 1 ? 1 : (NW == 2 ? 3 :
 __host__ __device__ constexpr int pair_p(int i) { return i == 2 || i == 3 ? 1 : (i == 5 ? 2 : 0); }
 __host__ __device__ constexpr int pair_q(int i) { return i == 1 || i == 3 ? 1 : (i == 4 ? 2 : 0); }
 
+// Split v into NW words: each word the rounded remainder of v minus the previous words.
 template <int FMT, int NW>
-__device__ inline void split_store(unsigned short *o, double v)
+__device__ inline void split_words(double v, unsigned short *out)
 {
     double rem = v;
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-        const unsigned short u = to_word<FMT>(rem);
-        o[32 * w] = u;
-        rem -= from_word<FMT>(u);
+        out[w] = to_word<FMT>(rem);
+        rem -= from_word<FMT>(out[w]);
     }
 }
 
@@ -749,22 +749,55 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
 }
 
 
-// X_0 words = split(a A), a = 1/s_g (the Gershgorin prescaling), one group per
-// blockIdx.y, columns over blockIdx.x, rows over the threads.
+// X_0 = a A_g, a = 1/s_g (the Gershgorin prescaling, bounds from the row-sum
+// pass), gathered straight into the word storage: one thread per row of a
+// 256-row chunk, as the FP64 gather.
 template <int FMT, int NW>
 __global__ __launch_bounds__(256)
-void f64_to_words_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ src,
-                         const unsigned long long *__restrict__ scale_bits, unsigned short *__restrict__ dst, int g0)
+void gather_words_kernel(const int2 *__restrict__ chunks, const GroupDesc *__restrict__ groups,
+                         const RowInfo *__restrict__ rinfo, const int32_t *__restrict__ bmap,
+                         const int32_t *__restrict__ boffs, const int64_t *__restrict__ valoff,
+                         const double *__restrict__ kvals, double mu,
+                         const unsigned long long *__restrict__ scale_bits, unsigned short *__restrict__ dst)
 {
-    const int g = g0 + blockIdx.y;
-    const GroupDesc gd = groups[g];
+    const int2 ch = chunks[blockIdx.x];
+    const GroupDesc gd = groups[ch.x];
+    const int r = ch.y + (int)threadIdx.x;
     const int ld = gd.npad;
-    const double s = __longlong_as_double((long long)scale_bits[g]);
+    if (r >= ld) return;
+    const double s = __longlong_as_double((long long)scale_bits[ch.x]);
     const double a = s > 0.0 ? 1.0 / s : 0.0;
     unsigned short *d = dst + NW * gd.off;
-    for (int c = blockIdx.x; c < ld; c += gridDim.x)
-        for (int r = threadIdx.x; r < ld; r += 256)
-            split_store<FMT, NW>(d + word_pos(NW, ld, r, c), a * src[gd.off + r + (int64_t)c * ld] * word_scale<FMT>());
+    auto store = [&](int c, double v) {
+        unsigned short w[NW];
+        split_words<FMT, NW>(a * v * word_scale<FMT>(), w);
+        unsigned short *p = d + word_pos(NW, ld, r, c);
+#pragma unroll
+        for (int q = 0; q < NW; q++) p[32 * q] = w[q];
+    };
+    gather_row(gd, r, rinfo, bmap, boffs, valoff, kvals, mu, store);
+    for (int c = gd.n; c < ld; c++)       // padding columns: the identity, scaled like the rest
+        store(c, r == c ? 1.0 : 0.0);
+}
+
+// The same for FP32 values (column-major like the FP64 slabs).
+__global__ __launch_bounds__(256)
+void gather_f32_kernel(const int2 *__restrict__ chunks, const GroupDesc *__restrict__ groups,
+                       const RowInfo *__restrict__ rinfo, const int32_t *__restrict__ bmap,
+                       const int32_t *__restrict__ boffs, const int64_t *__restrict__ valoff,
+                       const double *__restrict__ kvals, double mu,
+                       const unsigned long long *__restrict__ scale_bits, float *__restrict__ dst)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const GroupDesc gd = groups[ch.x];
+    const int r = ch.y + (int)threadIdx.x;
+    const int ld = gd.npad;
+    if (r >= ld) return;
+    const double s = __longlong_as_double((long long)scale_bits[ch.x]);
+    const double a = s > 0.0 ? 1.0 / s : 0.0;
+    float *d = dst + gd.off;
+    gather_row(gd, r, rinfo, bmap, boffs, valoff, kvals, mu, [&](int c, double v) { d[r + (int64_t)c * ld] = (float)(a * v); });
+    for (int c = gd.n; c < ld; c++) d[r + (int64_t)c * ld] = (float)(a * (r == c ? 1.0 : 0.0));
 }
 
 // fp64 copy of the bulk result X_kfinal (sum of its words).
@@ -788,20 +821,7 @@ void words_to_f64_kernel(const GroupDesc *__restrict__ groups, const unsigned sh
         }
 }
 
-// X_0 in FP32 = a A, a = 1/s_g; and the FP64 copy of the FP32 bulk result.
-__global__ __launch_bounds__(256)
-void f64_to_f32_kernel(const GroupDesc *__restrict__ groups, const double *__restrict__ src,
-                       const unsigned long long *__restrict__ scale_bits, float *__restrict__ dst, int g0)
-{
-    const int g = g0 + blockIdx.y;
-    const GroupDesc gd = groups[g];
-    const int64_t tot = (int64_t)gd.npad * gd.npad;
-    const double s = __longlong_as_double((long long)scale_bits[g]);
-    const double a = s > 0.0 ? 1.0 / s : 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
-        dst[gd.off + e] = (float)(a * src[gd.off + e]);
-}
-
+// FP64 copy of the FP32 bulk result.
 __global__ __launch_bounds__(256)
 void f32_to_f64_kernel(const GroupDesc *__restrict__ groups, const float *__restrict__ x0,
                        const float *__restrict__ x1, const int32_t *__restrict__ kfinal, double *__restrict__ dst,
@@ -854,23 +874,23 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_to_words(hipStream_t st, int fmt, int nw, int g0, int ngroups, int max_npad, const GroupDesc *groups,
-                           const double *src, const unsigned long long *scale_bits, unsigned short *dst)
+hipError_t launch_gather_words(hipStream_t st, int fmt, int nw, int nchunks, const int2 *chunks,
+                               const GroupDesc *groups, const RowInfo *rinfo, const int32_t *bmap,
+                               const int32_t *boffs, const int64_t *valoff, const double *kvals, double mu,
+                               const unsigned long long *scale_bits, unsigned short *dst)
 {
-    if (ngroups <= 0) return hipSuccess;
-    const int64_t tot = (int64_t)max_npad * max_npad;
-    const dim3 grid((unsigned)std::min<int64_t>((tot + 2047) / 2048, 4096), (unsigned)ngroups);
-    const dim3 gridc((unsigned)std::min(max_npad, 4096), (unsigned)ngroups);   // one column per block
-#define SMX_TW(F, N) hipLaunchKernelGGL((f64_to_words_kernel<F, N>), gridc, dim3(256), 0, st, groups, src, scale_bits, dst, g0)
+    if (nchunks <= 0) return hipSuccess;
+#define SMX_GW(F, N) hipLaunchKernelGGL((gather_words_kernel<F, N>), dim3(nchunks), dim3(256), 0, st, chunks, groups, \
+                                        rinfo, bmap, boffs, valoff, kvals, mu, scale_bits, dst)
     if (fmt == 2)
-        hipLaunchKernelGGL(f64_to_f32_kernel, grid, dim3(256), 0, st, groups, src, scale_bits,
-                           reinterpret_cast<float *>(dst), g0);
-    else if (fmt == 0 && nw == 1) SMX_TW(0, 1);
-    else if (fmt == 0 && nw == 2) SMX_TW(0, 2);
-    else if (fmt == 1 && nw == 1) SMX_TW(1, 1);
-    else if (fmt == 1 && nw == 3) SMX_TW(1, 3);
+        hipLaunchKernelGGL(gather_f32_kernel, dim3(nchunks), dim3(256), 0, st, chunks, groups, rinfo, bmap, boffs,
+                           valoff, kvals, mu, scale_bits, reinterpret_cast<float *>(dst));
+    else if (fmt == 0 && nw == 1) SMX_GW(0, 1);
+    else if (fmt == 0 && nw == 2) SMX_GW(0, 2);
+    else if (fmt == 1 && nw == 1) SMX_GW(1, 1);
+    else if (fmt == 1 && nw == 3) SMX_GW(1, 3);
     else return hipErrorInvalidValue;
-#undef SMX_TW
+#undef SMX_GW
     return hipGetLastError();
 }
 
