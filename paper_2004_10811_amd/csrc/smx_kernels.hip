@@ -224,7 +224,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                      const double *__restrict__ z, const double *__restrict__ o, double *__restrict__ y, int g0)
 {
     constexpr int KC = 128;                           // rows of z per LDS stage
-    constexpr int U = 8;                              // rows of X in flight per lane
+    constexpr int U = 4;                              // rows of X in flight per lane (4 ran faster than 2, 8 or 16)
     __shared__ __attribute__((aligned(16))) double zs[KC][MW + 2];
     const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
