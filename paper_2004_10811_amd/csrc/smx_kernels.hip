@@ -124,7 +124,7 @@ void scatter_kernel(int64_t nblocks, const int64_t *__restrict__ plist, const Sc
 // FP64 polish on the own columns only.  D needs only the group's own columns
 // of the polished sign, X_{k+p}[:, own] = X_{k+p} E (E selects the own
 // columns), and every polished iterate is a polynomial in the bulk result X:
-// X_{j+1} = 1.5 X_j - 0.5 X_j^3.  The driver evaluates X_{k+p} E by thin
+// X_{j+1} = 1.5 X_j - 0.5 X_j^3.  The host side evaluates X_{k+p} E by thin
 // products Y = X Z with n_pad x m_own blocks Z (column-major, leading
 // dimension n_pad), so the p FP64 steps cost 3^p - 1 passes over X instead
 // of 2p dense products.
