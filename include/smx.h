@@ -20,7 +20,7 @@
  *     3. The group's own block columns of D_g = (I - S_g) / 2 (Eq. DsignSym
  *        with S = I) are written into D, only at the block positions stored
  *        in K (the result keeps K's sparsity pattern).
- *   Then N = Tr D (Sec. IV-H, no spin factor) and E = Tr(D K) (Eq.
+ *   Then N = Tr D (Sec. IV-G, no spin factor) and E = Tr(D K) (Eq.
  *   bandenergy), reduced in FP64.
  *
  * Conventions
@@ -64,7 +64,7 @@ extern "C" {
 #define SMX_E_UNSUPPORTED     -5   /* option not implemented on this path     */
 #define SMX_E_NOMEM           -6   /* device or host allocation failed        */
 #define SMX_E_HIP             -7   /* HIP runtime error                        */
-#define SMX_E_NOT_CONVERGED   -8   /* a group reached max_iter; D is written  */
+#define SMX_E_NOT_CONVERGED   -8   /* a group did not converge; D is written  */
 
 /* ---- precision modes (smx_set_precision) ------------------------------- */
 #define SMX_FP64      0   /* every Newton-Schulz product in FP64 (MFMA f64)      */
@@ -227,8 +227,16 @@ int32_t smx_set_workspace_limit(smx_ctx ctx, int64_t bytes);
  */
 int32_t smx_evaluate(smx_ctx ctx);
 
-/* Wait for the last evaluation; SMX_E_NOT_CONVERGED if any group reached
- * max_iter (D is still written), SMX_E_NONFINITE if an iterate was not finite. */
+/* Wait for the last evaluation.  SMX_E_NONFINITE if an iterate was not
+ * finite; SMX_E_NOT_CONVERGED (D is still written) if any group did not
+ * converge:
+ *   SMX_FP64: max|X_k^2 - I| > tol at k = max_iter;
+ *   reduced-precision modes: the bulk left above switch_tol (stall rule or
+ *   step cap; for SMX_BF16_1W, whose rounding floor lies above switch_tol by
+ *   design, above 0.1), or the own-column residual r = max|X_{k+p-1}^2 E - E|
+ *   of the polish gives 3 r^2 / 4 > tol, i.e. the returned iterate misses the
+ *   FP64 stopping rule.  Convergence is about the iteration, not accuracy:
+ *   SMX_BF16_1W converges to the sign of its rounded iterate (~1e-3 off). */
 int32_t smx_wait(smx_ctx ctx);
 
 /* Copy D (K's layout, same number of doubles as K's values) into `out`
@@ -283,7 +291,7 @@ int32_t smx_set_frozen(smx_ctx ctx, int32_t on);
 int32_t smx_dn_dmu(smx_ctx ctx, double *out);
 
 /*
- * Chemical potential for a target electron count (Sec. IV-H, Algorithm 1
+ * Chemical potential for a target electron count (Sec. IV-G, Algorithm 1
  * reads n_elec off fixed decompositions; here the iteration itself is
  * frozen).  Bracket: the Gershgorin interval of K; scales s_g: the larger of
  * the bracket ends' ||K_sub - mu I||_inf (valid for every mu inside); step

@@ -198,7 +198,7 @@ def group_eig(s, g: int, mu: float | None = None, values: np.ndarray | None = No
 # ---------------------------------------------------------------------------
 # Frozen-iteration quantities (k Newton-Schulz steps, fixed scale), computed
 # from the eigendecomposition of each group's submatrix.  Algorithm 1 of the
-# paper (Sec. IV-H) reads the electron count off stored decompositions with
+# paper (Sec. IV-G) reads the electron count off stored decompositions with
 # signum(lambda - mu); here the signum is replaced by the k-step
 # Newton-Schulz polynomial p_k of the scaled eigenvalue, which is what a
 # frozen iteration evaluates.

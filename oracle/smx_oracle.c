@@ -13,14 +13,14 @@
  *     stored in any member column; the matrix function is evaluated on that
  *     dense submatrix and only the group's own columns are copied back, into
  *     the stored blocks of the input pattern.
- *   - Matrix sign by eigendecomposition (Sec. IV-G, Eq. eigendecompsym):
+ *   - Matrix sign by eigendecomposition (Sec. IV-F, Eq. eigendecompsym):
  *     sign(A) = Q signum(Lambda) Q^T, with the extension that an eigenvalue
  *     on the imaginary axis (here: zero) maps to 0 (Eq. signevext).
  *   - Density matrix for an orthogonalised K (Eq. DsignSym with S = I):
  *     D = (I - sign(K - mu I)) / 2; at finite temperature the signum is
- *     replaced by the Fermi function (Sec. IV-G, last paragraph), i.e.
+ *     replaced by the Fermi function (Sec. IV-F, last paragraph), i.e.
  *     D = Q f(Lambda) Q^T with f(x) = 1 / (1 + exp(x / kT)).
- *   - Electron count N = Tr D (Sec. IV-H, no spin factor) and band energy
+ *   - Electron count N = Tr D (Sec. IV-G, no spin factor) and band energy
  *     E = Tr(D K) (Eq. bandenergy), both over the stored blocks.
  *
  * The symmetric eigensolver is the cyclic-by-row two-sided Jacobi method
@@ -45,6 +45,7 @@
 #define ORACLE_E_INVALID -1
 #define ORACLE_E_JACOBI -2
 #define ORACLE_E_NOMEM -3
+#define ORACLE_E_NOT_SYMMETRIC -4
 
 typedef struct {
     int32_t n;          /* submatrix dimension n_g                          */
@@ -410,6 +411,35 @@ static int32_t make_view(bsc_view *v, int32_t nblk, const int32_t *blk_size,
     return ORACLE_OK;
 }
 
+/*
+ * Step 1 of the method reads K as the symmetric matrix it is (the Kohn-Sham
+ * matrix of Sec. II-A, orthogonalised, so that Eq. DsignSym applies): every
+ * stored block (I, J) must have its mirror (J, I) stored, with
+ * max|K_IJ - K_JI^T| <= 1e-12 max|K|.  The submatrix assembly reads both
+ * triangles, so an asymmetric input is refused rather than silently used.
+ */
+static int32_t check_symmetric(const bsc_view *k)
+{
+    double amax = 0.0, dmax = 0.0;
+    for (int32_t j = 0; j < k->nblk; j++)
+        for (int64_t p = k->col_ptr[j]; p < k->col_ptr[j + 1]; p++) {
+            int32_t i = k->row_idx[p];
+            int64_t q = find_block(k, j, i);
+            if (q < 0) return ORACLE_E_NOT_SYMMETRIC;
+            int32_t bi = k->blk_size[i], bj = k->blk_size[j];
+            const double *a = k->values + k->val_off[p];      /* bi x bj, column-major */
+            const double *b = k->values + k->val_off[q];      /* bj x bi */
+            for (int32_t c = 0; c < bj; c++)
+                for (int32_t r = 0; r < bi; r++) {
+                    double x = a[r + (int64_t)c * bi], y = b[c + (int64_t)r * bj];
+                    if (!isfinite(x)) return ORACLE_E_INVALID;
+                    if (fabs(x) > amax) amax = fabs(x);
+                    if (fabs(x - y) > dmax) dmax = fabs(x - y);
+                }
+        }
+    return dmax <= 1e-12 * amax ? ORACLE_OK : ORACLE_E_NOT_SYMMETRIC;
+}
+
 /* Dimension n_g and |R(g)| of every group (no decomposition). */
 int32_t oracle_group_dims(int32_t nblk, const int32_t *blk_size, const int64_t *col_ptr,
                           const int32_t *row_idx, int32_t ngroups, const int32_t *grp_ptr,
@@ -449,6 +479,8 @@ int32_t oracle_submatrix(int32_t nblk, const int32_t *blk_size, const int64_t *c
     int32_t st = make_view(&v, nblk, blk_size, col_ptr, row_idx, values);
     if (st) return st;
     if (ngroups < 0 || !grp_ptr || !grp_blocks || !d_values || kT < 0.0) { free(v.val_off); return ORACLE_E_INVALID; }
+    st = check_symmetric(&v);
+    if (st) { free(v.val_off); return st; }
     int32_t njobs = which ? nwhich : ngroups;
     int32_t status = ORACLE_OK;
 #ifdef _OPENMP

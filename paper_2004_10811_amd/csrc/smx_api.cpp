@@ -167,6 +167,7 @@ struct smx_context {
     bool use_kfix = false, use_sfix = false;  // frozen step counts / scales
     bool have_tangent = false;                 // last evaluation computed dN/dmu
     bool last_sfix = false;                    // last evaluation ran on the frozen scales
+    double last_mu = 0.0;                      // mu of the last evaluation (the adjoint's A_g)
 
     // step graphs (smx_set_graph)
     int32_t graph_steps = 0;                   // steps per graph; 0: direct launches
@@ -1172,6 +1173,7 @@ int32_t smx_evaluate(smx_ctx c)
             int32_t res = -1;
             if (int32_t e = own_polish(c, g0, wng, xs, it, &res)) return e;
             thin_result = c->d_tpool.p + (size_t)res * (size_t)P.thin_elems;
+            HIP_TRY(c, launch_polish_flags(st, g0, wng, it, c->max_iter + c->n_polish, c->tol));
         }
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
         const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
@@ -1198,6 +1200,7 @@ int32_t smx_evaluate(smx_ctx c)
     c->last_fmt = fmt;
     c->last_nw = nw;
     c->last_max_iter = c->max_iter;
+    c->last_mu = c->mu;
     c->evaluated = true;
     return SMX_OK;
 }
@@ -1214,7 +1217,10 @@ int32_t smx_wait(smx_ctx c)
         nf += (f & 2) != 0;
     }
     if (nf) return fail(c, SMX_E_NONFINITE, std::to_string(nf) + " group(s) produced non-finite iterates");
-    if (nc) return fail(c, SMX_E_NOT_CONVERGED, std::to_string(nc) + " group(s) reached max_iter");
+    if (nc)
+        return fail(c, SMX_E_NOT_CONVERGED,
+                    std::to_string(nc) + " group(s) did not converge (FP64: max_iter reached; reduced precision: "
+                                         "bulk left above switch_tol, or polished residual above tol)");
     return SMX_OK;
 }
 
@@ -1834,7 +1840,7 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     HIP_TRY(c, hipMemsetAsync(c->d_check.p, 0, 2 * sizeof(double), st));
     HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
     HIP_TRY(c, launch_gather(st, (int)P.chunks.size(), c->d_chunks.p, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p,
-                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->mu, seg[0], c->d_scale_scratch.p));
+                             c->d_boffs.p, c->d_valoff.p, c->d_k.p, c->last_mu, seg[0], c->d_scale_scratch.p));
     HIP_TRY(c, launch_scale_slab(st, ng, P.max_npad, c->d_gd.p, sptr, seg[0]));
     HIP_TRY(c, hipMemcpyAsync(cp(0), seg[0], sizeof(double) * (size_t)E, hipMemcpyDeviceToDevice, st));
     auto fwd_step = [&](int k, const double *x, double *xnext) -> int32_t {

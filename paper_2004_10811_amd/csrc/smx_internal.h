@@ -203,6 +203,10 @@ hipError_t launch_scatter(hipStream_t st, int64_t nblocks, const int64_t *plist,
                           const double *x1, const IterState &it, const double *kvals,
                           double *dvals, double *part_e, double *part_n, int from_thin);
 
+// flags[g] |= 1 unless 3 r^2 / 4 <= tol for the polish residual r in `slot`
+// (|= 2 if r is not finite), for the groups g0 .. g0 + ngroups - 1.
+hipError_t launch_polish_flags(hipStream_t st, int g0, int ngroups, const IterState &it, int slot, double tol);
+
 hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const double *part_n,
                          double *out2);
 

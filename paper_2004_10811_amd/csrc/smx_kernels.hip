@@ -327,6 +327,24 @@ void thin_resid_kernel(const GroupDesc *__restrict__ groups, const int32_t *__re
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(it.resid_bits + (int64_t)g * it.resid_stride + slot, rmax);
 }
 
+// Convergence of the own-column polish: r = max|X_{k+p-1}^2 E - E| is the
+// residual one step before the returned iterate, and one Newton-Schulz step
+// maps an eigenvalue with 1 - x^2 = r to one with 1 - x'^2 = 3r^2/4 + r^3/4.
+// The group is flagged not converged (bit 0) unless 3r^2/4 <= tol, the FP64
+// stopping rule applied to the returned iterate; non-finite r sets bit 1.
+__global__ __launch_bounds__(256)
+void polish_flags_kernel(int ngroups, IterState it, int slot, double tol, int g0)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= ngroups) return;
+    const int g = g0 + q;
+    const double r = __longlong_as_double((long long)it.resid_bits[(int64_t)g * it.resid_stride + slot]);
+    int fl = it.flags[g];
+    if (!(r <= 1.7976931348623157e308)) fl |= 2;
+    else if (!(0.75 * r * r <= tol)) fl |= 1;
+    it.flags[g] = fl;
+}
+
 // Fixed-order sum of the per-block partials (one workgroup): deterministic.
 __global__ __launch_bounds__(1024)
 void reduce_kernel(int64_t n, const double *__restrict__ pe, const double *__restrict__ pn,
@@ -562,6 +580,14 @@ hipError_t launch_thin_resid(hipStream_t st, int g0, int ngroups, int max_npad, 
     const int64_t tot = (int64_t)max_npad * max_own;
     const dim3 grid((unsigned)std::min<int64_t>((tot + 1023) / 1024, 1024), (unsigned)ngroups);
     hipLaunchKernelGGL(thin_resid_kernel, grid, dim3(256), 0, st, groups, own_list, b, it, slot, g0);
+    return hipGetLastError();
+}
+
+hipError_t launch_polish_flags(hipStream_t st, int g0, int ngroups, const IterState &it, int slot, double tol)
+{
+    if (ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(polish_flags_kernel, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0, st, ngroups, it,
+                       slot, tol, g0);
     return hipGetLastError();
 }
 

@@ -167,6 +167,12 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     // output layout; operands: lane l gives A[l%16][l/16] and B[l/16][l%16]).
     double *og = out + gd.off;
     const int n = gd.n;
+    // The prescaling a = 1/s_g belongs to the true n_g x n_g block only: the
+    // padded identity is a fixed point of the iteration and must stay exactly
+    // I (a scaled padding entry 1/s_g would leave [-1, 1] when s_g < 1 and
+    // grow without bound).  The padding never mixes with the true block, so
+    // setting it after the product is exact.
+    const bool pad_fix = (k == 0 && !polish && MODE < 2);
     double rmax = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
@@ -199,6 +205,7 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
                 } else {
                     val = acc[i][j][v];
                 }
+                if (pad_fix && (r >= n || c >= n)) val = (r == c) ? 1.0 : 0.0;
                 if (MODE == 4) {
                     if (r < ld && c < ld) og[r + (int64_t)c * ld] = val;
                     continue;

@@ -3,7 +3,7 @@
 // The bulk of the sign iteration (Sec. II-B) may run in low precision; the
 // paper runs the whole iteration on tensor cores in FP16, "FP16'" (FP16
 // multiply, FP32 accumulate) and FP32 and observes energies close to FP64
-// (Sec. VII-A, Table I).  Here every iterate is held as NW "words" of a
+// (Sec. VI-A, Table I).  Here every iterate is held as NW "words" of a
 // 16-bit format (FP16 or BF16): x ~ w0 + w1 + ... with w_{j+1} the rounded
 // remainder of x - (w0 + ... + w_j).  A product of two matrices becomes the
 // sum of the word products whose combined significance is kept (NW = 1: w0 w0;
@@ -248,7 +248,13 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (ti == 0 && tj == 0 && threadIdx.x == 0) {
                 it.done[g] = 1;
                 it.kfinal[g] = k;
-                it.flags[g] = finite ? 0 : 2;
+                // Not converged (bit 0) when the bulk leaves above the switch
+                // threshold, by the stall rule or at the step cap: the polish
+                // then cannot reach the FP64 tolerance.  The single-word format
+                // stalls at its rounding floor (~1e-2) by design; it is flagged
+                // only when it leaves before the quadratic phase (tau > 0.1).
+                const double conv = NW == 1 ? 0.1 : switch_tol;
+                it.flags[g] = !finite ? 2 : (tau > conv ? 1 : 0);
                 atomicAdd(it.ndone, 1);
             }
             return;
@@ -574,7 +580,8 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             if (ti == 0 && tj == 0 && threadIdx.x == 0) {
                 it.done[g] = 1;
                 it.kfinal[g] = k;
-                it.flags[g] = finite ? 0 : 2;
+                // not converged (bit 0) when the bulk leaves above the switch threshold
+                it.flags[g] = !finite ? 2 : (tau > switch_tol ? 1 : 0);
                 atomicAdd(it.ndone, 1);
             }
             return;
@@ -776,8 +783,15 @@ void gather_words_kernel(const int2 *__restrict__ chunks, const GroupDesc *__res
         for (int q = 0; q < NW; q++) p[32 * q] = w[q];
     };
     gather_row(gd, r, rinfo, bmap, boffs, valoff, kvals, mu, store);
-    for (int c = gd.n; c < ld; c++)       // padding columns: the identity, scaled like the rest
-        store(c, r == c ? 1.0 : 0.0);
+    // padding columns: exactly the identity (not prescaled): 1 is a fixed point
+    // of the iteration, whereas 1/s_g would leave [-1, 1] for s_g < 1
+    for (int c = gd.n; c < ld; c++) {
+        unsigned short w[NW];
+        split_words<FMT, NW>(r == c ? word_scale<FMT>() : 0.0, w);
+        unsigned short *p = d + word_pos(NW, ld, r, c);
+#pragma unroll
+        for (int q = 0; q < NW; q++) p[32 * q] = w[q];
+    }
 }
 
 // The same for FP32 values (column-major like the FP64 slabs).
@@ -797,7 +811,7 @@ void gather_f32_kernel(const int2 *__restrict__ chunks, const GroupDesc *__restr
     const double a = s > 0.0 ? 1.0 / s : 0.0;
     float *d = dst + gd.off;
     gather_row(gd, r, rinfo, bmap, boffs, valoff, kvals, mu, [&](int c, double v) { d[r + (int64_t)c * ld] = (float)(a * v); });
-    for (int c = gd.n; c < ld; c++) d[r + (int64_t)c * ld] = (float)(a * (r == c ? 1.0 : 0.0));
+    for (int c = gd.n; c < ld; c++) d[r + (int64_t)c * ld] = (r == c) ? 1.0f : 0.0f;   // the identity, not prescaled
 }
 
 // fp64 copy of the bulk result X_kfinal (sum of its words).

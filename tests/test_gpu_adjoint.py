@@ -45,17 +45,23 @@ def sym_direction(s, rng, i, j):
     return v
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x2"])
 @pytest.mark.parametrize("which", ["water16", "ragged"])
-def test_backward_matches_oracle_gradient(smx, oracle_lib, which):
+def test_backward_matches_oracle_gradient(smx, oracle_lib, which, precision):
+    """The adjoint after a forward in any precision mode differentiates the
+    frozen FP64 map of that evaluation (its step counts k_g, bulk plus polish,
+    and scales s_g); the oracle evaluates the same map by Daleckii-Krein.  The
+    forward's D itself is the reduced-precision one (1e-6 bar against the
+    frozen map's D)."""
     if which == "water16":
         s = water_config("water16")
     else:
-        s = random_block_system(61, [5, 3, 8, 2, 6, 4, 7], density=0.5, coupling=0.05,
-                                groups=[[0, 1], [2], [3, 4, 5], [6]], mu=0.02)
+        s = random_block_system(61, [5, 3, 8, 2, 6, 4, 7, 13, 5, 5], density=0.5, coupling=0.05,
+                                groups=[[0, 1], [2], [3, 4, 5], [6], [7, 8, 9]], mu=0.02)
     rng = np.random.default_rng(7)
     gd = rng.normal(size=s.values.shape)
     ge, gn = 1.0, 0.5
-    ctx = smx.Context(0).load(s).configure(precision="fp64")
+    ctx = smx.Context(0).load(s).configure(precision=precision)
     res = ctx.evaluate()
     info = ctx.group_info()
     dk, dmu = ctx.backward(ge, gn, gd)
@@ -64,11 +70,13 @@ def test_backward_matches_oracle_gradient(smx, oracle_lib, which):
     a = oracle_lib.symmetric_part(s, dk)
     b = oracle_lib.symmetric_part(s, ref["dk"])
     err = np.abs(a - b).max()
-    print(f"{which}: max|sym(dK) gpu - oracle| = {err:.2e} (max |dK| {np.abs(b).max():.2e}); "
-          f"dL/dmu gpu {dmu:.10e} oracle {ref['dmu']:.10e}")
+    derr = np.abs(res.d_values - ref["d_values"]).max()
+    print(f"{which} {precision} forward: max|sym(dK) gpu - oracle| = {err:.2e} (max |dK| {np.abs(b).max():.2e}); "
+          f"dL/dmu gpu {dmu:.10e} oracle {ref['dmu']:.10e}; max|D - D_frozen| = {derr:.1e}; "
+          f"k_g {info['iters'].min()}-{info['iters'].max()}")
     assert err <= 1e-9
     assert abs(dmu - ref["dmu"]) <= 1e-9 * max(1.0, abs(ref["dmu"]))
-    assert np.abs(res.d_values - ref["d_values"]).max() <= 1e-10
+    assert derr <= (1e-10 if precision == "fp64" else 1e-6)
 
 
 def test_reverse_dn_dmu_equals_forward_tangent(smx):
@@ -85,13 +93,18 @@ def test_reverse_dn_dmu_equals_forward_tangent(smx):
 
 
 @pytest.mark.timeout(600)
-def test_backward_finite_differences_water256(smx):
-    """Config of the differentiation run: 256 molecules, 6 A cutoff."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_backward_finite_differences_water256(smx, precision):
+    """Config of the differentiation run: 256 molecules, 6 A cutoff, forward in
+    FP32 (FP64 polish) as the run specifies, and in FP64.  The gradient is that
+    of the frozen map of the forward evaluation; the finite differences
+    evaluate that frozen map (FP64, same k_g and s_g)."""
     s = water_config("water256")
-    ctx = smx.Context(0).load(s).configure(precision="fp64")
+    ctx = smx.Context(0).load(s).configure(precision=precision)
     ctx.evaluate()
     dk, _ = ctx.backward(1.0, 0.0)
     smx.smx_set_frozen(ctx.handle, True)
+    ctx.configure(precision="fp64")
     rng = np.random.default_rng(2024)
     h = 1e-6
     worst = 0.0
@@ -112,7 +125,8 @@ def test_backward_finite_differences_water256(smx):
         worst = max(worst, abs(fd - ad) / max(1.0, abs(ad)))
         assert abs(fd - ad) <= 1e-5 * max(1.0, abs(ad)), (i, j, fd, ad)
     ctx.close()
-    print(f"water256 dE/dK: 20 symmetric block directions, worst |FD - AD| / max(1, |AD|) = {worst:.2e}")
+    print(f"water256 dE/dK ({precision} forward): 20 symmetric block directions, "
+          f"worst |FD - AD| / max(1, |AD|) = {worst:.2e}")
 
 
 def test_torch_autograd_function(smx):

@@ -11,7 +11,7 @@ h = 1e-5) to 1e-6 relative, and the mu search to |N_k(mu*) - N_e| <= 1e-8
 import numpy as np
 import pytest
 
-from waterbox import water_config, water_system
+from waterbox import water_config, block_offsets, water_system
 
 pytestmark = pytest.mark.gpu
 
@@ -83,17 +83,41 @@ def test_find_mu_reaches_target(smx, oracle_lib):
     assert abs(n_or - target) <= 1e-8 + 1e-9
 
 
-@pytest.mark.timeout(300)
+def lapack_frozen_count(s, mu, k, scale):
+    """N_k(mu) of Algorithm 1 with the k-step polynomial in place of signum,
+    by the independent dense-index route (the pinned route of the oracle tests:
+    the submatrix of every group taken from the dense K, eigenpairs by LAPACK),
+    with the own-column weights w_l = sum_{c in own} Q_cl^2."""
+    import oracle
+    kd = s.to_dense()
+    boff = block_offsets(s.blk_size)
+    stored = np.zeros((s.nblk, s.nblk), dtype=bool)
+    for j in range(s.nblk):
+        stored[s.row_idx[s.col_ptr[j]:s.col_ptr[j + 1]], j] = True
+    tot = 0.0
+    for g in range(s.ngroups):
+        cols = s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]
+        rows = np.nonzero(stored[:, cols].any(axis=1))[0]
+        idx = np.concatenate([np.arange(boff[r], boff[r + 1]) for r in rows])
+        lam, q = np.linalg.eigh(kd[np.ix_(idx, idx)])
+        own = np.searchsorted(idx, np.concatenate([np.arange(boff[j], boff[j + 1]) for j in cols]))
+        w = (q[own, :] ** 2).sum(axis=0)
+        tot += float((w * 0.5 * (1.0 - oracle.ns_poly((lam - mu) / scale[g], k[g]))).sum())
+    return tot
+
+
+@pytest.mark.timeout(600)
 def test_find_mu_water256(smx):
     """The 256-molecule system: mu search to N_e = n/2 within 1e-8 on the
-    frozen map.  The oracle pin of N_k(mu*) is the water16 case above (the
-    Jacobi eigenpairs of all 256 groups take minutes); here the search's frozen
-    map is evaluated again at mu*, its slope must be positive, and central
+    frozen map.  Pinned by the independent LAPACK route: N_k(mu*) from every
+    group's eigenpairs at the search's k_g and s_g.  The search's frozen map is
+    also evaluated again at mu*: its slope must be positive and central
     differences of it must match that slope."""
     s = water_config("water256")
     ctx = smx.Context(0).load(s).configure(precision="fp64")
     target = s.n / 2
     mu, steps = smx.smx_find_mu(ctx.handle, target, 1e-8, 60)
+    info = ctx.group_info()        # the last evaluation was the frozen one at mu*
     # the search's last evaluation ran the frozen map at mu*: freeze it again
     smx.smx_set_frozen(ctx.handle, True)
     n0, d0 = n_and_slope(smx, ctx, mu)
@@ -105,3 +129,6 @@ def test_find_mu_water256(smx):
     assert d0 > 0
     assert abs(fd - d0) <= 1e-5 * abs(d0)
     assert abs(n0 - target) <= 1e-8 + 1e-9
+    n_ref = lapack_frozen_count(s, mu, info["iters"], info["scale"])
+    print(f"water256: LAPACK-route N_k(mu*) - N_e = {n_ref - target:.2e}")
+    assert abs(n_ref - target) <= 1e-8 + 1e-9

@@ -103,3 +103,26 @@ def test_frozen_gradient_dmu_equals_tangent_form(oracle_lib):
     scale = [4.0] * s.ngroups
     r = oracle_lib.frozen_gradient(s, k, scale, 0.02, gN=1.0)
     assert abs(r["dmu"] - spec.dn_dmu_frozen(0.02, k, scale)) <= 1e-10 * max(1.0, abs(r["dmu"]))
+
+
+def test_frozen_forward_equals_submatrix_at_large_k(oracle_lib):
+    """frozen_gradient's forward outputs (D, N, E) are the k-step map
+    D = (I - p_k(A_g / s_g)) / 2; with k = 80 steps every eigenvalue with
+    |lambda| / s_g >= 1e-3 has reached +-1 to rounding (1.5^80 >> 1e3), so the
+    map must equal the oracle's Jacobi submatrix D (signum of the eigenvalues)."""
+    from waterbox import water_config, random_block_system
+    for s in (water_config("water16"),
+              random_block_system(23, [5, 3, 8, 2, 6, 4, 7, 5], density=0.5, coupling=0.05,
+                                  groups=[[0, 1], [2], [3, 4, 5], [6, 7]], mu=0.02)):
+        k = np.full(s.ngroups, 80)
+        scale = np.zeros(s.ngroups)
+        ref = oracle_lib.submatrix(s)
+        # a bound on each group's spectral radius, so that every |lambda / s| <= 1
+        for g in range(s.ngroups):
+            _, lam, _, _ = oracle_lib.group_eig(s, g)
+            scale[g] = 1.05 * np.abs(lam).max()
+            assert np.abs(lam).min() / scale[g] > 1e-3
+        fz = oracle_lib.frozen_gradient(s, k, scale, s.mu)
+        assert np.abs(fz["d_values"] - ref.d_values).max() <= 1e-12
+        assert abs(fz["n_elec"] - ref.n_elec) <= 1e-11
+        assert abs(fz["energy"] - ref.energy) <= 1e-11

@@ -338,3 +338,17 @@ def test_truncation_error_vs_full_matrix_sign_is_reported(oracle_lib):
     assert rep["N_exact"] == s.n / 2
     assert 1e-4 < rep["max_abs_dD"] < 5e-2
     assert abs(rep["dN"]) < 0.05
+
+
+def test_oracle_refuses_asymmetric_k(oracle_lib):
+    """Step 1 reads K as symmetric: a perturbed mirror block, or a stored block
+    whose mirror is missing, makes the oracle refuse the input."""
+    from waterbox import random_block_system
+    s = random_block_system(5, [3, 4, 2, 5], density=0.8, coupling=0.05, groups="column")
+    oracle_lib.submatrix(s)                       # symmetric: accepted
+    voff = s.val_off()
+    p = next(p for j in range(s.nblk) for p in range(s.col_ptr[j], s.col_ptr[j + 1]) if s.row_idx[p] != j)
+    v = s.values.copy()
+    v[voff[p]] += 1e-6
+    with pytest.raises(RuntimeError):
+        oracle_lib.submatrix(s.with_values(v))

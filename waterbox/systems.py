@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-# Basis functions per atom (DZVP-like sizes, Sec. VI-D mentions DZVP; the
+# Basis functions per atom (DZVP-like sizes, Sec. V-C mentions DZVP; the
 # paper's DBCSR blocks are "typically 5-30 rows and columns", Sec. II-C).
 O_BLOCK = 13
 H_BLOCK = 5
