@@ -219,6 +219,8 @@ def main():
                          "done by default up to 8000 basis functions)")
     ap.add_argument("--backward", action="store_true",
                     help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
+    ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1],
+                    help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the Newton-Schulz steps from HIP graphs of this many steps (0: direct launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -252,6 +254,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = smx.Context(0, stream=stream.cuda_stream).load(system)
+    smx.smx_set_kernel_variant(ctx.handle, args.kernel_variant)
     d64 = torch.empty(ctx.nvalues, dtype=torch.float64, device="cuda")
     d_mix = torch.empty_like(d64)
 
@@ -337,6 +340,7 @@ def main():
             "tol": 1e-12,
             "waves": int(stats["nwaves"]),
             "graph_steps": args.graph_steps,
+            "kernel_variant": args.kernel_variant,
         },
         "device_ms_per_D_median": float(np.median(run["dev_ms"])),
         "phase_ms": {"gather": stats["time_gather_ms"], "iterate": stats["time_iterate_ms"],

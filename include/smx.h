@@ -190,6 +190,15 @@ int32_t smx_set_graph(smx_ctx ctx, int32_t steps_per_graph);
 int32_t smx_set_tile_order(smx_ctx ctx, int32_t order);
 
 /*
+ * Operand stream of the reduced-precision word products: 0 (default) loads
+ * each K step of both operand panels straight into LDS and waits for it;
+ * 1 loads the next K step into registers while the matrix cores work on the
+ * current one from LDS (groups with 3 n_pad^2 >= 2^31 words fall back to 0).
+ * Results are bitwise the same.
+ */
+int32_t smx_set_kernel_variant(smx_ctx ctx, int32_t variant);
+
+/*
  * Autotuner.  Times whole evaluations of the loaded problem (current
  * precision, groups and mu) for every candidate launch configuration, the
  * tile launch order (smx_set_tile_order) x steps per graph (0, 2, 8;
@@ -220,10 +229,44 @@ int32_t smx_autotune(smx_ctx ctx, int32_t reps, int32_t use_cache, int32_t *grap
 int32_t smx_set_workspace_limit(smx_ctx ctx, int64_t bytes);
 
 /*
+ * Caller-owned work space, e.g. a torch tensor.  smx_workspace_size gives the
+ * bytes of a work space that holds every submatrix of the loaded problem at
+ * once (one wave): the arena of dense slabs / reduced-precision words (26
+ * bytes per padded element) and the own-column blocks of the polish (72
+ * bytes per n_pad x m_own element), with alignment slack.  It builds the plan
+ * for the current groups if needed.
+ * smx_set_workspace(ctx, dptr, bytes) makes evaluations use [dptr, dptr +
+ * bytes) instead of memory the library allocates: dptr is device memory of
+ * the context's device, 256-byte aligned; the caller keeps it allocated and
+ * does not touch it while the context may use it (until the next
+ * smx_set_workspace or smx_destroy).  A work space smaller than
+ * smx_workspace_size runs the groups in waves (as smx_set_workspace_limit);
+ * one too small for the largest group makes evaluations fail with
+ * SMX_E_NOMEM.  dptr = NULL with bytes = 0 returns to library-allocated
+ * memory.  Results are bitwise those of the library-allocated arena.  The
+ * adjoint (smx_backward) and the mu tangent of frozen evaluations keep using
+ * library-allocated buffers.  Synchronises the stream; invalidates results.
+ */
+int32_t smx_workspace_size(smx_ctx ctx, size_t *bytes);
+int32_t smx_set_workspace(smx_ctx ctx, void *dptr, size_t bytes);
+
+/*
+ * Host polling.  on = 1 (default): smx_evaluate reads the finished-group
+ * counter one step (or one step graph) behind the device and stops enqueueing
+ * steps once every group is done, which synchronises the host with the stream
+ * during the call.  on = 0: smx_evaluate enqueues every step up to the cap
+ * (max_iter, or max_iter - n_polish bulk steps) without waiting on the
+ * device; finished groups skip on the device, so results are bitwise the
+ * same, at the cost of the launches past convergence.  With smx_set_graph the
+ * steps are replayed from graphs either way.
+ */
+int32_t smx_set_host_poll(smx_ctx ctx, int32_t on);
+
+/*
  * Evaluate D, N and E for the current K, groups and mu.  The work is
  * enqueued on the context's stream; the call returns after enqueueing it
- * (the host only polls a small counter to stop the iteration when every
- * group has converged).  D stays resident on the device.
+ * (with host polling on, the host only polls a small counter to stop the
+ * iteration when every group has converged).  D stays resident on the device.
  */
 int32_t smx_evaluate(smx_ctx ctx);
 
@@ -258,6 +301,21 @@ int32_t smx_get_stats(smx_ctx ctx, smx_stats *out);
  */
 int32_t smx_get_group_info(smx_ctx ctx, int32_t *n_g, int32_t *iters,
                            double *scale, double *resid);
+
+/*
+ * Convergence history of the last evaluation (the involutority and trace
+ * histories behind the paper's GPU convergence plot, Sec. VI-A): for every
+ * group g, nsteps[g] = k_g + 1 bulk steps were taken (k_g: the step whose
+ * X_k was the bulk result), and for k < min(cap, nsteps[g]):
+ *   resid[g * cap + k] = max|X_k^2 - I| (FP64 mode: over the true n_g x n_g
+ *       block in FP64; reduced-precision modes: over its lower triangle, from
+ *       the FP32-accumulated square),
+ *   tau[g * cap + k]   = Tr(I - X_k^2) (reduced-precision modes; NaN in FP64
+ *       mode, which does not form it).
+ * Entries k >= nsteps[g] are NaN.  Host arrays of ngroups * cap (resid, tau)
+ * and ngroups (nsteps) entries, each nullable.  Synchronises.
+ */
+int32_t smx_get_history(smx_ctx ctx, int32_t cap, double *resid, double *tau, int32_t *nsteps);
 
 /*
  * Dense submatrix of group g (Sec. III-A: the submatrix a_i and its result

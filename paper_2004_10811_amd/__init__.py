@@ -67,6 +67,7 @@ SIGNATURES = {
     "smx_set_workspace_limit": (_i32, [_vp, _i64]),
     "smx_set_graph": (_i32, [_vp, _i32]),
     "smx_set_tile_order": (_i32, [_vp, _i32]),
+    "smx_set_kernel_variant": (_i32, [_vp, _i32]),
     "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
     "smx_wait": (_i32, [_vp]),
@@ -82,6 +83,10 @@ SIGNATURES = {
     "smx_dn_dmu": (_i32, [_vp, _P(_f64)]),
     "smx_find_mu": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
     "smx_backward": (_i32, [_vp, _f64, _f64, _vp, _i32, _vp, _i32, _P(_f64)]),
+    "smx_workspace_size": (_i32, [_vp, _P(ctypes.c_size_t)]),
+    "smx_set_workspace": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "smx_set_host_poll": (_i32, [_vp, _i32]),
+    "smx_get_history": (_i32, [_vp, _i32, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -222,6 +227,10 @@ def smx_set_tile_order(ctx, order=0):
     return _check(ctx, load_library().smx_set_tile_order(ctx, int(order)))
 
 
+def smx_set_kernel_variant(ctx, variant=0):
+    return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
 def smx_autotune(ctx, reps=3, use_cache=True):
     """Time the candidate launch configurations; returns (graph_steps, tile_order, best_ms)."""
     g, o, ms = _i32(), _i32(), _f64()
@@ -334,6 +343,39 @@ def smx_backward(ctx, gE: float = 0.0, gN: float = 0.0, gD=None, out=None):
                                              0 if gD is None else _on_device(gD),
                                              _ptr(out), _on_device(out), ctypes.byref(dmu)))
     return out, dmu.value
+
+
+def smx_workspace_size(ctx) -> int:
+    """Bytes of a work space holding every submatrix at once."""
+    v = ctypes.c_size_t()
+    _check(ctx, load_library().smx_workspace_size(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def smx_set_workspace(ctx, buf=None, nbytes=None):
+    """Use device memory `buf` (a torch tensor, or a raw device address with
+    `nbytes`) as the evaluation work space; None returns to library memory."""
+    if buf is None:
+        return _check(ctx, load_library().smx_set_workspace(ctx, None, 0))
+    if nbytes is None:
+        nbytes = buf.numel() * buf.element_size()
+    return _check(ctx, load_library().smx_set_workspace(ctx, _vp(_ptr(buf) if not isinstance(buf, int) else buf),
+                                                         int(nbytes)))
+
+
+def smx_set_host_poll(ctx, on: bool = True):
+    return _check(ctx, load_library().smx_set_host_poll(ctx, int(bool(on))))
+
+
+def smx_get_history(ctx, cap: int = 128):
+    """Per-group histories of the last evaluation: dict(resid, tau) of shape
+    (ngroups, cap) (NaN past each group's steps) and nsteps (ngroups,)."""
+    ng, _ = smx_get_sizes(ctx)
+    r = np.zeros((ng, cap))
+    t = np.zeros((ng, cap))
+    n = np.zeros(ng, np.int32)
+    _check(ctx, load_library().smx_get_history(ctx, int(cap), r.ctypes.data, t.ctypes.data, n.ctypes.data))
+    return dict(resid=r, tau=t, nsteps=n)
 
 
 # ---- convenience object -----------------------------------------------------

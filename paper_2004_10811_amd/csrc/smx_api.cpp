@@ -15,7 +15,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -124,9 +123,15 @@ struct smx_context {
     DevBuf<int32_t> d_bmap, d_boffs;
     DevBuf<ScatterDesc> d_scat;
     // device: work
-    DevBuf<double> d_arena;                 // one wave's slabs (see kArenaBytesPerElem)
+    DevBuf<double> d_arena;                 // one wave's slabs (see kArenaBytesPerElem), when no
+                                            // caller work space is set
     int64_t ws_limit = 0;                   // arena byte limit (0: from free device memory)
+    void *ws_ptr = nullptr;                 // caller work space (smx_set_workspace): arena, then polish pool
+    size_t ws_bytes = 0;
+    int32_t host_poll = 1;                  // 1: stop launching once every group is done (host polls);
+                                            // 0: enqueue all max_iter steps, no host synchronisation
     int32_t tile_order = 0;                 // 0: XCD-aware launch order, 1: group by group
+    int32_t kernel_variant = 0;             // operand stream of the word products (smx_set_kernel_variant)
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
@@ -167,6 +172,7 @@ struct smx_context {
     bool use_kfix = false, use_sfix = false;  // frozen step counts / scales
     bool have_tangent = false;                 // last evaluation computed dN/dmu
     bool last_sfix = false;                    // last evaluation ran on the frozen scales
+    bool eval_static = false;                  // last evaluation ran in the static scratch array
     double last_mu = 0.0;                      // mu of the last evaluation (the adjoint's A_g)
 
     // step graphs (smx_set_graph)
@@ -212,7 +218,18 @@ hipError_t upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
-double *slab(smx_ctx c, int i) { return c->d_arena.p + (size_t)i * (size_t)c->plan.work_elems; }
+// Bytes of one wave's arena (three FP64 slabs, or the words of three
+// iterates laid from byte 8E), rounded up to 256, and of its polish pool.
+int64_t arena_bytes(const Plan &P) { return (kArenaBytesPerElem * P.work_elems + 255) / 256 * 256; }
+int64_t pool_bytes(const Plan &P) { return (2 * kMaxPolishMixed + 1) * 8 * P.thin_elems; }
+
+double *arena_base(smx_ctx c) { return c->ws_ptr ? static_cast<double *>(c->ws_ptr) : c->d_arena.p; }
+double *pool_base(smx_ctx c)
+{
+    return c->ws_ptr ? reinterpret_cast<double *>(static_cast<char *>(c->ws_ptr) + arena_bytes(c->plan))
+                     : c->d_tpool.p;
+}
+double *slab(smx_ctx c, int i) { return arena_base(c) + (size_t)i * (size_t)c->plan.work_elems; }
 
 // XCD-aware launch order.  Workgroup b of a launch runs on XCD b % 8 (the
 // dispatcher deals workgroups round-robin over the 8 XCDs), and every XCD has
@@ -511,7 +528,8 @@ int32_t ensure_plan(smx_ctx c)
     c->d_tx0.release();
     c->d_tx1.release();
     c->d_adj.release();
-    int64_t budget = c->ws_limit;
+    int64_t budget = c->ws_ptr ? (int64_t)c->ws_bytes - 512 : c->ws_limit;
+    if (budget <= 0 && c->ws_ptr) return fail(c, SMX_E_NOMEM, "the work space is too small");
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
         HIP_TRY(c, hipMemGetInfo(&fr, &tot));
@@ -529,9 +547,16 @@ int32_t ensure_plan(smx_ctx c)
     }
     st = partition_waves(c, budget);
     if (st) return st;
+    // a caller work space holds the largest wave's arena and pool side by side;
+    // the largest arena and the largest pool may come from different waves, so
+    // shrink the wave budget until both fit
+    while (c->ws_ptr && arena_bytes(P) + pool_bytes(P) > (int64_t)c->ws_bytes) {
+        budget = budget * 15 / 16;
+        st = partition_waves(c, budget);
+        if (st) return st;
+    }
     st = check_plan(c);
     if (st) return st;
-    HIP_TRY(c, c->d_arena.ensure((size_t)(3 * P.work_elems)));
     HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
     HIP_TRY(c, upload(c->d_tiles_full, P.tiles_full, c->stream));
@@ -606,58 +631,76 @@ int32_t need_sync_results(smx_ctx c)
 // p-times polished sign are A_p(E), E the own-column selector (A_0(E) is a
 // gather).  Thin blocks come from a pool of 2p + 1; the residual
 // max|X_{k+p-1}^2 E - E| is taken on the innermost square of the last step.
-int32_t own_polish(smx_ctx c, int32_t g0, int32_t wng, const XSource &x, const IterState &it, int32_t *result)
+int32_t own_polish(smx_ctx c, double *pool, int32_t g0, int32_t wng, const XSource &x, const IterState &it,
+                   int32_t *result)
 {
     const Plan &P = c->plan;
     hipStream_t st = c->stream;
     const int32_t nbuf = 2 * c->n_polish + 1;
-    std::vector<char> used((size_t)nbuf, 0);
-    auto buf = [&](int i) { return c->d_tpool.p + (size_t)i * (size_t)P.thin_elems; };
-    auto take = [&]() -> int {
-        for (int i = 0; i < nbuf; i++)
-            if (!used[i]) {
-                used[i] = 1;
-                return i;
-            }
-        return -1;
-    };
+    char used[2 * kMaxPolishMixed + 1] = {0};
     const int slot = c->max_iter + c->n_polish;
     hipError_t herr = hipSuccess;
-    std::function<int(int, int, bool)> apply = [&](int j, int zi, bool top) -> int {
-        if (herr != hipSuccess) return -1;
-        if (j == 1) {
-            const int a = take();
-            if (a < 0) return -1;
-            herr = zi < 0 ? launch_own_gather(st, g0, wng, P.max_npad, c->d_gd.p, c->d_own.p, x, buf(a))
-                          : launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(zi), nullptr, buf(a));
-            const int b = take();
-            if (b < 0) return -1;
-            if (herr == hipSuccess)
-                herr = launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(a), nullptr, buf(b));
-            if (top && herr == hipSuccess)
-                herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(b), it, slot);
-            const int out = take();
-            if (out < 0) return -1;
-            if (herr == hipSuccess)
-                herr = launch_thin_mul(st, 1, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(b), buf(a), buf(out));
-            used[a] = used[b] = 0;
-            return out;
+    struct Poly {
+        // own columns of A_j(Z) for Z in buffer zi (zi < 0: the selector E);
+        // returns the result's buffer, or -1
+        smx_ctx c;
+        const Plan &P;
+        hipStream_t st;
+        int32_t g0, wng, slot;
+        const XSource &x;
+        const IterState &it;
+        char *used;
+        int nbuf;
+        double *pool;
+        hipError_t &herr;
+        double *buf(int i) const { return pool + (size_t)i * (size_t)P.thin_elems; }
+        int take()
+        {
+            for (int i = 0; i < nbuf; i++)
+                if (!used[i]) {
+                    used[i] = 1;
+                    return i;
+                }
+            return -1;
         }
-        const int aa = apply(j - 1, zi, false);
-        if (aa < 0) return -1;
-        const int bb = apply(j - 1, aa, false);
-        if (bb < 0) return -1;
-        if (top && herr == hipSuccess)
-            herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(bb), it, slot);
-        const int cc = apply(j - 1, bb, false);
-        if (cc < 0) return -1;
-        used[bb] = 0;
-        if (herr == hipSuccess)
-            herr = launch_thin_combine(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, buf(aa), buf(cc));
-        used[aa] = 0;
-        return cc;
-    };
-    const int r = apply(c->n_polish, -1, true);
+        int apply(int j, int zi, bool top)
+        {
+            if (herr != hipSuccess) return -1;
+            if (j == 1) {
+                const int a = take();
+                if (a < 0) return -1;
+                herr = zi < 0 ? launch_own_gather(st, g0, wng, P.max_npad, c->d_gd.p, c->d_own.p, x, buf(a))
+                              : launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(zi), nullptr,
+                                                buf(a));
+                const int b = take();
+                if (b < 0) return -1;
+                if (herr == hipSuccess)
+                    herr = launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(a), nullptr, buf(b));
+                if (top && herr == hipSuccess)
+                    herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(b), it, slot);
+                const int out = take();
+                if (out < 0) return -1;
+                if (herr == hipSuccess)
+                    herr = launch_thin_mul(st, 1, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(b), buf(a), buf(out));
+                used[a] = used[b] = 0;
+                return out;
+            }
+            const int aa = apply(j - 1, zi, false);
+            if (aa < 0) return -1;
+            const int bb = apply(j - 1, aa, false);
+            if (bb < 0) return -1;
+            if (top && herr == hipSuccess)
+                herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(bb), it, slot);
+            const int cc = apply(j - 1, bb, false);
+            if (cc < 0) return -1;
+            used[bb] = 0;
+            if (herr == hipSuccess)
+                herr = launch_thin_combine(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, buf(aa), buf(cc));
+            used[aa] = 0;
+            return cc;
+        }
+    } poly{c, P, st, g0, wng, slot, x, it, used, nbuf, pool, herr};
+    const int r = poly.apply(c->n_polish, -1, true);
     if (herr != hipSuccess)
         return fail(c, herr == hipErrorOutOfMemory ? SMX_E_NOMEM : SMX_E_HIP,
                     std::string("own-column polish: ") + hipGetErrorString(herr));
@@ -935,6 +978,15 @@ int32_t smx_set_tile_order(smx_ctx c, int32_t order)
     return SMX_OK;
 }
 
+int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
+{
+    if (!c) return SMX_E_INVALID;
+    if (variant != 0 && variant != 1) return fail(c, SMX_E_INVALID, "variant must be 0 or 1");
+    if (variant != c->kernel_variant) drop_graphs(c);
+    c->kernel_variant = variant;
+    return SMX_OK;
+}
+
 int32_t smx_set_workspace_limit(smx_ctx c, int64_t bytes)
 {
     if (!c) return SMX_E_INVALID;
@@ -947,63 +999,110 @@ int32_t smx_set_workspace_limit(smx_ctx c, int64_t bytes)
     return SMX_OK;
 }
 
-int32_t smx_evaluate(smx_ctx c)
+}  // extern "C"
+
+namespace {
+
+// Settings of one evaluation, derived from the context.
+struct EvalMode {
+    int fmt = -1, nw = 0;          // storage of the reduced-precision bulk (fmt < 0: FP64)
+    bool mixed = false;
+    bool tangent = false;          // the mu tangent rides along (frozen step counts)
+    int32_t stride = 0;            // residual / tau history slots per group
+    int32_t kmax = 0;              // last bulk step
+};
+
+int32_t eval_mode(smx_ctx c, EvalMode &m)
 {
-    if (!c) return SMX_E_INVALID;
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (c->kT > 0.0) return fail(c, SMX_E_UNSUPPORTED, "finite temperature (kT > 0) is not implemented on the GPU path");
-    int fmt = -1, nw = 0;
     switch (c->precision) {
     case SMX_FP64: break;
-    case SMX_FP16_2W: fmt = 0; nw = 2; break;
-    case SMX_BF16_3W: fmt = 1; nw = 3; break;
-    case SMX_BF16_1W: fmt = 1; nw = 1; break;
-    case SMX_FP32: fmt = 2; nw = 2; break;       // one FP32 value = two 16-bit storage units
+    case SMX_FP16_2W: m.fmt = 0; m.nw = 2; break;
+    case SMX_BF16_3W: m.fmt = 1; m.nw = 3; break;
+    case SMX_BF16_1W: m.fmt = 1; m.nw = 1; break;
+    case SMX_FP32: m.fmt = 2; m.nw = 2; break;       // one FP32 value = two 16-bit storage units
     default: return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented on the GPU path");
     }
-    const bool mixed = fmt >= 0;
+    m.mixed = m.fmt >= 0;
     const bool frozen = c->use_kfix || c->use_sfix;
-    if (frozen && mixed)
+    if (frozen && m.mixed)
         return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) runs in SMX_FP64 only");
-    if (mixed && c->max_iter <= c->n_polish)
+    if (m.mixed && c->max_iter <= c->n_polish)
         return fail(c, SMX_E_INVALID, "max_iter must exceed n_polish in reduced-precision modes");
-    if (mixed && c->n_polish > kMaxPolishMixed)
+    if (m.mixed && c->n_polish > kMaxPolishMixed)
         return fail(c, SMX_E_INVALID, "n_polish above " + std::to_string(kMaxPolishMixed) +
                                           " in a reduced-precision mode (the own-column polish costs 3^n_polish - 1 "
                                           "passes over each submatrix)");
-    if (int32_t st = set_device(c)) return st;
-    c->evaluated = false;
+    m.tangent = c->use_kfix;
+    m.stride = c->max_iter + 2 + c->n_polish;
+    m.kmax = m.mixed ? c->max_iter - c->n_polish : c->max_iter;
+    return SMX_OK;
+}
+
+// Every allocation an evaluation needs except the arena and the polish pool:
+// the plan, per-group state and histories, the pinned polling buffer, events,
+// and the tangent buffers of frozen evaluations.
+int32_t eval_prepare(smx_ctx c, const EvalMode &m)
+{
     if (int32_t st = ensure_plan(c)) return st;
     const Plan &P = c->plan;
     const int32_t ng = P.ngroups;
-    const int32_t stride = c->max_iter + 2 + c->n_polish;
-    HIP_TRY(c, c->d_resid.ensure((size_t)ng * stride));
+    HIP_TRY(c, c->d_resid.ensure((size_t)ng * m.stride));
     const int32_t tau_nt = (P.max_npad + kTile - 1) / kTile;
     HIP_TRY(c, c->d_tau_parts.ensure((size_t)ng * std::max(tau_nt, 1)));
-    HIP_TRY(c, c->d_tau_hist.ensure((size_t)ng * stride));
-    if (c->h_ndone_cap < stride) {
+    HIP_TRY(c, c->d_tau_hist.ensure((size_t)ng * m.stride));
+    if (c->h_ndone_cap < m.stride) {
         if (c->h_ndone) (void)hipHostFree(c->h_ndone);
         c->h_ndone = nullptr;
-        HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_ndone), sizeof(int32_t) * stride));
-        c->h_ndone_cap = stride;
+        c->h_ndone_cap = 0;
+        HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_ndone), sizeof(int32_t) * m.stride));
+        c->h_ndone_cap = m.stride;
     }
-    while ((int32_t)c->ev_poll.size() < stride) {
+    while ((int32_t)c->ev_poll.size() < m.stride) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         c->ev_poll.push_back(ev);
     }
-    if (mixed) {
-        HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1)));
-        // words of X_a, X_b and W from byte 8E to 8E + 6 nw E of the arena
-        const size_t need = (size_t)((8 * P.work_elems + 6 * (int64_t)nw * P.work_elems + 7) / 8);
-        if (c->d_arena.cap < need) HIP_TRY(c, c->d_arena.ensure(need));
-    }
-    const int32_t nwave = P.nwaves();
-    while ((int32_t)c->ev_wave.size() < 4 * nwave) {
+    while ((int32_t)c->ev_wave.size() < 4 * P.nwaves()) {
         hipEvent_t ev;
         HIP_TRY(c, hipEventCreate(&ev));
         c->ev_wave.push_back(ev);
     }
+    if (c->use_sfix) HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
+    if (m.tangent) {
+        HIP_TRY(c, c->d_tx0.ensure((size_t)P.work_elems));
+        HIP_TRY(c, c->d_tx1.ensure((size_t)P.work_elems));
+        HIP_TRY(c, c->d_dnp.ensure((size_t)std::max(ng, 1)));
+        HIP_TRY(c, c->d_dn.ensure(2));
+    }
+    return SMX_OK;
+}
+
+// The library's own arena (and polish pool) when the caller set no work space.
+int32_t ensure_arena(smx_ctx c, bool pool)
+{
+    if (c->ws_ptr) return SMX_OK;
+    const Plan &P = c->plan;
+    HIP_TRY(c, c->d_arena.ensure((size_t)(arena_bytes(P) / 8)));
+    if (pool) HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1)));
+    return SMX_OK;
+}
+
+// Enqueue one evaluation on the context's stream.  `arena` holds the largest
+// wave's three slabs (or the words of three iterates from byte 8E), `pool`
+// the own-column blocks of the polish (2 n_polish + 1 of them).  With
+// `timing`, HIP events bracket every product launch (smx_get_launch_profile);
+// `graphs` allows the step graphs of smx_set_graph.  Nothing is allocated
+// here unless `timing` or `graphs` ask for events or graph captures.
+int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, bool timing, bool graphs)
+{
+    const Plan &P = c->plan;
+    const int32_t ng = P.ngroups;
+    const int32_t fmt = m.fmt, nw = m.nw;
+    const bool mixed = m.mixed, tangent = m.tangent;
+    const int32_t stride = m.stride, kmax = m.kmax;
+    const int32_t nwave = P.nwaves();
     hipStream_t st = c->stream;
     IterState it;
     it.scale_bits = c->d_scale.p;
@@ -1017,20 +1116,8 @@ int32_t smx_evaluate(smx_ctx c)
     it.tau_parts = c->d_tau_parts.p;
     it.tau_hist = c->d_tau_hist.p;
     it.resid_stride = stride;
-    it.tau_nt = std::max(tau_nt, 1);
-
-    // the mu tangent is carried whenever the step count is frozen (FP64)
-    const bool tangent = c->use_kfix;
-    if (c->use_sfix) {
-        HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
-        it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
-    }
-    if (tangent) {
-        HIP_TRY(c, c->d_tx0.ensure((size_t)P.work_elems));
-        HIP_TRY(c, c->d_tx1.ensure((size_t)P.work_elems));
-        HIP_TRY(c, c->d_dnp.ensure((size_t)std::max(ng, 1)));
-        HIP_TRY(c, c->d_dn.ensure(2));
-    }
+    it.tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
+    if (c->use_sfix) it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
     unsigned long long *gather_scale = c->use_sfix ? c->d_scale_scratch.p : it.scale_bits;
     HIP_TRY(c, hipEventRecord(c->ev_t0, st));
     HIP_TRY(c, hipMemsetAsync(gather_scale, 0, sizeof(unsigned long long) * ng, st));
@@ -1060,23 +1147,26 @@ int32_t smx_evaluate(smx_ctx c)
         return e;
     };
     const int64_t welems = P.work_elems;        // an operand's words take nw * welems 16-bit units
-    double *xb[2] = {slab(c, 0), slab(c, 1)};
-    double *wslab = slab(c, 2);
-    unsigned short *wbase = reinterpret_cast<unsigned short *>(slab(c, 1));
+    double *xb[2] = {arena, arena + welems};
+    double *wslab = arena + 2 * welems;
+    unsigned short *wbase = reinterpret_cast<unsigned short *>(arena + welems);
     unsigned short *wb[2] = {wbase, wbase + (size_t)nw * welems};
     unsigned short *wwp = wbase + (size_t)2 * nw * welems;
     double *tb[2] = {c->d_tx0.p, c->d_tx1.p};
     double *thin_result = nullptr;
-    const int32_t kmax = mixed ? c->max_iter - c->n_polish : c->max_iter;
     int32_t launched = 0;
-    if (c->graph_steps > 0) {
+    const bool use_graphs = graphs && c->graph_steps > 0;
+    // the register-prefetch stream indexes a group's words with 32-bit offsets
+    const int32_t variant =
+        (c->kernel_variant == 1 && (int64_t)std::max(nw, 1) * P.max_npad * P.max_npad < (int64_t)INT32_MAX) ? 1 : 0;
+    if (use_graphs) {
         // replayable step graphs: valid while everything baked into their
         // launches (plan, buffers, mode and convergence settings) is unchanged
         if (!c->cap_stream) HIP_TRY(c, hipStreamCreate(&c->cap_stream));
         const std::vector<uint64_t> sig = {
             c->plan_gen, (uint64_t)c->precision, (uint64_t)c->max_iter, (uint64_t)c->n_polish,
             (uint64_t)c->graph_steps, (uint64_t)tangent, (uint64_t)c->use_sfix, (uint64_t)c->use_kfix,
-            (uint64_t)(uintptr_t)c->d_arena.p, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
+            (uint64_t)c->kernel_variant, (uint64_t)(uintptr_t)arena, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
             (uint64_t)(uintptr_t)c->d_resid.p, (uint64_t)(uintptr_t)c->d_tau_parts.p, (uint64_t)(uintptr_t)c->d_tau_hist.p,
             (uint64_t)(uintptr_t)c->d_sfix.p, (uint64_t)(uintptr_t)c->d_kfix.p,
             __builtin_bit_cast(uint64_t, c->tol), __builtin_bit_cast(uint64_t, c->switch_tol)};
@@ -1124,22 +1214,24 @@ int32_t smx_evaluate(smx_ctx c)
                     e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, c->d_gd.p, tb[k & 1], wslab, tb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
             } else {
-                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, ntiles, tl, c->d_gd.p, wb[k & 1], wb[k & 1], wwp,
-                                                        it, k, c->switch_tol, kmax); });
+                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, ntiles, tl, c->d_gd.p, wb[k & 1],
+                                                        wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
                 if (e == hipSuccess)
-                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, ntiles, tl, c->d_gd.p, wb[k & 1], wwp,
-                                                            wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
+                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, ntiles, tl, c->d_gd.p,
+                                                            wb[k & 1], wwp, wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
             }
             return e;
         };
-        // bulk steps: every group iterates until its own stopping rule; the
-        // host polls the wave's finished-group counter one step (or one graph
-        // of graph_steps steps) behind the device
-        const int32_t S = c->graph_steps > 0 ? c->graph_steps : 1;
+        // bulk steps: every group iterates until its own stopping rule.  With
+        // host polling, the host reads the wave's finished-group counter one
+        // step (or one graph of graph_steps steps) behind the device and stops
+        // launching once all are done; without, every step up to the cap is
+        // enqueued and finished groups skip on the device
+        const int32_t S = use_graphs ? c->graph_steps : 1;
         const int32_t nchunk = kmax / S + 1;
         for (int32_t ch = 0; ch < nchunk; ch++) {
             const int32_t k0 = ch * S, k1 = std::min(k0 + S - 1, kmax);
-            if (c->graph_steps > 0) {
+            if (use_graphs) {
                 hipGraphExec_t &ex = c->graphs[(size_t)wave * nchunk + ch];
                 if (!ex) {
                     // capture on the private stream (capture does not run anything)
@@ -1156,14 +1248,16 @@ int32_t smx_evaluate(smx_ctx c)
                 }
                 HIP_TRY(c, hipGraphLaunch(ex, st));
             } else {
-                HIP_TRY(c, step(st, k0, true));
+                HIP_TRY(c, step(st, k0, timing));
             }
             launched = std::max(launched, k1 + 1);
-            HIP_TRY(c, hipMemcpyAsync(c->h_ndone + ch, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            HIP_TRY(c, hipEventRecord(c->ev_poll[ch], st));
-            if (ch >= 1) {
-                HIP_TRY(c, hipEventSynchronize(c->ev_poll[ch - 1]));
-                if (c->h_ndone[ch - 1] >= wng) break;
+            if (c->host_poll) {
+                HIP_TRY(c, hipMemcpyAsync(c->h_ndone + ch, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipEventRecord(c->ev_poll[ch], st));
+                if (ch >= 1) {
+                    HIP_TRY(c, hipEventSynchronize(c->ev_poll[ch - 1]));
+                    if (c->h_ndone[ch - 1] >= wng) break;
+                }
             }
         }
         if (mixed) {
@@ -1171,8 +1265,8 @@ int32_t smx_evaluate(smx_ctx c)
             // read from its words (converted exactly on the fly)
             const XSource xs{nullptr, wb[0], wb[1], it.kfinal, fmt, nw};
             int32_t res = -1;
-            if (int32_t e = own_polish(c, g0, wng, xs, it, &res)) return e;
-            thin_result = c->d_tpool.p + (size_t)res * (size_t)P.thin_elems;
+            if (int32_t e = own_polish(c, pool, g0, wng, xs, it, &res)) return e;
+            thin_result = pool + (size_t)res * (size_t)P.thin_elems;
             HIP_TRY(c, launch_polish_flags(st, g0, wng, it, c->max_iter + c->n_polish, c->tol));
         }
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
@@ -1203,6 +1297,23 @@ int32_t smx_evaluate(smx_ctx c)
     c->last_mu = c->mu;
     c->evaluated = true;
     return SMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t smx_evaluate(smx_ctx c)
+{
+    if (!c) return SMX_E_INVALID;
+    EvalMode m;
+    if (int32_t st = eval_mode(c, m)) return st;
+    if (int32_t st = set_device(c)) return st;
+    c->evaluated = false;
+    c->eval_static = false;
+    if (int32_t st = eval_prepare(c, m)) return st;
+    if (int32_t st = ensure_arena(c, m.mixed)) return st;
+    return eval_enqueue(c, m, arena_base(c), pool_base(c), true, true);
 }
 
 int32_t smx_wait(smx_ctx c)
@@ -1361,7 +1472,7 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
     double ws = 0;
     for (size_t b : {c->d_k.bytes(), c->d_d.bytes(), c->d_arena.bytes(), c->d_tpool.bytes(), c->d_tx0.bytes(), c->d_tx1.bytes(), c->d_adj.bytes(), c->d_bmap.bytes(),
                      c->d_rinfo.bytes(), c->d_scat.bytes(), c->d_resid.bytes(), c->d_tiles.bytes(),
-                     c->d_tiles_full.bytes(), c->d_plist.bytes()})
+                     c->d_tiles_full.bytes(), c->d_plist.bytes(), c->ws_ptr ? c->ws_bytes : (size_t)0})
         ws += (double)b;
     s.workspace_bytes = ws;
     *out = s;
@@ -1408,7 +1519,10 @@ int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32
     if (what != 0 && what != 1) return fail(c, SMX_E_INVALID, "what must be 0 or 1");
     if (int32_t st = set_device(c)) return st;
     if (what == 1 && !c->evaluated) return fail(c, SMX_E_STATE, "no evaluation has been run");
+    if (what == 1 && c->eval_static)
+        return fail(c, SMX_E_STATE, "the iterates of a static-scratch evaluation are not kept");
     if (int32_t st = ensure_plan(c)) return st;
+    if (int32_t st = ensure_arena(c, false)) return st;
     const Plan &P = c->plan;
     if (g < 0 || g >= P.ngroups) return fail(c, SMX_E_INVALID, "group index out of range");
     const GroupDesc d = P.gd[g];
@@ -1634,6 +1748,7 @@ static int32_t scales_at(smx_ctx c, double mu, std::vector<double> &out)
 {
     const Plan &P = c->plan;
     const int32_t ng = P.ngroups;
+    if (int32_t st = ensure_arena(c, false)) return st;
     HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
     HIP_TRY(c, hipMemsetAsync(c->d_scale_scratch.p, 0, sizeof(unsigned long long) * ng, c->stream));
     for (int32_t w = 0; w < P.nwaves(); w++)
@@ -1888,6 +2003,88 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     HIP_TRY(c, hipStreamSynchronize(st));
     gdd.release();
     if (dmu_out) *dmu_out = dm[0];
+    return SMX_OK;
+}
+
+int32_t smx_workspace_size(smx_ctx c, size_t *bytes)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!bytes) return fail(c, SMX_E_INVALID, "bytes is NULL");
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (int32_t st = set_device(c)) return st;
+    if (int32_t st = ensure_plan(c)) return st;
+    // every group resident at once: one wave's arena, then its polish pool
+    int64_t e = 0, t = 0;
+    for (const GroupDesc &d : c->plan.gd) {
+        e += (int64_t)d.npad * d.npad;
+        t += (int64_t)d.npad * d.m_own;
+    }
+    *bytes = (size_t)((kArenaBytesPerElem * e + 255) / 256 * 256 + (2 * kMaxPolishMixed + 1) * 8 * t + 512);
+    return SMX_OK;
+}
+
+int32_t smx_set_workspace(smx_ctx c, void *dptr, size_t bytes)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = set_device(c)) return st;
+    if ((dptr == nullptr) != (bytes == 0)) return fail(c, SMX_E_INVALID, "dptr and bytes must both be set or both be 0");
+    if (dptr) {
+        if (reinterpret_cast<uintptr_t>(dptr) % 256) return fail(c, SMX_E_INVALID, "the work space must be 256-byte aligned");
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, dptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+            attr.device != c->device) {
+            (void)hipGetLastError();
+            return fail(c, SMX_E_INVALID, "the work space is not device memory of this context's device");
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));      // no enqueued work may still use the old arena
+    c->ws_ptr = dptr;
+    c->ws_bytes = bytes;
+    c->d_arena.release();
+    c->d_tpool.release();
+    drop_graphs(c);
+    c->plan_dirty = true;
+    c->evaluated = false;
+    c->use_kfix = c->use_sfix = false;
+    c->contrib_ready = false;
+    return SMX_OK;
+}
+
+int32_t smx_set_host_poll(smx_ctx c, int32_t on)
+{
+    if (!c) return SMX_E_INVALID;
+    if (on != 0 && on != 1) return fail(c, SMX_E_INVALID, "on must be 0 or 1");
+    c->host_poll = on;
+    return SMX_OK;
+}
+
+int32_t smx_get_history(smx_ctx c, int32_t cap, double *resid, double *tau, int32_t *nsteps)
+{
+    if (!c) return SMX_E_INVALID;
+    if (cap < 0) return fail(c, SMX_E_INVALID, "cap must be >= 0");
+    if (int32_t st = need_sync_results(c)) return st;
+    const int32_t ng = c->plan.ngroups;
+    const int32_t stride = c->last_stride;
+    std::vector<int32_t> kf((size_t)ng);
+    std::vector<unsigned long long> rb((size_t)ng * stride);
+    std::vector<double> tb((size_t)ng * stride);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(rb.data(), c->d_resid.p, rb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(tb.data(), c->d_tau_hist.p, tb.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const bool has_tau = c->last_polish > 0;      // tau_k is computed by the reduced-precision bulk only
+    for (int32_t g = 0; g < ng; g++) {
+        const int32_t n = kf[g] + 1;
+        if (nsteps) nsteps[g] = n;
+        for (int32_t k = 0; k < cap; k++) {
+            double r = NAN, t = NAN;
+            if (k < n) {
+                std::memcpy(&r, &rb[(size_t)g * stride + k], sizeof r);
+                if (has_tau) t = tb[(size_t)g * stride + k];
+            }
+            if (resid) resid[(size_t)g * cap + k] = r;
+            if (tau) tau[(size_t)g * cap + k] = t;
+        }
+    }
     return SMX_OK;
 }
 

@@ -152,7 +152,10 @@ __host__ __device__ inline int64_t word_pos(int nw, int ld, int r, int c)
 
 // Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value;
 // fmt 2 = one FP32 value per element, column-major like the FP64 slabs).
-hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
+// variant: operand stream of the word products (0: global_load_lds into LDS one
+// K step at a time; 1: next K step prefetched into registers); results are
+// bitwise the same.
+hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int variant, int ntiles, const TileDesc *tiles,
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                            unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
 // Group-walking launchers take the first group g0 and the count ngroups (a wave).

@@ -183,6 +183,8 @@ __device__ inline int swz(int col) { return (col ^ (col >> 2)) & 3; }
 
 // s_waitcnt vmcnt(0) (the gfx9 encoding with expcnt and lgkmcnt left at their maxima)
 __device__ inline void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima): LDS writes done
+__device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // Workgroup barrier without the memory fence of __syncthreads(): the operand
 // loads are waited for explicitly; the empty asm statements keep the compiler
@@ -212,7 +214,11 @@ __host__ __device__ constexpr int words_lds_bytes()
     return (2 * NW * BM * BK * 2) > (BM * CSTH * 4) ? (2 * NW * BM * BK * 2) : (BM * CSTH * 4);
 }
 
-template <int FMT, int NW, int MODE>
+// RP = 0: operands go straight into LDS by global_load_lds, one K step at a
+// time.  RP = 1: the next K step's operands are loaded into registers (whole
+// 128-B lines, eight lanes per column) while the matrix cores work on the
+// current one from LDS, then written to LDS in the same swizzled layout.
+template <int FMT, int NW, int MODE, int RP>
 __global__ __launch_bounds__(256, 2)
 void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
                      const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
@@ -251,10 +257,10 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                 // Not converged (bit 0) when the bulk leaves above the switch
                 // threshold, by the stall rule or at the step cap: the polish
                 // then cannot reach the FP64 tolerance.  The single-word format
-                // stalls at its rounding floor (~1e-2) by design; it is flagged
-                // only when it leaves before the quadratic phase (tau > 0.1).
-                const double conv = NW == 1 ? 0.1 : switch_tol;
-                it.flags[g] = !finite ? 2 : (tau > conv ? 1 : 0);
+                // always leaves at its rounding floor (tau ~ 1e-2 .. 1e-1, itself
+                // noisy at that level); whether its polish converged is decided
+                // on the polished residual alone.
+                it.flags[g] = !finite ? 2 : ((NW > 1 && tau > switch_tol) ? 1 : 0);
                 atomicAdd(it.ndone, 1);
             }
             return;
@@ -294,23 +300,61 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         for (int j = 0; j < 4; j++) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int nk = ld / BK;             // ld is a multiple of 32
+    // register-prefetch path: chunk u = tid + 256 q of an operand's K step is
+    // 16-B part u % (4 NW) of tile column u / (4 NW) (word p / 4, chunk p % 4);
+    // columns beyond ld read column ld - 1 instead (their products reach only
+    // discarded outputs).  Offsets are recomputed per load to spare registers.
+    constexpr int RQ = RP ? 2 * NW : 1;     // chunks per thread and operand
+    u4 stA[RQ], stB[RQ];
+    const unsigned short *gA = xin + NW * gd.off, *gB = bin + NW * gd.off;
+    auto rp_load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const int u = tid + 256 * q;
+            const int cl = u / (4 * NW), pp = u % (4 * NW);
+            const int ca = min(ti * BM + cl, ld - 1), cb = min(tj * BM + cl, ld - 1);
+            // NW n_pad^2 < 2^31 (the host's choice of variant)
+            stA[q] = *reinterpret_cast<const u4 *>(gA + (ca * ld * NW + pp * 8 + NW * k0));
+            stB[q] = *reinterpret_cast<const u4 *>(gB + (cb * ld * NW + pp * 8 + NW * k0));
+        }
+    };
+    auto rp_store = [&]() {
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const int u = tid + 256 * q;
+            const int cl = u / (4 * NW), pp = u % (4 * NW);
+            const int d = (pp / 4) * PH + cl * BK + (((pp % 4) ^ swz(cl)) * 8);
+            *reinterpret_cast<u4 *>(Ls + d) = stA[q];
+            *reinterpret_cast<u4 *>(Ls + NW * PH + d) = stB[q];
+        }
+    };
+    if constexpr (RP) {
+        rp_load(0);
+        rp_store();
+        wait_lgkm0();
+        lds_barrier();
+    }
     for (int kt = 0; kt < nk; kt++) {
         const int k0 = kt * BK;
+        if constexpr (RP) {
+            if (kt + 1 < nk) rp_load(k0 + BK);       // in flight during this step's products
+        } else {
 #pragma unroll
-        for (int w = 0; w < NW; w++)
+            for (int w = 0; w < NW; w++)
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                unsigned short *dA = Ls + (0 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
-                unsigned short *dB = Ls + (1 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(srcA[q] + NW * k0 + 32 * w + kcoff[q]),
-                    (__attribute__((address_space(3))) void *)dA, 16, 0, 0);
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(srcB[q] + NW * k0 + 32 * w + kcoff[q]),
-                    (__attribute__((address_space(3))) void *)dB, 16, 0, 0);
-            }
-        wait_vm0();
-        lds_barrier();                  // every wave's loads of this step are in LDS
+                for (int q = 0; q < 2; q++) {
+                    unsigned short *dA = Ls + (0 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
+                    unsigned short *dB = Ls + (1 * NW + w) * PH + (wave + 4 * q) * 16 * BK;
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(srcA[q] + NW * k0 + 32 * w + kcoff[q]),
+                        (__attribute__((address_space(3))) void *)dA, 16, 0, 0);
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(srcB[q] + NW * k0 + 32 * w + kcoff[q]),
+                        (__attribute__((address_space(3))) void *)dB, 16, 0, 0);
+                }
+            wait_vm0();
+            lds_barrier();                  // every wave's loads of this step are in LDS
+        }
         if (wave_live) {
             u16x8 bv[4][NW];
 #pragma unroll
@@ -335,6 +379,13 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             }
         }
         lds_barrier();                  // every wave is done reading before the next loads land
+        if constexpr (RP) {
+            if (kt + 1 < nk) {
+                rp_store();
+                wait_lgkm0();
+                lds_barrier();          // the next step's operands are in LDS
+            }
+        }
     }
 
     // ---- epilogue, in two rounds over the column halves h of the tile (the
@@ -850,22 +901,24 @@ void f32_to_f64_kernel(const GroupDesc *__restrict__ groups, const float *__rest
 }
 
 template <int FMT, int NW>
-hipError_t launch_words_t(hipStream_t st, int mode, int ntiles, const TileDesc *tiles, const GroupDesc *groups,
-                          const unsigned short *x, const unsigned short *b, unsigned short *out,
-                          const IterState &it, int k, double switch_tol, int kmax)
+hipError_t launch_words_t(hipStream_t st, int mode, int variant, int ntiles, const TileDesc *tiles,
+                          const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
+                          unsigned short *out, const IterState &it, int k, double switch_tol, int kmax)
 {
-    if (mode == 0)
-        hipLaunchKernelGGL((ns_words_kernel<FMT, NW, 0>), dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b, out,
-                           it, k, switch_tol, kmax);
-    else
-        hipLaunchKernelGGL((ns_words_kernel<FMT, NW, 1>), dim3(ntiles), dim3(256), 0, st, tiles, groups, x, b, out,
-                           it, k, switch_tol, kmax);
+#define SMX_WK(M, R) hipLaunchKernelGGL((ns_words_kernel<FMT, NW, M, R>), dim3(ntiles), dim3(256), 0, st, tiles, \
+                                        groups, x, b, out, it, k, switch_tol, kmax)
+    if (mode == 0) {
+        if (variant == 1) SMX_WK(0, 1); else SMX_WK(0, 0);
+    } else {
+        if (variant == 1) SMX_WK(1, 1); else SMX_WK(1, 0);
+    }
+#undef SMX_WK
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
+hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int variant, int ntiles, const TileDesc *tiles,
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                            unsigned short *out, const IterState &it, int k, double switch_tol, int kmax)
 {
@@ -881,10 +934,10 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int ntiles
                                switch_tol, kmax);
         return hipGetLastError();
     }
-    if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
-    if (fmt == 0 && nw == 2) return launch_words_t<0, 2>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
-    if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
-    if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 0 && nw == 2) return launch_words_t<0, 2>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
+    if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     return hipErrorInvalidValue;
 }
 

@@ -81,9 +81,10 @@ def test_water16_bf16_single_word_is_reported(smx, oracle_lib):
     expect_nc = int(np.sum(0.75 * info["resid"] ** 2 > 1e-12))
     assert stats["n_not_converged"] == expect_nc
     assert (res.status == smx.SMX_E_NOT_CONVERGED) == (expect_nc > 0)
-    res3, info3, stats3 = run(smx, s, "bf16", allow_not_converged=True, n_polish=3)
-    print(f"water16 bf16 (1 word), 3 polish steps: status {res3.status}, max|dD| = {max_err(res3, ref):.2e}")
-    assert res3.status == smx.SMX_OK and stats3["n_not_converged"] == 0
+    res4, info4, stats4 = run(smx, s, "bf16", allow_not_converged=True, n_polish=4)
+    print(f"water16 bf16 (1 word), 4 polish steps: status {res4.status}, max|dD| = {max_err(res4, ref):.2e}, "
+          f"polished residual max {info4['resid'].max():.2e}")
+    assert res4.status == smx.SMX_OK and stats4["n_not_converged"] == 0
 
 
 @pytest.mark.parametrize("seed,sizes,dens,groups", [
@@ -177,23 +178,23 @@ def _edge_gap_system(oracle_lib, seed, sizes, gap):
     for g in range(s.ngroups):
         _, lam, _, _ = oracle_lib.group_eig(s, g, mu=mu)
         mind = min(mind, float(np.abs(lam).min()))
-    assert abs(mind - gap) <= 1e-9 * max(1.0, gap) + 1e-12
-    return s, mu
+    assert 0.5 * gap <= mind <= gap * (1 + 1e-9) + 1e-15
+    return s, mu, mind
 
 
-@pytest.mark.parametrize("gap", [1e-1, 1e-2, 1e-3])
-@pytest.mark.parametrize("precision", ["fp16x2", "bf16x3"])
+@pytest.mark.parametrize("gap", [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6])
+@pytest.mark.parametrize("precision", ["fp16x2", "bf16x3", "fp32"])
 def test_small_gap_meets_bar_or_flags(smx, oracle_lib, precision, gap):
-    """min|lambda - mu| = 1e-1, 1e-2, 1e-3 on ragged systems (several tiles and
-    ragged tails): every group either meets max|dD| <= 1e-6 against the oracle,
-    or the call reports SMX_E_NOT_CONVERGED; a converged status with a larger
-    error would be a silent failure."""
-    s, mu = _edge_gap_system(oracle_lib, 31, [13, 5, 5, 17, 9, 31, 22, 13, 27, 11, 5, 25] * 2, gap)
+    """min|lambda - mu| from 1e-1 down to 1e-6 on ragged systems (several tiles
+    and ragged tails): every group either meets max|dD| <= 1e-6 against the
+    oracle, or the call reports SMX_E_NOT_CONVERGED; a converged status with a
+    larger error would be a silent failure."""
+    s, mu, mind = _edge_gap_system(oracle_lib, 31, [13, 5, 5, 17, 9, 31, 22, 13, 27, 11, 5, 25] * 2, gap)
     ref = oracle_lib.submatrix(s, mu=mu)
     res, info, stats = run(smx, s, precision, allow_not_converged=True, mu=mu)
     err = max_err(res, ref)
     r64, _, st64 = run(smx, s, "fp64", mu=mu)
-    print(f"gap {gap:.0e} {precision}: status {res.status}, max|dD| = {err:.2e}, "
+    print(f"gap {mind:.2e} {precision}: status {res.status}, max|dD| = {err:.2e}, "
           f"not converged {stats['n_not_converged']}/{s.ngroups}, steps {stats['iters_min']}-{stats['iters_max']} "
           f"(FP64 {st64['iters_min']}-{st64['iters_max']}, max|dD| {max_err(r64, ref):.1e})")
     assert max_err(r64, ref) <= 1e-10
