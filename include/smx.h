@@ -270,6 +270,30 @@ int32_t smx_set_host_poll(smx_ctx ctx, int32_t on);
  */
 int32_t smx_evaluate(smx_ctx ctx);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as smx_evaluate, with every piece of work memory (the plan's
+ * tables, the iteration state, the dense submatrices or their words, the
+ * polish blocks) taken from one fixed device array of
+ * SMX_STATIC_SCRATCH_BYTES inside the library (one per device, held until the
+ * process ends).  The call allocates nothing: no device or pinned memory, no
+ * events, no graphs.  K and D are the context's (allocated by smx_load_k).
+ * Groups run in waves sized to the array; a problem whose tables, state and
+ * largest group do not fit returns SMX_E_NOMEM before anything is enqueued.
+ * All steps up to the cap are enqueued without host polling (as with
+ * smx_set_host_poll(0)); finished groups skip on the device.  Results (D, N,
+ * E, the status of smx_wait) are bitwise those of smx_evaluate.  Per-group
+ * details are not kept: smx_get_stats, smx_get_group_info, smx_get_history,
+ * smx_get_launch_profile, smx_get_submatrix(what = 1), smx_set_frozen and
+ * smx_backward return SMX_E_STATE after it.  Frozen evaluations are refused
+ * (SMX_E_UNSUPPORTED).  Every static evaluation on a device shares that
+ * device's array: calls that overlap in time on one device (other threads,
+ * other streams) race and give undefined results.
+ */
+#define SMX_STATIC_SCRATCH_BYTES (1024ull * 1024ull * 1024ull)
+int32_t smx_evaluate_static(smx_ctx ctx);
+
 /* Wait for the last evaluation.  SMX_E_NONFINITE if an iterate was not
  * finite; SMX_E_NOT_CONVERGED (D is still written) if any group did not
  * converge:

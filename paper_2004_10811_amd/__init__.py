@@ -70,6 +70,7 @@ SIGNATURES = {
     "smx_set_kernel_variant": (_i32, [_vp, _i32]),
     "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
+    "smx_evaluate_static": (_i32, [_vp]),
     "smx_wait": (_i32, [_vp]),
     "smx_get_d": (_i32, [_vp, _vp, _i32]),
     "smx_trace": (_i32, [_vp, _P(_f64)]),
@@ -241,6 +242,10 @@ def smx_autotune(ctx, reps=3, use_cache=True):
 
 def smx_evaluate(ctx):
     return _check(ctx, load_library().smx_evaluate(ctx))
+
+
+def smx_evaluate_static(ctx):
+    return _check(ctx, load_library().smx_evaluate_static(ctx))
 
 
 def smx_wait(ctx, allow_not_converged: bool = False):
@@ -433,6 +438,16 @@ class Context:
 
     def evaluate(self, out=None, allow_not_converged=False) -> Result:
         smx_evaluate(self.handle)
+        st = smx_wait(self.handle, allow_not_converged)
+        if out is None:
+            out = np.empty(self.nvalues)
+        smx_get_d(self.handle, out)
+        return Result(out, smx_trace(self.handle), smx_energy(self.handle), st)
+
+    def evaluate_static(self, out=None, allow_not_converged=False) -> Result:
+        """smx_evaluate_static: the same evaluation with all work memory in the
+        library's fixed scratch array (no allocation inside the call)."""
+        smx_evaluate_static(self.handle)
         st = smx_wait(self.handle, allow_not_converged)
         if out is None:
             out = np.empty(self.nvalues)

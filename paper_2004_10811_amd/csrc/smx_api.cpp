@@ -11,15 +11,26 @@
 #include "smx_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace smx;
+
+// Work memory of smx_evaluate_static: a fixed array in device memory, one
+// copy per device, held until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in for the
+// symbol); each device's address is resolved once, at smx_create, and kept
+// in g_scratch_ptr.  External linkage on purpose: the HIP runtime resolves a
+// device variable by name among the code object's exported symbols, and an
+// internal-linkage array would be a local symbol it cannot find.
+__device__ __align__(256) unsigned char smx_static_scratch[SMX_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -76,6 +87,21 @@ struct Plan {
     int32_t nwaves() const { return (int32_t)wave_g.size() - 1; }
 };
 
+// Device addresses of a plan's tables and of the per-evaluation state: the
+// context's own buffers, or places in the static scratch array.
+struct DevView {
+    const GroupDesc *gd = nullptr;
+    const TileDesc *tiles = nullptr;
+    const int2 *chunks = nullptr;
+    const RowInfo *rinfo = nullptr;
+    const int32_t *bmap = nullptr, *boffs = nullptr, *own = nullptr;
+    const ScatterDesc *scat = nullptr;
+    const int64_t *plist = nullptr;
+    unsigned long long *scale = nullptr, *resid = nullptr;
+    int32_t *done = nullptr, *kfinal = nullptr, *flags = nullptr, *ndone = nullptr;
+    double *tau_parts = nullptr, *tau_hist = nullptr, *pe = nullptr, *pn = nullptr, *ne = nullptr;
+};
+
 // Arena of one wave: three FP64 slabs X_a | X_b | W (24 bytes per element);
 // in the reduced-precision modes the words of X_a, X_b and W (nw E 16-bit
 // words each) start at byte 8E (over X_b and W, dead during the bulk) and reach 8E + 6 nw E bytes,
@@ -104,6 +130,13 @@ struct smx_context {
     std::vector<int32_t> grp_ptr, grp_blocks;
     bool plan_dirty = true;
     Plan plan;
+    // plan of the static-scratch evaluation (smx_evaluate_static): same groups
+    // and tiles, waves sized to the fixed scratch array, tables kept in it
+    bool splan_dirty = true;
+    Plan splan;
+    uint64_t splan_gen = 0;
+    uint64_t uid = 0;                    // unique per context (owner tag of the scratch tables)
+    int32_t splan_stride = -1;           // history stride the static layout was sized for
 
     // options
     double mu = 0.0, kT = 0.0;
@@ -135,6 +168,7 @@ struct smx_context {
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
+    DevBuf<int32_t> d_fsum;                 // flag counts of a static-scratch evaluation
     DevBuf<int32_t> d_own;
     DevBuf<double> d_tau_parts, d_tau_hist;
     // frozen iteration (derivatives, mu search): step counts and scales of a previous evaluation
@@ -192,6 +226,17 @@ int32_t fail(smx_ctx c, int32_t code, const std::string &msg)
 }
 
 std::string g_create_err;
+
+// Per-device address of the static scratch array, resolved once per device
+// (with that device current) by the first smx_create on it; and which
+// context's plan tables the array holds (uid, plan generation).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_tried[kMaxDevices] = {};
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+uint64_t g_scratch_owner[kMaxDevices][2] = {};
+std::atomic<uint64_t> g_ctx_uid{0};
 
 void drop_graphs(smx_ctx c)
 {
@@ -261,9 +306,8 @@ void xcd_order(const Plan &P, int32_t g0, int32_t g1, std::vector<TileDesc> &til
         for (size_t q = 0; q < lists[x].size(); q++) tiles[q * kXcd + x] = lists[x][q];
 }
 
-int32_t build_plan(smx_ctx c)
+int32_t build_plan(smx_ctx c, Plan &P)
 {
-    Plan &P = c->plan;
     P = Plan();
     const int32_t nblk = c->nblk;
     const int32_t ng = (int32_t)c->grp_ptr.size() - 1;
@@ -364,9 +408,8 @@ int64_t group_bytes(const GroupDesc &d)
 // Split the groups into consecutive waves of at most `budget` bytes each
 // (balanced: about total / ceil(total / budget) per wave), assign the
 // wave-relative slab offsets, and build each wave's launch lists.
-int32_t partition_waves(smx_ctx c, int64_t budget)
+int32_t partition_waves(smx_ctx c, Plan &P, int64_t budget)
 {
-    Plan &P = c->plan;
     const int32_t ng = P.ngroups;
     int64_t total = 0;
     for (int32_t g = 0; g < ng; g++) {
@@ -442,9 +485,8 @@ int32_t partition_waves(smx_ctx c, int64_t budget)
 }
 
 // Host-side consistency check of everything the kernels will index with.
-int32_t check_plan(smx_ctx c)
+int32_t check_plan(smx_ctx c, const Plan &P)
 {
-    const Plan &P = c->plan;
     const int32_t nw = P.nwaves();
     if (nw < 1 || P.wave_g[0] != 0 || P.wave_g[nw] != P.ngroups || (int32_t)P.tile_beg.size() != nw + 1 ||
         (int32_t)P.chunk_beg.size() != nw + 1 || P.tile_beg[nw] != (int64_t)P.tiles.size() ||
@@ -516,9 +558,9 @@ size_t vbytes(const std::vector<T> &v) { return v.size() * sizeof(T); }
 int32_t ensure_plan(smx_ctx c)
 {
     if (!c->plan_dirty) return SMX_OK;
-    int32_t st = build_plan(c);
-    if (st) return st;
     Plan &P = c->plan;
+    int32_t st = build_plan(c, P);
+    if (st) return st;
     // work space: release what depends on the plan, then size the waves to
     // the limit set by smx_set_workspace_limit or to the free device memory
     // left after the plan's tables (with 1 GiB held back, and no more than
@@ -545,17 +587,17 @@ int32_t ensure_plan(smx_ctx c)
         budget = std::min<int64_t>((int64_t)fr - tables - (int64_t)(1ll << 30), (int64_t)(tot / 4 * 3));
         if (budget <= 0) return fail(c, SMX_E_NOMEM, "no device memory left for the submatrix work space");
     }
-    st = partition_waves(c, budget);
+    st = partition_waves(c, P, budget);
     if (st) return st;
     // a caller work space holds the largest wave's arena and pool side by side;
     // the largest arena and the largest pool may come from different waves, so
     // shrink the wave budget until both fit
     while (c->ws_ptr && arena_bytes(P) + pool_bytes(P) > (int64_t)c->ws_bytes) {
         budget = budget * 15 / 16;
-        st = partition_waves(c, budget);
+        st = partition_waves(c, P, budget);
         if (st) return st;
     }
-    st = check_plan(c);
+    st = check_plan(c, P);
     if (st) return st;
     HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
@@ -625,16 +667,25 @@ int32_t need_sync_results(smx_ctx c)
     return SMX_OK;
 }
 
+// Per-group state of a static-scratch evaluation stays in the shared scratch
+// array, which any later static evaluation on the device overwrites.
+int32_t need_group_state(smx_ctx c)
+{
+    if (c->evaluated && c->eval_static)
+        return fail(c, SMX_E_STATE, "per-group results of smx_evaluate_static are not kept (D, N, E and the "
+                                    "convergence status are)");
+    return need_sync_results(c);
+}
+
 // FP64 polish of the reduced-precision modes on the own columns.  With
 // A_0(Z) = X Z (X the bulk result, FP64) and A_j(Z) = X_{k+j} Z =
 // 1.5 A_{j-1}(Z) - 0.5 A_{j-1}(A_{j-1}(A_{j-1}(Z))), the own columns of the
 // p-times polished sign are A_p(E), E the own-column selector (A_0(E) is a
 // gather).  Thin blocks come from a pool of 2p + 1; the residual
 // max|X_{k+p-1}^2 E - E| is taken on the innermost square of the last step.
-int32_t own_polish(smx_ctx c, double *pool, int32_t g0, int32_t wng, const XSource &x, const IterState &it,
-                   int32_t *result)
+int32_t own_polish(smx_ctx c, const Plan &P, const DevView &V, double *pool, int32_t g0, int32_t wng,
+                   const XSource &x, const IterState &it, int32_t *result)
 {
-    const Plan &P = c->plan;
     hipStream_t st = c->stream;
     const int32_t nbuf = 2 * c->n_polish + 1;
     char used[2 * kMaxPolishMixed + 1] = {0};
@@ -643,8 +694,8 @@ int32_t own_polish(smx_ctx c, double *pool, int32_t g0, int32_t wng, const XSour
     struct Poly {
         // own columns of A_j(Z) for Z in buffer zi (zi < 0: the selector E);
         // returns the result's buffer, or -1
-        smx_ctx c;
         const Plan &P;
+        const DevView &V;
         hipStream_t st;
         int32_t g0, wng, slot;
         const XSource &x;
@@ -669,19 +720,19 @@ int32_t own_polish(smx_ctx c, double *pool, int32_t g0, int32_t wng, const XSour
             if (j == 1) {
                 const int a = take();
                 if (a < 0) return -1;
-                herr = zi < 0 ? launch_own_gather(st, g0, wng, P.max_npad, c->d_gd.p, c->d_own.p, x, buf(a))
-                              : launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(zi), nullptr,
+                herr = zi < 0 ? launch_own_gather(st, g0, wng, P.max_npad, V.gd, V.own, x, buf(a))
+                              : launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, V.gd, x, buf(zi), nullptr,
                                                 buf(a));
                 const int b = take();
                 if (b < 0) return -1;
                 if (herr == hipSuccess)
-                    herr = launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(a), nullptr, buf(b));
+                    herr = launch_thin_mul(st, 0, g0, wng, P.max_npad, P.max_own, V.gd, x, buf(a), nullptr, buf(b));
                 if (top && herr == hipSuccess)
-                    herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(b), it, slot);
+                    herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, V.gd, V.own, buf(b), it, slot);
                 const int out = take();
                 if (out < 0) return -1;
                 if (herr == hipSuccess)
-                    herr = launch_thin_mul(st, 1, g0, wng, P.max_npad, P.max_own, c->d_gd.p, x, buf(b), buf(a), buf(out));
+                    herr = launch_thin_mul(st, 1, g0, wng, P.max_npad, P.max_own, V.gd, x, buf(b), buf(a), buf(out));
                 used[a] = used[b] = 0;
                 return out;
             }
@@ -690,16 +741,16 @@ int32_t own_polish(smx_ctx c, double *pool, int32_t g0, int32_t wng, const XSour
             const int bb = apply(j - 1, aa, false);
             if (bb < 0) return -1;
             if (top && herr == hipSuccess)
-                herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, c->d_own.p, buf(bb), it, slot);
+                herr = launch_thin_resid(st, g0, wng, P.max_npad, P.max_own, V.gd, V.own, buf(bb), it, slot);
             const int cc = apply(j - 1, bb, false);
             if (cc < 0) return -1;
             used[bb] = 0;
             if (herr == hipSuccess)
-                herr = launch_thin_combine(st, g0, wng, P.max_npad, P.max_own, c->d_gd.p, buf(aa), buf(cc));
+                herr = launch_thin_combine(st, g0, wng, P.max_npad, P.max_own, V.gd, buf(aa), buf(cc));
             used[aa] = 0;
             return cc;
         }
-    } poly{c, P, st, g0, wng, slot, x, it, used, nbuf, pool, herr};
+    } poly{P, V, st, g0, wng, slot, x, it, used, nbuf, pool, herr};
     const int r = poly.apply(c->n_polish, -1, true);
     if (herr != hipSuccess)
         return fail(c, herr == hipErrorOutOfMemory ? SMX_E_NOMEM : SMX_E_HIP,
@@ -732,9 +783,24 @@ int32_t smx_create(int32_t device, smx_ctx *out)
         return SMX_E_NOMEM;
     }
     c->device = device;
+    c->uid = ++g_ctx_uid;
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_t0);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_t3);
+    if (e == hipSuccess) e = c->d_ne.ensure(2);
+    if (e == hipSuccess) e = c->d_fsum.ensure(2);
+    if (e == hipSuccess && device < kMaxDevices) {
+        // the static scratch array's address on this device (once per device)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_tried[device]) {
+            void *ptr = nullptr;
+            const hipError_t se = hipGetSymbolAddress(&ptr, HIP_SYMBOL(smx_static_scratch));
+            g_scratch_tried[device] = true;
+            g_scratch_err[device] = se;
+            g_scratch_ptr[device] = se == hipSuccess ? ptr : nullptr;
+            if (se != hipSuccess) (void)hipGetLastError();
+        }
+    }
     if (e != hipSuccess) {
         g_create_err = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
         delete c;
@@ -751,6 +817,7 @@ int32_t smx_destroy(smx_ctx c)
     (void)hipStreamSynchronize(c->stream);
     for (auto *b : {&c->d_k, &c->d_d, &c->d_arena, &c->d_pe, &c->d_pn, &c->d_ne, &c->d_check})
         b->release();
+    c->d_fsum.release();
     c->d_plist.release();
     c->d_valoff.release();
     c->d_mirror.release();
@@ -818,6 +885,7 @@ int32_t smx_load_k(smx_ctx c, int32_t nblk, const int32_t *blk_size, const int64
     c->loaded = false;
     c->evaluated = false;
     c->plan_dirty = true;
+    c->splan_dirty = true;
     c->use_kfix = c->use_sfix = false;
     if (nblk <= 0 || !blk_size || !col_ptr || !row_idx || !values)
         return fail(c, SMX_E_INVALID, "nblk must be positive and all arrays non-NULL");
@@ -914,6 +982,7 @@ int32_t smx_set_groups(smx_ctx c, int32_t ngroups, const int32_t *grp_ptr, const
     c->grp_ptr.assign(grp_ptr, grp_ptr + ngroups + 1);
     c->grp_blocks.assign(grp_blocks, grp_blocks + c->nblk);
     c->plan_dirty = true;
+    c->splan_dirty = true;
     c->evaluated = false;
     c->use_kfix = c->use_sfix = false;
     return SMX_OK;
@@ -972,6 +1041,7 @@ int32_t smx_set_tile_order(smx_ctx c, int32_t order)
     if (order != c->tile_order) {
         c->tile_order = order;
         c->plan_dirty = true;
+        c->splan_dirty = true;
         c->evaluated = false;
         c->contrib_ready = false;
     }
@@ -1089,15 +1159,41 @@ int32_t ensure_arena(smx_ctx c, bool pool)
     return SMX_OK;
 }
 
+DevView ctx_view(smx_ctx c)
+{
+    DevView v;
+    v.gd = c->d_gd.p;
+    v.tiles = c->d_tiles.p;
+    v.chunks = c->d_chunks.p;
+    v.rinfo = c->d_rinfo.p;
+    v.bmap = c->d_bmap.p;
+    v.boffs = c->d_boffs.p;
+    v.own = c->d_own.p;
+    v.scat = c->d_scat.p;
+    v.plist = c->d_plist.p;
+    v.scale = c->d_scale.p;
+    v.resid = c->d_resid.p;
+    v.done = c->d_done.p;
+    v.kfinal = c->d_kfinal.p;
+    v.flags = c->d_flags.p;
+    v.ndone = c->d_ndone.p;
+    v.tau_parts = c->d_tau_parts.p;
+    v.tau_hist = c->d_tau_hist.p;
+    v.pe = c->d_pe.p;
+    v.pn = c->d_pn.p;
+    v.ne = c->d_ne.p;
+    return v;
+}
+
 // Enqueue one evaluation on the context's stream.  `arena` holds the largest
 // wave's three slabs (or the words of three iterates from byte 8E), `pool`
 // the own-column blocks of the polish (2 n_polish + 1 of them).  With
 // `timing`, HIP events bracket every product launch (smx_get_launch_profile);
 // `graphs` allows the step graphs of smx_set_graph.  Nothing is allocated
 // here unless `timing` or `graphs` ask for events or graph captures.
-int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, bool timing, bool graphs)
+int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView &V, double *arena, double *pool,
+                     bool timing, bool graphs, bool events, bool poll)
 {
-    const Plan &P = c->plan;
     const int32_t ng = P.ngroups;
     const int32_t fmt = m.fmt, nw = m.nw;
     const bool mixed = m.mixed, tangent = m.tangent;
@@ -1105,21 +1201,21 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, 
     const int32_t nwave = P.nwaves();
     hipStream_t st = c->stream;
     IterState it;
-    it.scale_bits = c->d_scale.p;
-    it.resid_bits = c->d_resid.p;
-    it.done = c->d_done.p;
-    it.kfinal = c->d_kfinal.p;
-    it.flags = c->d_flags.p;
-    it.ndone = c->d_ndone.p;
+    it.scale_bits = V.scale;
+    it.resid_bits = V.resid;
+    it.done = V.done;
+    it.kfinal = V.kfinal;
+    it.flags = V.flags;
+    it.ndone = V.ndone;
     it.kfix = c->use_kfix ? c->d_kfix.p : nullptr;
     it.kact = -1;
-    it.tau_parts = c->d_tau_parts.p;
-    it.tau_hist = c->d_tau_hist.p;
+    it.tau_parts = V.tau_parts;
+    it.tau_hist = V.tau_hist;
     it.resid_stride = stride;
     it.tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
     if (c->use_sfix) it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
     unsigned long long *gather_scale = c->use_sfix ? c->d_scale_scratch.p : it.scale_bits;
-    HIP_TRY(c, hipEventRecord(c->ev_t0, st));
+    if (events) HIP_TRY(c, hipEventRecord(c->ev_t0, st));
     HIP_TRY(c, hipMemsetAsync(gather_scale, 0, sizeof(unsigned long long) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.resid_bits, 0, sizeof(unsigned long long) * (size_t)ng * stride, st));
     HIP_TRY(c, hipMemsetAsync(it.done, 0, sizeof(int32_t) * ng, st));
@@ -1182,42 +1278,42 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, 
     for (wave = 0; wave < nwave; wave++) {
         const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
         const int ntiles = (int)(P.tile_beg[wave + 1] - P.tile_beg[wave]);
-        const TileDesc *tl = c->d_tiles.p + P.tile_beg[wave];
-        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
+        const TileDesc *tl = V.tiles + P.tile_beg[wave];
+        if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
         const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
-        const int2 *chs = c->d_chunks.p + P.chunk_beg[wave];
+        const int2 *chs = V.chunks + P.chunk_beg[wave];
         if (!mixed) {
-            HIP_TRY(c, launch_gather(st, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p, c->d_valoff.p,
+            HIP_TRY(c, launch_gather(st, nch, chs, V.gd, V.rinfo, V.bmap, V.boffs, c->d_valoff.p,
                                      c->d_k.p, c->mu, xb[0], gather_scale));
         } else {
             // bounds first, then X_0 straight into the words (no FP64 copy of A_g)
-            HIP_TRY(c, launch_gather_bound(st, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p,
+            HIP_TRY(c, launch_gather_bound(st, nch, chs, V.gd, V.rinfo, V.bmap, V.boffs,
                                            c->d_valoff.p, c->d_k.p, c->mu, gather_scale));
-            HIP_TRY(c, launch_gather_words(st, fmt, nw, nch, chs, c->d_gd.p, c->d_rinfo.p, c->d_bmap.p, c->d_boffs.p,
+            HIP_TRY(c, launch_gather_words(st, fmt, nw, nch, chs, V.gd, V.rinfo, V.bmap, V.boffs,
                                            c->d_valoff.p, c->d_k.p, c->mu, it.scale_bits, wb[0]));
         }
-        if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, c->d_gd.p, it.scale_bits, tb[0]));
-        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
+        if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, V.gd, it.scale_bits, tb[0]));
+        if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
         // one Newton-Schulz step of the wave on stream s (timed: HIP events around
         // each product launch; not inside a graph capture)
         auto step = [&](hipStream_t s, int32_t k, bool time_it) -> hipError_t {
             auto run = [&](int kind, auto &&launch) -> hipError_t { return time_it ? timed(kind, k, launch) : launch(); };
             hipError_t e;
             if (!mixed) {
-                e = run(0, [&] { return launch_ns_f64(s, 0, ntiles, tl, c->d_gd.p, xb[k & 1], xb[k & 1], wslab, it, k,
+                e = run(0, [&] { return launch_ns_f64(s, 0, ntiles, tl, V.gd, xb[k & 1], xb[k & 1], wslab, it, k,
                                                       c->tol, c->max_iter, 0); });
                 if (e == hipSuccess)
-                    e = run(1, [&] { return launch_ns_f64(s, 1, ntiles, tl, c->d_gd.p, xb[k & 1], wslab, xb[(k + 1) & 1],
+                    e = run(1, [&] { return launch_ns_f64(s, 1, ntiles, tl, V.gd, xb[k & 1], wslab, xb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
                 if (e == hipSuccess && tangent)
-                    e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, c->d_gd.p, tb[k & 1], wslab, tb[(k + 1) & 1],
+                    e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, V.gd, tb[k & 1], wslab, tb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
             } else {
-                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, ntiles, tl, c->d_gd.p, wb[k & 1],
+                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, ntiles, tl, V.gd, wb[k & 1],
                                                         wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
                 if (e == hipSuccess)
-                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, ntiles, tl, c->d_gd.p,
+                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, ntiles, tl, V.gd,
                                                             wb[k & 1], wwp, wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
             }
             return e;
@@ -1251,7 +1347,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, 
                 HIP_TRY(c, step(st, k0, timing));
             }
             launched = std::max(launched, k1 + 1);
-            if (c->host_poll) {
+            if (poll) {
                 HIP_TRY(c, hipMemcpyAsync(c->h_ndone + ch, it.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipEventRecord(c->ev_poll[ch], st));
                 if (ch >= 1) {
@@ -1265,28 +1361,28 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, 
             // read from its words (converted exactly on the fly)
             const XSource xs{nullptr, wb[0], wb[1], it.kfinal, fmt, nw};
             int32_t res = -1;
-            if (int32_t e = own_polish(c, pool, g0, wng, xs, it, &res)) return e;
+            if (int32_t e = own_polish(c, P, V, pool, g0, wng, xs, it, &res)) return e;
             thin_result = pool + (size_t)res * (size_t)P.thin_elems;
             HIP_TRY(c, launch_polish_flags(st, g0, wng, it, c->max_iter + c->n_polish, c->tol));
         }
-        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
+        if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
         const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
-        const int64_t *pl = nwave > 1 ? c->d_plist.p + P.plist_beg[wave] : nullptr;
+        const int64_t *pl = nwave > 1 ? V.plist + P.plist_beg[wave] : nullptr;
         if (mixed)
-            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, thin_result, nullptr, it,
-                                      c->d_k.p, c->d_d.p, c->d_pe.p, c->d_pn.p, 1));
+            HIP_TRY(c, launch_scatter(st, nsc, pl, V.scat, c->d_valoff.p, V.gd, thin_result, nullptr, it,
+                                      c->d_k.p, c->d_d.p, V.pe, V.pn, 1));
         else
-            HIP_TRY(c, launch_scatter(st, nsc, pl, c->d_scat.p, c->d_valoff.p, c->d_gd.p, xb[0], xb[1], it, c->d_k.p,
-                                      c->d_d.p, c->d_pe.p, c->d_pn.p, 0));
+            HIP_TRY(c, launch_scatter(st, nsc, pl, V.scat, c->d_valoff.p, V.gd, xb[0], xb[1], it, c->d_k.p,
+                                      c->d_d.p, V.pe, V.pn, 0));
         if (tangent)
-            HIP_TRY(c, launch_own_trace(st, g0, wng, c->d_gd.p, c->d_own.p, tb[0], tb[1], it.kfinal, c->d_dnp.p));
-        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
+            HIP_TRY(c, launch_own_trace(st, g0, wng, V.gd, V.own, tb[0], tb[1], it.kfinal, c->d_dnp.p));
+        if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
     }
-    HIP_TRY(c, launch_reduce(st, c->nnzb, c->d_pe.p, c->d_pn.p, c->d_ne.p));
+    HIP_TRY(c, launch_reduce(st, c->nnzb, V.pe, V.pn, V.ne));
     if (tangent) HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dn.p));
     c->have_tangent = tangent;
     c->last_sfix = c->use_sfix;
-    HIP_TRY(c, hipEventRecord(c->ev_t3, st));
+    if (events) HIP_TRY(c, hipEventRecord(c->ev_t3, st));
     c->steps_launched = launched;
     c->last_precision = c->precision;
     c->last_stride = stride;
@@ -1297,6 +1393,99 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, double *arena, double *pool, 
     c->last_mu = c->mu;
     c->evaluated = true;
     return SMX_OK;
+}
+
+
+// ---- static scratch layout (smx_evaluate_static) ---------------------------
+// The whole work memory of a static evaluation lies in the fixed scratch
+// array, in this order: the plan's tables (group descriptors, tiles, gather
+// chunks, row tables, block maps, block offsets, scatter descriptors, own-column
+// lists, per-wave scatter lists), the per-evaluation state (scales, residual
+// and trace histories, flags, counters, energy/trace partials), then one
+// wave's arena and polish pool.  Only K, D and the two result scalars live in
+// context memory allocated by earlier calls.
+struct StaticLayout {
+    int64_t gd = 0, tiles = 0, chunks = 0, rinfo = 0, bmap = 0, boffs = 0, scat = 0, own = 0, plist = 0;
+    int64_t scale = 0, resid = 0, done = 0, kfinal = 0, flags = 0, ndone = 0, tau_parts = 0, tau_hist = 0;
+    int64_t pe = 0, pn = 0, arena = 0, pool = 0, end = 0;
+};
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+StaticLayout static_layout(smx_ctx c, const Plan &P, int32_t stride)
+{
+    StaticLayout L;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o += align256(std::max<int64_t>(bytes, 1));
+        return at;
+    };
+    const int64_t ng = std::max(P.ngroups, 1);
+    const int64_t tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
+    const int64_t nb = std::max<int64_t>(c->nnzb, 1);
+    L.gd = take(vbytes(P.gd));
+    L.tiles = take(vbytes(P.tiles));
+    L.chunks = take(vbytes(P.chunks));
+    L.rinfo = take(vbytes(P.rinfo));
+    L.bmap = take(vbytes(P.bmap));
+    L.boffs = take(vbytes(P.boffs));
+    L.scat = take(vbytes(P.scat));
+    L.own = take(vbytes(P.own_list));
+    L.plist = take(vbytes(P.plist));
+    L.scale = take(8 * ng);
+    L.resid = take(8 * ng * stride);
+    L.done = take(4 * ng);
+    L.kfinal = take(4 * ng);
+    L.flags = take(4 * ng);
+    L.ndone = take(4);
+    L.tau_parts = take(8 * ng * tau_nt);
+    L.tau_hist = take(8 * ng * stride);
+    L.pe = take(8 * nb);
+    L.pn = take(8 * nb);
+    L.arena = take(arena_bytes(P));
+    L.pool = take(pool_bytes(P));
+    L.end = o;
+    return L;
+}
+
+// Host-side plan of the static evaluation: waves sized so that tables, state,
+// arena and pool fit the scratch array together.  Allocates host memory only.
+int32_t static_plan(smx_ctx c, int32_t stride)
+{
+    if (!c->splan_dirty && c->splan_stride == stride) return SMX_OK;
+    // earlier static evaluations may still be copying the old tables from the host
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Plan &P = c->splan;
+    c->splan_dirty = true;
+    if (int32_t st = build_plan(c, P)) return st;
+    const int64_t cap = (int64_t)SMX_STATIC_SCRATCH_BYTES;
+    // first guess: everything but the arena and pool, with the tiles and
+    // scatter lists at their one-wave sizes
+    int64_t budget = cap - static_layout(c, P, stride).end - 8 * c->nnzb - 64 * 1024;
+    for (;;) {
+        if (budget <= 0)
+            return fail(c, SMX_E_NOMEM, "the plan tables and iteration state need more than the " +
+                                            std::to_string(cap >> 20) + " MiB static scratch array");
+        if (int32_t st = partition_waves(c, P, budget)) {
+            c->err = "static scratch array (" + std::to_string(cap >> 20) + " MiB): " + c->err;
+            return st;
+        }
+        if (static_layout(c, P, stride).end <= cap) break;
+        budget = budget * 15 / 16;
+    }
+    if (int32_t st = check_plan(c, P)) return st;
+    c->splan_gen++;
+    c->splan_stride = stride;
+    c->splan_dirty = false;
+    return SMX_OK;
+}
+
+template <typename T>
+hipError_t upload_to(char *base, int64_t off, const std::vector<T> &v, hipStream_t st)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(base + off, v.data(), vbytes(v), hipMemcpyHostToDevice, st);
 }
 
 }  // namespace
@@ -1313,19 +1502,101 @@ int32_t smx_evaluate(smx_ctx c)
     c->eval_static = false;
     if (int32_t st = eval_prepare(c, m)) return st;
     if (int32_t st = ensure_arena(c, m.mixed)) return st;
-    return eval_enqueue(c, m, arena_base(c), pool_base(c), true, true);
+    return eval_enqueue(c, m, c->plan, ctx_view(c), arena_base(c), pool_base(c), true, true, true, c->host_poll != 0);
+}
+
+
+int32_t smx_evaluate_static(smx_ctx c)
+{
+    if (!c) return SMX_E_INVALID;
+    EvalMode m;
+    if (int32_t st = eval_mode(c, m)) return st;
+    if (c->use_kfix || c->use_sfix)
+        return fail(c, SMX_E_UNSUPPORTED, "frozen evaluations (derivatives, mu search) do not run in the static scratch");
+    if (int32_t st = set_device(c)) return st;
+    void *sp = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (c->device < kMaxDevices && g_scratch_tried[c->device]) sp = g_scratch_ptr[c->device];
+        if (!sp)
+            return fail(c, SMX_E_HIP, std::string("the static scratch array has no address on this device: ") +
+                                          hipGetErrorString(c->device < kMaxDevices ? g_scratch_err[c->device]
+                                                                                    : hipErrorInvalidDevice));
+    }
+    c->evaluated = false;
+    c->eval_static = false;
+    if (int32_t st = static_plan(c, m.stride)) return st;
+    const Plan &P = c->splan;
+    const StaticLayout L = static_layout(c, P, m.stride);
+    char *base = static_cast<char *>(sp);
+    hipStream_t st = c->stream;
+    {
+        // the plan's tables, unless this context's current tables are already there
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        uint64_t *own = g_scratch_owner[c->device];
+        if (own[0] != c->uid || own[1] != c->splan_gen) {
+            HIP_TRY(c, upload_to(base, L.gd, P.gd, st));
+            HIP_TRY(c, upload_to(base, L.tiles, P.tiles, st));
+            HIP_TRY(c, upload_to(base, L.chunks, P.chunks, st));
+            HIP_TRY(c, upload_to(base, L.rinfo, P.rinfo, st));
+            HIP_TRY(c, upload_to(base, L.bmap, P.bmap, st));
+            HIP_TRY(c, upload_to(base, L.boffs, P.boffs, st));
+            HIP_TRY(c, upload_to(base, L.scat, P.scat, st));
+            HIP_TRY(c, upload_to(base, L.own, P.own_list, st));
+            HIP_TRY(c, upload_to(base, L.plist, P.plist, st));
+            own[0] = c->uid;
+            own[1] = c->splan_gen;
+        }
+    }
+    DevView V;
+    V.gd = reinterpret_cast<const GroupDesc *>(base + L.gd);
+    V.tiles = reinterpret_cast<const TileDesc *>(base + L.tiles);
+    V.chunks = reinterpret_cast<const int2 *>(base + L.chunks);
+    V.rinfo = reinterpret_cast<const RowInfo *>(base + L.rinfo);
+    V.bmap = reinterpret_cast<const int32_t *>(base + L.bmap);
+    V.boffs = reinterpret_cast<const int32_t *>(base + L.boffs);
+    V.scat = reinterpret_cast<const ScatterDesc *>(base + L.scat);
+    V.own = reinterpret_cast<const int32_t *>(base + L.own);
+    V.plist = reinterpret_cast<const int64_t *>(base + L.plist);
+    V.scale = reinterpret_cast<unsigned long long *>(base + L.scale);
+    V.resid = reinterpret_cast<unsigned long long *>(base + L.resid);
+    V.done = reinterpret_cast<int32_t *>(base + L.done);
+    V.kfinal = reinterpret_cast<int32_t *>(base + L.kfinal);
+    V.flags = reinterpret_cast<int32_t *>(base + L.flags);
+    V.ndone = reinterpret_cast<int32_t *>(base + L.ndone);
+    V.tau_parts = reinterpret_cast<double *>(base + L.tau_parts);
+    V.tau_hist = reinterpret_cast<double *>(base + L.tau_hist);
+    V.pe = reinterpret_cast<double *>(base + L.pe);
+    V.pn = reinterpret_cast<double *>(base + L.pn);
+    V.ne = c->d_ne.p;
+    // state that must start at zero is cleared inside (scales, histories,
+    // flags, step counts, the finished-group counter); every other state
+    // array and the arena are written before they are read
+    if (int32_t e = eval_enqueue(c, m, P, V, reinterpret_cast<double *>(base + L.arena),
+                                 reinterpret_cast<double *>(base + L.pool), false, false, false, false))
+        return e;
+    HIP_TRY(c, launch_count_flags(st, P.ngroups, V.flags, c->d_fsum.p));
+    c->eval_static = true;
+    return SMX_OK;
 }
 
 int32_t smx_wait(smx_ctx c)
 {
     if (!c) return SMX_E_INVALID;
     if (int32_t st = need_sync_results(c)) return st;
-    std::vector<int32_t> fl((size_t)c->plan.ngroups);
-    HIP_TRY(c, hipMemcpy(fl.data(), c->d_flags.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     int nc = 0, nf = 0;
-    for (int32_t f : fl) {
-        nc += (f & 1) != 0;
-        nf += (f & 2) != 0;
+    if (c->eval_static) {
+        int32_t cnt[2] = {0, 0};
+        HIP_TRY(c, hipMemcpy(cnt, c->d_fsum.p, sizeof cnt, hipMemcpyDeviceToHost));
+        nc = cnt[0];
+        nf = cnt[1];
+    } else {
+        std::vector<int32_t> fl((size_t)c->plan.ngroups);
+        HIP_TRY(c, hipMemcpy(fl.data(), c->d_flags.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int32_t f : fl) {
+            nc += (f & 1) != 0;
+            nf += (f & 2) != 0;
+        }
     }
     if (nf) return fail(c, SMX_E_NONFINITE, std::to_string(nf) + " group(s) produced non-finite iterates");
     if (nc)
@@ -1377,7 +1648,7 @@ int32_t smx_energy(smx_ctx c, double *e_out)
 int32_t smx_get_group_info(smx_ctx c, int32_t *n_g, int32_t *iters, double *scale, double *resid)
 {
     if (!c) return SMX_E_INVALID;
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     const int32_t ng = c->plan.ngroups;
     std::vector<int32_t> kf((size_t)ng);
     std::vector<unsigned long long> sb((size_t)ng), rb((size_t)ng * c->last_stride);
@@ -1404,7 +1675,7 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
 {
     if (!c) return SMX_E_INVALID;
     if (!out) return fail(c, SMX_E_INVALID, "out is NULL");
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     const int32_t ng = c->plan.ngroups;
     std::vector<int32_t> n((size_t)ng), it((size_t)ng), fl((size_t)ng);
     std::vector<double> sc((size_t)ng), rs((size_t)ng);
@@ -1483,7 +1754,7 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
                                int32_t *count)
 {
     if (!c) return SMX_E_INVALID;
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     const int32_t nl = (int32_t)c->launch_step.size();
     if (count) *count = nl;
     std::vector<int32_t> kf((size_t)c->plan.ngroups);
@@ -1588,7 +1859,7 @@ int32_t smx_set_frozen(smx_ctx c, int32_t on)
         c->use_kfix = c->use_sfix = false;
         return SMX_OK;
     }
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     const int32_t ng = c->plan.ngroups;
     std::vector<int32_t> kf((size_t)ng);
     HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1877,7 +2148,7 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     if (!c) return SMX_E_INVALID;
     if (!dK_out && !dmu_out) return fail(c, SMX_E_INVALID, "nothing to compute (dK_out and dmu_out are NULL)");
     if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     if (int32_t st = set_device(c)) return st;
     if (c->plan.nwaves() != 1)
         return fail(c, SMX_E_UNSUPPORTED, "the adjoint needs every submatrix resident at once (one wave); "
@@ -2062,7 +2333,7 @@ int32_t smx_get_history(smx_ctx c, int32_t cap, double *resid, double *tau, int3
 {
     if (!c) return SMX_E_INVALID;
     if (cap < 0) return fail(c, SMX_E_INVALID, "cap must be >= 0");
-    if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = need_group_state(c)) return st;
     const int32_t ng = c->plan.ngroups;
     const int32_t stride = c->last_stride;
     std::vector<int32_t> kf((size_t)ng);

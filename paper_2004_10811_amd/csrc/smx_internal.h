@@ -212,6 +212,8 @@ hipError_t launch_polish_flags(hipStream_t st, int g0, int ngroups, const IterSt
 
 hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const double *part_n,
                          double *out2);
+// out2[0] / out2[1] = number of groups with flag bit 0 / bit 1 set.
+hipError_t launch_count_flags(hipStream_t st, int ngroups, const int32_t *flags, int32_t *out2);
 
 // Xd_0 = -a I on the true n_g x n_g block (a = 1/s_g), zero elsewhere: the mu tangent
 // of X_0 = (K_sub - mu I) / s_g with s_g frozen.

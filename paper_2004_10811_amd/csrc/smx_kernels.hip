@@ -345,6 +345,38 @@ void polish_flags_kernel(int ngroups, IterState it, int slot, double tol, int g0
     it.flags[g] = fl;
 }
 
+// out2[0] = groups with flag bit 0 (not converged), out2[1] = groups with bit 1
+// (non-finite), over flags[0 .. ngroups-1]; one workgroup, no atomics.
+__global__ __launch_bounds__(1024)
+void count_flags_kernel(int ngroups, const int32_t *__restrict__ flags, int32_t *__restrict__ out2)
+{
+    __shared__ int s0[16], s1[16];
+    const int t = threadIdx.x;
+    int c0 = 0, c1 = 0;
+    for (int g = t; g < ngroups; g += 1024) {
+        c0 += flags[g] & 1;
+        c1 += (flags[g] >> 1) & 1;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        c0 += __shfl_xor(c0, o, 64);
+        c1 += __shfl_xor(c1, o, 64);
+    }
+    if ((t & 63) == 0) {
+        s0[t >> 6] = c0;
+        s1[t >> 6] = c1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int a0 = 0, a1 = 0;
+        for (int w = 0; w < 16; w++) {
+            a0 += s0[w];
+            a1 += s1[w];
+        }
+        out2[0] = a0;
+        out2[1] = a1;
+    }
+}
+
 // Fixed-order sum of the per-block partials (one workgroup): deterministic.
 __global__ __launch_bounds__(1024)
 void reduce_kernel(int64_t n, const double *__restrict__ pe, const double *__restrict__ pn,
@@ -588,6 +620,12 @@ hipError_t launch_polish_flags(hipStream_t st, int g0, int ngroups, const IterSt
     if (ngroups <= 0) return hipSuccess;
     hipLaunchKernelGGL(polish_flags_kernel, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0, st, ngroups, it,
                        slot, tol, g0);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_flags(hipStream_t st, int ngroups, const int32_t *flags, int32_t *out2)
+{
+    hipLaunchKernelGGL(count_flags_kernel, dim3(1), dim3(1024), 0, st, ngroups, flags, out2);
     return hipGetLastError();
 }
 
