@@ -97,6 +97,15 @@ def full_sign_report(system, d_values, n_gpu, e_gpu):
             "method": "numpy.linalg.eigh of the dense K - mu I", "seconds": time.perf_counter() - t0}
 
 
+def kernel_name(kind, precision):
+    """Product kernel of a launch kind (smx_get_launch_profile)."""
+    if kind in (0, 1, 4, 5, 6):
+        return "ns_f64_kernel"
+    if kind in (7, 8):
+        return "ns_words256_kernel"
+    return "ns_f32_kernel" if precision == "fp32" else "ns_words_kernel"
+
+
 def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
     """Warm up, then time exactly `steps` evaluations; returns timings and stats.
 
@@ -121,7 +130,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
         step()
         ms, fl, kd = ctx.launch_profile()
         for m, f, k in zip(ms, fl, kd):
-            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else ("ns_f32_kernel" if precision == "fp32" else "ns_words_kernel")
+            key = kernel_name(k, precision)
             e = prof.setdefault(key, [0.0, 0.0, 0])
             e[0] += m
             e[1] += f
@@ -139,7 +148,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
         step()
         ms, fl, kd = ctx.launch_profile()
         for m, f, k in zip(ms, fl, kd):
-            key = "ns_f64_kernel" if k in (0, 1, 4, 5) else ("ns_f32_kernel" if precision == "fp32" else "ns_words_kernel")
+            key = kernel_name(k, precision)
             e = prof.setdefault(key, [0.0, 0.0, 0])
             e[0] += m
             e[1] += f
@@ -153,7 +162,7 @@ DTYPES = {"fp64": "f64", "fp16x2": "f16x2 words, f32 accumulation; f64 polish",
           "bf16": "bf16 words, f32 accumulation; f64 polish",
           "fp32": "f32, f32 accumulation; f64 polish"}
 PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf16", 2516.6),
-                  "ns_f32_kernel": ("fp32", 157.3)}
+                  "ns_words256_kernel": ("fp16/bf16", 2516.6), "ns_f32_kernel": ("fp32", 157.3)}
 
 # HBM bytes per launch of the dominant kernel on water1024, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the
@@ -221,6 +230,12 @@ def main():
                     help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
     ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1],
                     help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch)")
+    ap.add_argument("--tile-shape", type=int, default=None, metavar="NPAD",
+                    help="size bucket boundary of the word products: groups with n_pad >= NPAD on 256 x 256 "
+                         "tiles (0: 128 x 128 only; default: the library's)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the timed precision in the given launch configuration instead of the autotuner's "
+                         "choice (launch order x step graphs x size bucket boundary)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the Newton-Schulz steps from HIP graphs of this many steps (0: direct launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -255,18 +270,37 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = smx.Context(0, stream=stream.cuda_stream).load(system)
     smx.smx_set_kernel_variant(ctx.handle, args.kernel_variant)
+    if args.tile_shape is not None:
+        smx.smx_set_tile_shape(ctx.handle, args.tile_shape)
     d64 = torch.empty(ctx.nvalues, dtype=torch.float64, device="cuda")
     d_mix = torch.empty_like(d64)
 
+    graph_steps = args.graph_steps
+    tuned = None
+
+    def autotune():
+        # the autotuner times whole evaluations of every candidate launch
+        # configuration (launch order x step graphs x size bucket boundary) for
+        # the timed precision and applies the fastest
+        ctx.configure(precision=args.precision, graph_steps=0)
+        g, o, tms = smx.smx_autotune(ctx.handle, reps=2, use_cache=True)
+        cfg = {"best_ms": tms, **smx.smx_get_launch_config(ctx.handle)}
+        progress(f"autotune {args.precision}: {cfg}")
+        return g, cfg
+
     # FP64 path first: the reference D and the iteration counts k_g of the
     # effective-TFLOP/s numerator (the same numerator for every precision)
+    if args.precision == "fp64" and not args.no_autotune:
+        graph_steps, tuned = autotune()
     r64 = run_path(smx, ctx, "fp64", args.steps if args.precision == "fp64" else 2, 1, d64,
-                   args.graph_steps if args.precision == "fp64" else 0)
+                   graph_steps if args.precision == "fp64" else 0)
     algo = r64["stats"]["algo_flops"]
     run = r64
     d_out = d64
     if args.precision != "fp64":
-        run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, args.graph_steps)
+        if not args.no_autotune:
+            graph_steps, tuned = autotune()
+        run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, graph_steps)
         d_out = d_mix
     backward = None
     if args.backward:
@@ -286,6 +320,7 @@ def main():
                     "ms_per_backward": bms, "backward_over_forward": bms / run["ms_per_step"],
                     "max_abs_dK": float(dk.abs().max().item())}
         progress(f"backward: {bms:.1f} ms per call")
+    launch_config = smx.smx_get_launch_config(ctx.handle)
     ctx.close()
 
     stats = run["stats"]
@@ -339,8 +374,11 @@ def main():
             "fp64_ns_steps_mean": round(r64["stats"]["iters_mean"], 2),
             "tol": 1e-12,
             "waves": int(stats["nwaves"]),
-            "graph_steps": args.graph_steps,
+            "graph_steps": graph_steps,
+            "tile_order": launch_config["tile_order"],
             "kernel_variant": args.kernel_variant,
+            "big_tile_min_npad": launch_config["big_min_npad"],
+            "autotuned": tuned is not None,
         },
         "device_ms_per_D_median": float(np.median(run["dev_ms"])),
         "phase_ms": {"gather": stats["time_gather_ms"], "iterate": stats["time_iterate_ms"],

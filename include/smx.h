@@ -199,15 +199,37 @@ int32_t smx_set_tile_order(smx_ctx ctx, int32_t order);
 int32_t smx_set_kernel_variant(smx_ctx ctx, int32_t variant);
 
 /*
+ * Size buckets of the 2-word FP16 and 1-word BF16 products (the paper
+ * balances submatrices of uneven size over workers, Sec. IV-E; here the
+ * uneven submatrices of one launch are split by size): groups whose padded
+ * dimension n_pad is at least big_min_npad run on 256 x 256 output tiles
+ * (one 512-lane workgroup per CU, operands double-buffered in LDS), the
+ * others on 128 x 128 tiles; each bucket is one launch per product.
+ * big_min_npad = 0 puts every group on 128 x 128 tiles.  Results are bitwise
+ * the same for every choice.  Takes effect at the next plan build; other
+ * precision modes always use 128 x 128 tiles.
+ */
+int32_t smx_set_tile_shape(smx_ctx ctx, int32_t big_min_npad);
+
+/* The launch configuration in effect (outputs nullable): steps per graph
+ * (smx_set_graph), tile launch order (smx_set_tile_order), size bucket
+ * boundary (smx_set_tile_shape) and operand stream (smx_set_kernel_variant). */
+int32_t smx_get_launch_config(smx_ctx ctx, int32_t *graph_steps, int32_t *tile_order,
+                              int32_t *big_min_npad, int32_t *kernel_variant);
+
+/*
  * Autotuner.  Times whole evaluations of the loaded problem (current
  * precision, groups and mu) for every candidate launch configuration, the
  * tile launch order (smx_set_tile_order) x steps per graph (0, 2, 8;
- * smx_set_graph): one untimed run per candidate, then the minimum device time
- * of `reps` runs.  It applies the fastest and returns it (outputs nullable).
- * If the environment variable SMX_TUNE_CACHE names a file, the choice is
- * appended there as "key graph_steps tile_order ms", keyed by device
- * architecture, precision and the batch shape.  With use_cache != 0 a matching
- * record is applied without timing.  Invalidates results.
+ * smx_set_graph) x, in the 2-word FP16 and 1-word BF16 modes, the size bucket
+ * boundary of the 256 x 256 tiles (0, 384, 640, 896; smx_set_tile_shape): one
+ * untimed run per candidate, then the minimum device time of `reps` runs.  It
+ * applies the fastest and returns it (outputs nullable; the bucket boundary
+ * through smx_get_launch_config).  If the environment variable SMX_TUNE_CACHE
+ * names a file, the choice is appended there as "key graph_steps tile_order
+ * big_min_npad ms", keyed by device architecture, precision and the batch
+ * shape.  With use_cache != 0 a matching record is applied without timing.
+ * Invalidates results.
  */
 int32_t smx_autotune(smx_ctx ctx, int32_t reps, int32_t use_cache, int32_t *graph_steps_out,
                      int32_t *tile_order_out, double *best_ms_out);
@@ -414,8 +436,9 @@ int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
  * evaluation, in launch order: device time in ms measured with HIP events on
  * the context's stream, the algorithmic flops of the launch (2 n_g^3 for
  * every group the launch works on, i.e. one dense n_g x n_g product), and
- * its kind: 0/1 FP64 square/update, 2/3 reduced-precision square/update,
- * 4/5 FP64 polish square/update.  Writes min(cap, count) entries to the host
+ * its kind: 0/1 FP64 square/update, 2/3 reduced-precision square/update on
+ * 128 x 128 tiles, 4/5 FP64 polish square/update, 6 mu tangent, 7/8
+ * reduced-precision square/update on 256 x 256 tiles.  Writes min(cap, count) entries to the host
  * arrays (any may be NULL) and the launch count to *count.  Synchronises.
  */
 int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,

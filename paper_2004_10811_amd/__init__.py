@@ -68,6 +68,8 @@ SIGNATURES = {
     "smx_set_graph": (_i32, [_vp, _i32]),
     "smx_set_tile_order": (_i32, [_vp, _i32]),
     "smx_set_kernel_variant": (_i32, [_vp, _i32]),
+    "smx_set_tile_shape": (_i32, [_vp, _i32]),
+    "smx_get_launch_config": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
     "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
     "smx_evaluate_static": (_i32, [_vp]),
@@ -230,6 +232,17 @@ def smx_set_tile_order(ctx, order=0):
 
 def smx_set_kernel_variant(ctx, variant=0):
     return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
+def smx_set_tile_shape(ctx, big_min_npad=0):
+    return _check(ctx, load_library().smx_set_tile_shape(ctx, int(big_min_npad)))
+
+
+def smx_get_launch_config(ctx) -> dict:
+    g, o, b, v = _i32(), _i32(), _i32(), _i32()
+    _check(ctx, load_library().smx_get_launch_config(ctx, ctypes.byref(g), ctypes.byref(o), ctypes.byref(b),
+                                                     ctypes.byref(v)))
+    return dict(graph_steps=g.value, tile_order=o.value, big_min_npad=b.value, kernel_variant=v.value)
 
 
 def smx_autotune(ctx, reps=3, use_cache=True):
@@ -423,8 +436,10 @@ class Context:
         return self
 
     def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
-                  mu=None, kT=None, workspace_limit=None, graph_steps=None):
+                  mu=None, kT=None, workspace_limit=None, graph_steps=None, tile_shape=None):
         smx_set_precision(self.handle, precision)
+        if tile_shape is not None:
+            smx_set_tile_shape(self.handle, tile_shape)
         if graph_steps is not None:
             smx_set_graph(self.handle, graph_steps)
         if workspace_limit is not None:

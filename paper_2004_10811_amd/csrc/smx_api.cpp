@@ -77,6 +77,13 @@ struct Plan {
     std::vector<int32_t> wave_g;
     std::vector<int32_t> wave_of;      // wave of every group
     std::vector<int64_t> tile_beg;     // wave w's lower tiles: tiles[tile_beg[w] .. tile_beg[w+1])
+    // size buckets of the one- and two-word products: groups with n_pad >= the
+    // context's big_min_npad take 256 x 256 tiles (tiles_b), the others 128 x 128
+    // tiles (tiles_s); per wave like tile_beg
+    std::vector<char> big;
+    std::vector<TileDesc> tiles_s, tiles_b;
+    std::vector<int64_t> tiles_s_beg, tiles_b_beg;
+    std::vector<double> wtiles2;       // live 16 x 16 blocks of one product on 256 x 256 tiles, per group
     std::vector<int64_t> chunk_beg;    // wave w's gather chunks (chunks are in group order)
     std::vector<int64_t> plist;        // stored blocks of the own columns of each wave (more than one wave)
     std::vector<int64_t> plist_beg;
@@ -91,7 +98,7 @@ struct Plan {
 // context's own buffers, or places in the static scratch array.
 struct DevView {
     const GroupDesc *gd = nullptr;
-    const TileDesc *tiles = nullptr;
+    const TileDesc *tiles = nullptr, *tiles_s = nullptr, *tiles_b = nullptr;
     const int2 *chunks = nullptr;
     const RowInfo *rinfo = nullptr;
     const int32_t *bmap = nullptr, *boffs = nullptr, *own = nullptr;
@@ -99,7 +106,7 @@ struct DevView {
     const int64_t *plist = nullptr;
     unsigned long long *scale = nullptr, *resid = nullptr;
     int32_t *done = nullptr, *kfinal = nullptr, *flags = nullptr, *ndone = nullptr;
-    double *tau_parts = nullptr, *tau_hist = nullptr, *pe = nullptr, *pn = nullptr, *ne = nullptr;
+    double *tdiag = nullptr, *tau_hist = nullptr, *pe = nullptr, *pn = nullptr, *ne = nullptr;
 };
 
 // Arena of one wave: three FP64 slabs X_a | X_b | W (24 bytes per element);
@@ -111,6 +118,10 @@ constexpr int64_t kArenaBytesPerElem = 26;
 // Largest n_polish of the reduced-precision modes (the own-column polish
 // evaluates a degree-3^n_polish polynomial by 3^n_polish - 1 thin products).
 constexpr int32_t kMaxPolishMixed = 4;
+
+// Default size bucket boundary of the one- and two-word products: groups whose
+// padded dimension reaches it take 256 x 256 tiles (0: 128 x 128 tiles only).
+constexpr int32_t kDefaultBigMinNpad = 0;
 
 }  // namespace
 
@@ -150,7 +161,7 @@ struct smx_context {
     DevBuf<int32_t> d_brow, d_bcol;
     // device: plan
     DevBuf<GroupDesc> d_gd;
-    DevBuf<TileDesc> d_tiles;
+    DevBuf<TileDesc> d_tiles, d_tiles_s, d_tiles_b;
     DevBuf<int2> d_chunks;
     DevBuf<RowInfo> d_rinfo;
     DevBuf<int32_t> d_bmap, d_boffs;
@@ -165,12 +176,13 @@ struct smx_context {
                                             // 0: enqueue all max_iter steps, no host synchronisation
     int32_t tile_order = 0;                 // 0: XCD-aware launch order, 1: group by group
     int32_t kernel_variant = 0;             // operand stream of the word products (smx_set_kernel_variant)
+    int32_t big_min_npad = kDefaultBigMinNpad;   // 256 x 256 tiles from this n_pad on (smx_set_tile_shape)
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
     DevBuf<double> d_pe, d_pn, d_ne, d_check;
     DevBuf<int32_t> d_fsum;                 // flag counts of a static-scratch evaluation
     DevBuf<int32_t> d_own;
-    DevBuf<double> d_tau_parts, d_tau_hist;
+    DevBuf<double> d_tdiag, d_tau_hist;
     // frozen iteration (derivatives, mu search): step counts and scales of a previous evaluation
     DevBuf<int32_t> d_kfix;
     DevBuf<unsigned long long> d_sfix, d_scale_scratch;
@@ -190,8 +202,10 @@ struct smx_context {
     std::vector<hipEvent_t> ev_poll;
     std::vector<hipEvent_t> ev_launch;   // two per product launch (before, after)
     std::vector<int32_t> launch_step;    // step k of each product launch
-    std::vector<int32_t> launch_kind;    // 0/1 FP64 square/update, 2/3 word square/update, 4/5 polish
+    std::vector<int32_t> launch_kind;    // 0/1 FP64 square/update, 2/3 word square/update (128 x 128
+                                         // tiles), 4/5 polish, 6 tangent, 7/8 word square/update (256 x 256)
     std::vector<int32_t> launch_wave;    // wave of each product launch
+    std::vector<int32_t> launch_subset;  // groups of the launch: 0 all, 1 the 128-tile bucket, 2 the 256-tile bucket
     std::vector<hipEvent_t> ev_wave;     // four per wave: start, iterate, scatter, end
     hipEvent_t ev_t0 = nullptr, ev_t3 = nullptr;
 
@@ -391,6 +405,19 @@ int32_t build_plan(smx_ctx c, Plan &P)
                         wt += 1;
                     }
         P.wtiles.push_back(wt);
+        // the same on 256 x 256 tiles: live 16 x 16 blocks (inside the matrix,
+        // not entirely above the diagonal of a diagonal tile)
+        const int32_t nt2 = (d.npad + kTile2 - 1) / kTile2;
+        double wt2 = 0;
+        for (int32_t ti = 0; ti < nt2; ti++)
+            for (int32_t tj = 0; tj <= ti; tj++)
+                for (int32_t r0 = 0; r0 < kTile2; r0 += 16)
+                    for (int32_t c0 = 0; c0 < kTile2; c0 += 16) {
+                        if (ti * kTile2 + r0 >= d.npad || tj * kTile2 + c0 >= d.npad) continue;
+                        if (ti == tj && r0 + 15 < c0) continue;
+                        wt2 += 1;
+                    }
+        P.wtiles2.push_back(wt2);
         P.gd.push_back(d);
     }
     for (int64_t p = 0; p < c->nnzb; p++)
@@ -440,13 +467,19 @@ int32_t partition_waves(smx_ctx c, Plan &P, int64_t budget)
     P.tiles.clear();
     P.tiles_full.clear();
     P.tile_beg.assign(1, 0);
+    P.tiles_s.clear();
+    P.tiles_b.clear();
+    P.tiles_s_beg.assign(1, 0);
+    P.tiles_b_beg.assign(1, 0);
+    P.big.assign((size_t)ng, 0);
+    for (int32_t g = 0; g < ng; g++) P.big[g] = c->big_min_npad > 0 && P.gd[g].npad >= c->big_min_npad;
     P.chunk_beg.assign(1, 0);
     P.plist.clear();
     P.plist_beg.assign(1, 0);
     size_t ch = 0;
     for (int32_t w = 0; w < nw; w++) {
         int64_t e = 0, t = 0;
-        std::vector<TileDesc> tl;
+        std::vector<TileDesc> tl, ts, tb;
         for (int32_t g = P.wave_g[w]; g < P.wave_g[w + 1]; g++) {
             GroupDesc &d = P.gd[g];
             d.off = e;
@@ -456,12 +489,28 @@ int32_t partition_waves(smx_ctx c, Plan &P, int64_t budget)
             const int32_t nt = (d.npad + kTile - 1) / kTile;
             for (int32_t ti = 0; ti < nt; ti++)
                 for (int32_t tj = 0; tj <= ti; tj++) tl.push_back(TileDesc{g, (ti << 16) | tj});
+            if (P.big[g]) {
+                const int32_t nt2 = (d.npad + kTile2 - 1) / kTile2;
+                for (int32_t ti = 0; ti < nt2; ti++)
+                    for (int32_t tj = 0; tj <= ti; tj++) tb.push_back(TileDesc{g, (ti << 16) | tj});
+            } else {
+                for (int32_t ti = 0; ti < nt; ti++)
+                    for (int32_t tj = 0; tj <= ti; tj++) ts.push_back(TileDesc{g, (ti << 16) | tj});
+            }
         }
         P.work_elems = std::max(P.work_elems, e);
         P.thin_elems = std::max(P.thin_elems, t);
-        if (c->tile_order == 0) xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
+        if (c->tile_order == 0) {
+            xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
+            if (!ts.empty()) xcd_order(P, P.wave_g[w], P.wave_g[w + 1], ts);
+            if (!tb.empty()) xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tb);
+        }
         P.tiles.insert(P.tiles.end(), tl.begin(), tl.end());
         P.tile_beg.push_back((int64_t)P.tiles.size());
+        P.tiles_s.insert(P.tiles_s.end(), ts.begin(), ts.end());
+        P.tiles_s_beg.push_back((int64_t)P.tiles_s.size());
+        P.tiles_b.insert(P.tiles_b.end(), tb.begin(), tb.end());
+        P.tiles_b_beg.push_back((int64_t)P.tiles_b.size());
         while (ch < P.chunks.size() && P.chunks[ch].x < P.wave_g[w + 1]) ch++;
         P.chunk_beg.push_back((int64_t)ch);
     }
@@ -501,6 +550,32 @@ int32_t check_plan(smx_ctx c, const Plan &P)
             const GroupDesc &d = P.gd[t.x];
             const int ti = t.y >> 16, tj = t.y & 0xffff;
             if (tj > ti || ti * kTile >= d.npad) return fail(c, SMX_E_INVALID, "internal: tile index");
+        }
+        // size-bucket lists: every group of the wave in exactly one of them,
+        // with its full set of lower tiles of that shape
+        if ((int32_t)P.tiles_s_beg.size() != nw + 1 || (int32_t)P.tiles_b_beg.size() != nw + 1 ||
+            P.tiles_s_beg[nw] != (int64_t)P.tiles_s.size() || P.tiles_b_beg[nw] != (int64_t)P.tiles_b.size() ||
+            (int32_t)P.big.size() != P.ngroups)
+            return fail(c, SMX_E_INVALID, "internal: size-bucket tables");
+        std::vector<int64_t> seen((size_t)(P.wave_g[w + 1] - P.wave_g[w]), 0);
+        for (int pass = 0; pass < 2; pass++) {
+            const std::vector<TileDesc> &L = pass ? P.tiles_b : P.tiles_s;
+            const std::vector<int64_t> &B = pass ? P.tiles_b_beg : P.tiles_s_beg;
+            const int edge = pass ? kTile2 : kTile;
+            for (int64_t q = B[w]; q < B[w + 1]; q++) {
+                const TileDesc &t = L[(size_t)q];
+                if (t.x == -1) continue;
+                if (t.x < P.wave_g[w] || t.x >= P.wave_g[w + 1] || (P.big[t.x] != 0) != (pass == 1))
+                    return fail(c, SMX_E_INVALID, "internal: size-bucket tile group");
+                const int ti = t.y >> 16, tj = t.y & 0xffff;
+                if (tj > ti || ti * edge >= P.gd[t.x].npad) return fail(c, SMX_E_INVALID, "internal: size-bucket tile");
+                seen[(size_t)(t.x - P.wave_g[w])]++;
+            }
+        }
+        for (int32_t g = P.wave_g[w]; g < P.wave_g[w + 1]; g++) {
+            const int64_t nt = (P.gd[g].npad + (P.big[g] ? kTile2 : kTile) - 1) / (P.big[g] ? kTile2 : kTile);
+            if (seen[(size_t)(g - P.wave_g[w])] != nt * (nt + 1) / 2)
+                return fail(c, SMX_E_INVALID, "internal: size-bucket tile count");
         }
         for (int64_t q = P.chunk_beg[w]; q < P.chunk_beg[w + 1]; q++) {
             const int2 &ch = P.chunks[(size_t)q];
@@ -601,6 +676,8 @@ int32_t ensure_plan(smx_ctx c)
     if (st) return st;
     HIP_TRY(c, upload(c->d_gd, P.gd, c->stream));
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
+    HIP_TRY(c, upload(c->d_tiles_s, P.tiles_s, c->stream));
+    HIP_TRY(c, upload(c->d_tiles_b, P.tiles_b, c->stream));
     HIP_TRY(c, upload(c->d_tiles_full, P.tiles_full, c->stream));
     HIP_TRY(c, upload(c->d_plist, P.plist, c->stream));
     c->contrib_ready = false;
@@ -825,6 +902,8 @@ int32_t smx_destroy(smx_ctx c)
     c->d_bcol.release();
     c->d_gd.release();
     c->d_tiles.release();
+    c->d_tiles_s.release();
+    c->d_tiles_b.release();
     c->d_chunks.release();
     c->d_rinfo.release();
     c->d_bmap.release();
@@ -837,7 +916,7 @@ int32_t smx_destroy(smx_ctx c)
     c->d_flags.release();
     c->d_ndone.release();
     c->d_own.release();
-    c->d_tau_parts.release();
+    c->d_tdiag.release();
     c->d_tau_hist.release();
     c->d_kfix.release();
     c->d_sfix.release();
@@ -1057,6 +1136,31 @@ int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
     return SMX_OK;
 }
 
+int32_t smx_set_tile_shape(smx_ctx c, int32_t big_min_npad)
+{
+    if (!c) return SMX_E_INVALID;
+    if (big_min_npad < 0) return fail(c, SMX_E_INVALID, "big_min_npad must be >= 0");
+    if (big_min_npad != c->big_min_npad) {
+        c->big_min_npad = big_min_npad;
+        c->plan_dirty = true;
+        c->splan_dirty = true;
+        c->evaluated = false;
+        c->contrib_ready = false;
+    }
+    return SMX_OK;
+}
+
+int32_t smx_get_launch_config(smx_ctx c, int32_t *graph_steps, int32_t *tile_order, int32_t *big_min_npad,
+                              int32_t *kernel_variant)
+{
+    if (!c) return SMX_E_INVALID;
+    if (graph_steps) *graph_steps = c->graph_steps;
+    if (tile_order) *tile_order = c->tile_order;
+    if (big_min_npad) *big_min_npad = c->big_min_npad;
+    if (kernel_variant) *kernel_variant = c->kernel_variant;
+    return SMX_OK;
+}
+
 int32_t smx_set_workspace_limit(smx_ctx c, int64_t bytes)
 {
     if (!c) return SMX_E_INVALID;
@@ -1119,8 +1223,7 @@ int32_t eval_prepare(smx_ctx c, const EvalMode &m)
     const Plan &P = c->plan;
     const int32_t ng = P.ngroups;
     HIP_TRY(c, c->d_resid.ensure((size_t)ng * m.stride));
-    const int32_t tau_nt = (P.max_npad + kTile - 1) / kTile;
-    HIP_TRY(c, c->d_tau_parts.ensure((size_t)ng * std::max(tau_nt, 1)));
+    HIP_TRY(c, c->d_tdiag.ensure(std::max<size_t>(P.rinfo.size(), 1)));
     HIP_TRY(c, c->d_tau_hist.ensure((size_t)ng * m.stride));
     if (c->h_ndone_cap < m.stride) {
         if (c->h_ndone) (void)hipHostFree(c->h_ndone);
@@ -1164,6 +1267,8 @@ DevView ctx_view(smx_ctx c)
     DevView v;
     v.gd = c->d_gd.p;
     v.tiles = c->d_tiles.p;
+    v.tiles_s = c->d_tiles_s.p;
+    v.tiles_b = c->d_tiles_b.p;
     v.chunks = c->d_chunks.p;
     v.rinfo = c->d_rinfo.p;
     v.bmap = c->d_bmap.p;
@@ -1177,7 +1282,7 @@ DevView ctx_view(smx_ctx c)
     v.kfinal = c->d_kfinal.p;
     v.flags = c->d_flags.p;
     v.ndone = c->d_ndone.p;
-    v.tau_parts = c->d_tau_parts.p;
+    v.tdiag = c->d_tdiag.p;
     v.tau_hist = c->d_tau_hist.p;
     v.pe = c->d_pe.p;
     v.pn = c->d_pn.p;
@@ -1209,10 +1314,9 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     it.ndone = V.ndone;
     it.kfix = c->use_kfix ? c->d_kfix.p : nullptr;
     it.kact = -1;
-    it.tau_parts = V.tau_parts;
+    it.tdiag = V.tdiag;
     it.tau_hist = V.tau_hist;
     it.resid_stride = stride;
-    it.tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
     if (c->use_sfix) it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
     unsigned long long *gather_scale = c->use_sfix ? c->d_scale_scratch.p : it.scale_bits;
     if (events) HIP_TRY(c, hipEventRecord(c->ev_t0, st));
@@ -1225,7 +1329,9 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     c->launch_step.clear();
     c->launch_kind.clear();
     c->launch_wave.clear();
+    c->launch_subset.clear();
     int32_t wave = 0;
+    int32_t subset = 0;
     auto timed = [&](int kind, int k, auto &&launch) -> hipError_t {
         const size_t idx = c->launch_step.size();
         while (c->ev_launch.size() < 2 * (idx + 1)) {
@@ -1240,6 +1346,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         c->launch_step.push_back(k);
         c->launch_kind.push_back(kind);
         c->launch_wave.push_back(wave);
+        c->launch_subset.push_back(subset);
         return e;
     };
     const int64_t welems = P.work_elems;        // an operand's words take nw * welems 16-bit units
@@ -1263,7 +1370,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
             c->plan_gen, (uint64_t)c->precision, (uint64_t)c->max_iter, (uint64_t)c->n_polish,
             (uint64_t)c->graph_steps, (uint64_t)tangent, (uint64_t)c->use_sfix, (uint64_t)c->use_kfix,
             (uint64_t)c->kernel_variant, (uint64_t)(uintptr_t)arena, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
-            (uint64_t)(uintptr_t)c->d_resid.p, (uint64_t)(uintptr_t)c->d_tau_parts.p, (uint64_t)(uintptr_t)c->d_tau_hist.p,
+            (uint64_t)(uintptr_t)c->d_resid.p, (uint64_t)(uintptr_t)c->d_tdiag.p, (uint64_t)(uintptr_t)c->d_tau_hist.p,
             (uint64_t)(uintptr_t)c->d_sfix.p, (uint64_t)(uintptr_t)c->d_kfix.p,
             __builtin_bit_cast(uint64_t, c->tol), __builtin_bit_cast(uint64_t, c->switch_tol)};
         const size_t ngraph = (size_t)nwave * (size_t)(kmax / c->graph_steps + 1);
@@ -1279,6 +1386,11 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
         const int ntiles = (int)(P.tile_beg[wave + 1] - P.tile_beg[wave]);
         const TileDesc *tl = V.tiles + P.tile_beg[wave];
+        // one- and two-word products: the size buckets (128 x 128 and 256 x 256 tiles)
+        const bool buckets = mixed && fmt != 2 && nw <= 2;
+        const int nts = (int)(P.tiles_s_beg[wave + 1] - P.tiles_s_beg[wave]);
+        const int ntb = (int)(P.tiles_b_beg[wave + 1] - P.tiles_b_beg[wave]);
+        const TileDesc *tls = V.tiles_s + P.tiles_s_beg[wave], *tlb = V.tiles_b + P.tiles_b_beg[wave];
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
         const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
@@ -1309,12 +1421,33 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
                 if (e == hipSuccess && tangent)
                     e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, V.gd, tb[k & 1], wslab, tb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
-            } else {
+            } else if (!buckets) {
                 e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, ntiles, tl, V.gd, wb[k & 1],
                                                         wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
                 if (e == hipSuccess)
                     e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, ntiles, tl, V.gd,
                                                             wb[k & 1], wwp, wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
+            } else {
+                // squares of both buckets, then their updates (a group's square
+                // always precedes its update; the groups are independent)
+                e = hipSuccess;
+                subset = 1;
+                if (nts > 0)
+                    e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, nts, tls, V.gd, wb[k & 1],
+                                                            wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
+                subset = 2;
+                if (e == hipSuccess && ntb > 0)
+                    e = run(7, [&] { return launch_ns_words256(s, fmt, nw, 0, ntb, tlb, V.gd, wb[k & 1], wb[k & 1],
+                                                               wwp, it, k, c->switch_tol, kmax); });
+                subset = 1;
+                if (e == hipSuccess && nts > 0)
+                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, nts, tls, V.gd, wb[k & 1], wwp,
+                                                            wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
+                subset = 2;
+                if (e == hipSuccess && ntb > 0)
+                    e = run(8, [&] { return launch_ns_words256(s, fmt, nw, 1, ntb, tlb, V.gd, wb[k & 1], wwp,
+                                                               wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
+                subset = 0;
             }
             return e;
         };
@@ -1406,7 +1539,8 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
 // context memory allocated by earlier calls.
 struct StaticLayout {
     int64_t gd = 0, tiles = 0, chunks = 0, rinfo = 0, bmap = 0, boffs = 0, scat = 0, own = 0, plist = 0;
-    int64_t scale = 0, resid = 0, done = 0, kfinal = 0, flags = 0, ndone = 0, tau_parts = 0, tau_hist = 0;
+    int64_t tiles_s = 0, tiles_b = 0;
+    int64_t scale = 0, resid = 0, done = 0, kfinal = 0, flags = 0, ndone = 0, tdiag = 0, tau_hist = 0;
     int64_t pe = 0, pn = 0, arena = 0, pool = 0, end = 0;
 };
 
@@ -1422,10 +1556,11 @@ StaticLayout static_layout(smx_ctx c, const Plan &P, int32_t stride)
         return at;
     };
     const int64_t ng = std::max(P.ngroups, 1);
-    const int64_t tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
     const int64_t nb = std::max<int64_t>(c->nnzb, 1);
     L.gd = take(vbytes(P.gd));
     L.tiles = take(vbytes(P.tiles));
+    L.tiles_s = take(vbytes(P.tiles_s));
+    L.tiles_b = take(vbytes(P.tiles_b));
     L.chunks = take(vbytes(P.chunks));
     L.rinfo = take(vbytes(P.rinfo));
     L.bmap = take(vbytes(P.bmap));
@@ -1439,7 +1574,7 @@ StaticLayout static_layout(smx_ctx c, const Plan &P, int32_t stride)
     L.kfinal = take(4 * ng);
     L.flags = take(4 * ng);
     L.ndone = take(4);
-    L.tau_parts = take(8 * ng * tau_nt);
+    L.tdiag = take(8 * (int64_t)P.rinfo.size());
     L.tau_hist = take(8 * ng * stride);
     L.pe = take(8 * nb);
     L.pn = take(8 * nb);
@@ -1537,6 +1672,8 @@ int32_t smx_evaluate_static(smx_ctx c)
         if (own[0] != c->uid || own[1] != c->splan_gen) {
             HIP_TRY(c, upload_to(base, L.gd, P.gd, st));
             HIP_TRY(c, upload_to(base, L.tiles, P.tiles, st));
+            HIP_TRY(c, upload_to(base, L.tiles_s, P.tiles_s, st));
+            HIP_TRY(c, upload_to(base, L.tiles_b, P.tiles_b, st));
             HIP_TRY(c, upload_to(base, L.chunks, P.chunks, st));
             HIP_TRY(c, upload_to(base, L.rinfo, P.rinfo, st));
             HIP_TRY(c, upload_to(base, L.bmap, P.bmap, st));
@@ -1551,6 +1688,8 @@ int32_t smx_evaluate_static(smx_ctx c)
     DevView V;
     V.gd = reinterpret_cast<const GroupDesc *>(base + L.gd);
     V.tiles = reinterpret_cast<const TileDesc *>(base + L.tiles);
+    V.tiles_s = reinterpret_cast<const TileDesc *>(base + L.tiles_s);
+    V.tiles_b = reinterpret_cast<const TileDesc *>(base + L.tiles_b);
     V.chunks = reinterpret_cast<const int2 *>(base + L.chunks);
     V.rinfo = reinterpret_cast<const RowInfo *>(base + L.rinfo);
     V.bmap = reinterpret_cast<const int32_t *>(base + L.bmap);
@@ -1564,7 +1703,7 @@ int32_t smx_evaluate_static(smx_ctx c)
     V.kfinal = reinterpret_cast<int32_t *>(base + L.kfinal);
     V.flags = reinterpret_cast<int32_t *>(base + L.flags);
     V.ndone = reinterpret_cast<int32_t *>(base + L.ndone);
-    V.tau_parts = reinterpret_cast<double *>(base + L.tau_parts);
+    V.tdiag = reinterpret_cast<double *>(base + L.tdiag);
     V.tau_hist = reinterpret_cast<double *>(base + L.tau_hist);
     V.pe = reinterpret_cast<double *>(base + L.pe);
     V.pn = reinterpret_cast<double *>(base + L.pn);
@@ -1709,9 +1848,11 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
         int npairs = 1;
         if (c->last_precision == SMX_FP16_2W) npairs = 3;
         if (c->last_precision == SMX_BF16_3W) npairs = 6;
+        const bool buckets = c->last_precision == SMX_FP16_2W || c->last_precision == SMX_BF16_1W;
         for (int32_t g = 0; g < ng; g++) {
             const GroupDesc &d = P.gd[g];
-            const double per = P.wtiles[g] * 2.0 * 64 * 64 * d.npad;
+            const double per = (buckets && P.big[g]) ? P.wtiles2[g] * 2.0 * 16 * 16 * d.npad
+                                                     : P.wtiles[g] * 2.0 * 64 * 64 * d.npad;
             const double kb = it[g] - c->last_polish;     // bulk steps taken
             if (c->last_polish == 0) {
                 exec += per * (2.0 * kb + 1.0);
@@ -1768,12 +1909,14 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
             ms[l] = t;
         }
         if (algo_flops) {
-            const int32_t k = c->launch_step[l], w = c->launch_wave[l];
+            const int32_t k = c->launch_step[l], w = c->launch_wave[l], sub = c->launch_subset[l];
             double f = 0;
             for (int32_t g = c->plan.wave_g[w]; g < c->plan.wave_g[w + 1]; g++) {
+                if (sub == 1 && c->plan.big[g]) continue;     // the launch covers one size bucket
+                if (sub == 2 && !c->plan.big[g]) continue;
                 bool active = true;                           // polish launches work on every group
-                if (kd == 0 || kd == 2) active = k <= kf[g];  // squares run up to the last step
-                if (kd == 1 || kd == 3 || kd == 6) active = k < kf[g];   // updates (and tangents) stop one earlier
+                if (kd == 0 || kd == 2 || kd == 7) active = k <= kf[g];  // squares run up to the last step
+                if (kd == 1 || kd == 3 || kd == 6 || kd == 8) active = k < kf[g];   // updates (and tangents) stop one earlier
                 const double n = c->plan.gd[g].n;
                 if (active) f += 2.0 * n * n * n;
             }
@@ -1903,7 +2046,7 @@ static std::string tune_key(smx_ctx c)
         s3 += (double)d.npad * d.npad * d.npad;
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|p%d|g%d|w%d|n%.0f|m%d|c%.4e", dev.c_str(), c->precision, P.ngroups, P.nwaves(),
+    std::snprintf(buf, sizeof buf, "v2|%s|p%d|g%d|w%d|n%.0f|m%d|c%.4e", dev.c_str(), c->precision, P.ngroups, P.nwaves(),
                   s1, P.max_npad, s3);
     return buf;
 }
@@ -1918,19 +2061,20 @@ int32_t smx_autotune(smx_ctx c, int32_t reps, int32_t use_cache, int32_t *graph_
     if (int32_t st = ensure_plan(c)) return st;
     const char *path = std::getenv("SMX_TUNE_CACHE");
     std::string key = tune_key(c);
-    int32_t best_g = -1, best_o = -1;
+    int32_t best_g = -1, best_o = -1, best_b = -1;
     double best = INFINITY;
     if (use_cache && path) {
         if (FILE *f = std::fopen(path, "r")) {
             char line[512];
             while (std::fgets(line, sizeof line, f)) {
                 char k[320];
-                int g, o;
+                int g, o, b;
                 double ms;
-                if (std::sscanf(line, "%319s %d %d %lf", k, &g, &o, &ms) == 4 && key == k && g >= 0 && g <= 64 &&
-                    (o == 0 || o == 1)) {
+                if (std::sscanf(line, "%319s %d %d %d %lf", k, &g, &o, &b, &ms) == 5 && key == k && g >= 0 && g <= 64 &&
+                    (o == 0 || o == 1) && b >= 0) {
                     best_g = g;
                     best_o = o;
+                    best_b = b;
                     best = ms;
                 }
             }
@@ -1939,39 +2083,46 @@ int32_t smx_autotune(smx_ctx c, int32_t reps, int32_t use_cache, int32_t *graph_
     }
     const bool from_cache = best_g >= 0;
     if (!from_cache) {
-        // candidates: launch order x step graphs; each timed by device time of whole evaluations
-        const int32_t orders[2] = {0, 1};
-        const int32_t graphs[3] = {0, 2, 8};
-        const int32_t keep_g = c->graph_steps, keep_o = c->tile_order;
-        for (int32_t o : orders)
-            for (int32_t g : graphs) {
-                if (int32_t st = smx_set_tile_order(c, o)) return st;
-                if (int32_t st = smx_set_graph(c, g)) return st;
-                double tmin = INFINITY;
-                for (int32_t r = 0; r <= reps; r++) {      // the first run captures graphs / warms up
-                    int32_t st = smx_evaluate(c);
-                    if (st == SMX_OK) st = smx_wait(c);
-                    if (st != SMX_OK && st != SMX_E_NOT_CONVERGED) {
-                        (void)smx_set_tile_order(c, keep_o);
-                        (void)smx_set_graph(c, keep_g);
-                        return st;
+        // candidates: launch order x step graphs x (one- and two-word products)
+        // the size bucket boundary of the 256 x 256 tiles; each timed by device
+        // time of whole evaluations
+        const int32_t keep_g = c->graph_steps, keep_o = c->tile_order, keep_b = c->big_min_npad;
+        std::vector<int32_t> shapes = {c->big_min_npad};
+        if (c->precision == SMX_FP16_2W || c->precision == SMX_BF16_1W) shapes = {0, 384, 640, 896};
+        for (int32_t b : shapes)
+            for (int32_t o : {0, 1})
+                for (int32_t g : {0, 2, 8}) {
+                    if (int32_t st = smx_set_tile_shape(c, b)) return st;
+                    if (int32_t st = smx_set_tile_order(c, o)) return st;
+                    if (int32_t st = smx_set_graph(c, g)) return st;
+                    double tmin = INFINITY;
+                    for (int32_t r = 0; r <= reps; r++) {      // the first run captures graphs / warms up
+                        int32_t st = smx_evaluate(c);
+                        if (st == SMX_OK) st = smx_wait(c);
+                        if (st != SMX_OK && st != SMX_E_NOT_CONVERGED) {
+                            (void)smx_set_tile_shape(c, keep_b);
+                            (void)smx_set_tile_order(c, keep_o);
+                            (void)smx_set_graph(c, keep_g);
+                            return st;
+                        }
+                        smx_stats sst;
+                        if (int32_t e = smx_get_stats(c, &sst)) return e;
+                        if (r > 0) tmin = std::min(tmin, sst.time_total_ms);
                     }
-                    smx_stats sst;
-                    if (int32_t e = smx_get_stats(c, &sst)) return e;
-                    if (r > 0) tmin = std::min(tmin, sst.time_total_ms);
+                    if (tmin < best) {
+                        best = tmin;
+                        best_g = g;
+                        best_o = o;
+                        best_b = b;
+                    }
                 }
-                if (tmin < best) {
-                    best = tmin;
-                    best_g = g;
-                    best_o = o;
-                }
-            }
         if (path)
             if (FILE *f = std::fopen(path, "a")) {
-                std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), best_g, best_o, best);
+                std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), best_g, best_o, best_b, best);
                 std::fclose(f);
             }
     }
+    if (int32_t st = smx_set_tile_shape(c, best_b)) return st;
     if (int32_t st = smx_set_tile_order(c, best_o)) return st;
     if (int32_t st = smx_set_graph(c, best_g)) return st;
     c->evaluated = false;
@@ -2198,10 +2349,9 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     it.ndone = c->d_ndone.p;
     it.kfix = c->d_kfix.p;
     it.kact = -1;
-    it.tau_parts = c->d_tau_parts.p;
+    it.tdiag = c->d_tdiag.p;
     it.tau_hist = c->d_tau_hist.p;
     it.resid_stride = c->last_stride;
-    it.tau_nt = std::max((P.max_npad + kTile - 1) / kTile, 1);
     const int scratch_slot = c->last_max_iter + 1;    // residual slot the adjoint squares may use
     const int nt = (int)P.tiles.size(), ntf = (int)P.tiles_full.size();
     const TileDesc *tl = c->d_tiles.p, *tf = c->d_tiles_full.p;

@@ -53,10 +53,10 @@ struct IterState {
     int32_t *ndone;                   // [1] number of finished groups
     const int32_t *kfix;              // [ngroups] frozen step counts (nullptr: stopping rule)
     int32_t kact;                     // >= 0: only groups with kact < kfix[g] take part (adjoint passes)
-    double *tau_parts;                // [ngroups * tau_nt] per diagonal tile: sum of (1 - T_ii)
+    double *tdiag;                    // [sum of n_pad] 1 - T_ii of the last square, row i of group g
+                                      // at GroupDesc::rinfo_off + i (reduced-precision bulk)
     double *tau_hist;                 // [ngroups * resid_stride] Tr(I - X_k^2) per step
     int32_t resid_stride;             // steps 0..max_iter, then one slot per polish step
-    int32_t tau_nt;                   // tile rows of the largest group
 };
 
 // Row r of A_g = K[R(g), R(g)] - mu I over the columns c < n_g (Sec. III-A
@@ -158,6 +158,13 @@ __host__ __device__ inline int64_t word_pos(int nw, int ld, int r, int c)
 hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int variant, int ntiles, const TileDesc *tiles,
                            const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                            unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
+// The same products on 256 x 256 output tiles (tiles list (group, tile row
+// << 16 | tile column) in units of 256; fmt 0 / 1 with nw = 1 or 2 only).
+// Results are bitwise those of the 128 x 128 tiles.
+constexpr int kTile2 = 256;
+hipError_t launch_ns_words256(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
+                              const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
+                              unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
 // Group-walking launchers take the first group g0 and the count ngroups (a wave).
 // Gershgorin bounds only (atomic max of the row sums into scale_bits), no
 // writes of A_g; then X_0 = A_g / s_g gathered straight into the word storage

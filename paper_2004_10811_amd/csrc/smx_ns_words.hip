@@ -119,6 +119,52 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+// tau_k = Tr(I - X_k^2) of a group from the diagonal values 1 - T_ii the
+// square wrote for its true rows: lane l sums rows l, l + 64, ... in order,
+// then a fixed xor tree, and lane 0's sum is taken.  Every wave of every
+// workgroup evaluates the same expression, so all of them (whatever their
+// tile shape) see the same bits.
+__device__ inline double tau_of(const double *__restrict__ td, int n, int lane)
+{
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += td[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return __shfl(s, 0, 64);
+}
+
+// Stopping rule of the bulk at step k (update products, before any work):
+// the group leaves the bulk at X_k once tau_k <= switch_tol, or once tau_k
+// stops falling (tau_k >= tau_{k-1}, or tau_k < 0.1 and tau_k > tau_{k-1} / 2:
+// the floor of the word format), or at the step cap.  The leader (thread 0 of
+// the group's first tile) records tau_k and, on leaving, the result step and
+// the flags: not converged (bit 0) when the bulk leaves above switch_tol and
+// `strict` (every format but single-word BF16, whose floor lies above
+// switch_tol by design and whose polished residual decides alone), non-finite
+// (bit 1).  Returns true when the group has left the bulk.
+__device__ inline bool bulk_stop(const IterState &it, const GroupDesc &gd, int g, int k, bool leader, int lane,
+                                 double switch_tol, int kmax, bool strict)
+{
+    const int64_t base = (int64_t)g * it.resid_stride;
+    const double rk = __longlong_as_double((long long)it.resid_bits[base + k]);
+    const double tau = tau_of(it.tdiag + gd.rinfo_off, gd.n, lane);
+    const double tp = k > 0 ? it.tau_hist[base + k - 1] : __builtin_huge_val();
+    const bool finite = (rk <= 1.7976931348623157e308) && (fabs(tau) <= 1.7976931348623157e308);
+    // floor of the word format: tau stops halving in the quadratic phase, or
+    // stops falling at all (in the linear phase every 1 - x_i^2 shrinks)
+    const bool stall = ((tau < 0.1) && (tau > 0.5 * tp)) || (tau >= tp);
+    if (leader) it.tau_hist[base + k] = tau;
+    if (tau <= switch_tol || stall || k >= kmax || !finite) {
+        if (leader) {
+            it.done[g] = 1;
+            it.kfinal[g] = k;
+            it.flags[g] = !finite ? 2 : ((strict && tau > switch_tol) ? 1 : 0);
+            atomicAdd(it.ndone, 1);
+        }
+        return true;
+    }
+    return false;
+}
+
 template <int FMT>
 __device__ inline unsigned short to_word_f(float v);
 template <>
@@ -226,7 +272,6 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                      double switch_tol, int kmax)
 {
     __shared__ __attribute__((aligned(16))) unsigned char smem[words_lds_bytes<NW>()];
-    __shared__ double wsum[4];
     unsigned short *Ls = reinterpret_cast<unsigned short *>(smem);   // [2 operands][NW][BM][BK]
     float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
 
@@ -238,34 +283,9 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const GroupDesc gd = groups[g];
     const int ld = gd.npad;
 
-    if (MODE == 1) {
-        const int64_t base = (int64_t)g * it.resid_stride;
-        const double rk = __longlong_as_double((long long)it.resid_bits[base + k]);
-        const int nt = (ld + BM - 1) / BM;
-        double tau = 0.0;
-        for (int t = 0; t < nt; t++) tau += it.tau_parts[(int64_t)g * it.tau_nt + t];
-        const double tp = k > 0 ? it.tau_hist[base + k - 1] : __builtin_huge_val();
-        const bool finite = (rk <= 1.7976931348623157e308) && (fabs(tau) <= 1.7976931348623157e308);
-        // floor of the word format: tau stops halving in the quadratic phase, or
-        // stops falling at all (in the linear phase every 1 - x_i^2 shrinks)
-        const bool stall = ((tau < 0.1) && (tau > 0.5 * tp)) || (tau >= tp);
-        if (ti == 0 && tj == 0 && threadIdx.x == 0) it.tau_hist[base + k] = tau;
-        if (tau <= switch_tol || stall || k >= kmax || !finite) {
-            if (ti == 0 && tj == 0 && threadIdx.x == 0) {
-                it.done[g] = 1;
-                it.kfinal[g] = k;
-                // Not converged (bit 0) when the bulk leaves above the switch
-                // threshold, by the stall rule or at the step cap: the polish
-                // then cannot reach the FP64 tolerance.  The single-word format
-                // always leaves at its rounding floor (tau ~ 1e-2 .. 1e-1, itself
-                // noisy at that level); whether its polish converged is decided
-                // on the polished residual alone.
-                it.flags[g] = !finite ? 2 : ((NW > 1 && tau > switch_tol) ? 1 : 0);
-                atomicAdd(it.ndone, 1);
-            }
-            return;
-        }
-    }
+    if (MODE == 1 && bulk_stop(it, gd, g, k, ti == 0 && tj == 0 && threadIdx.x == 0, threadIdx.x & 63, switch_tol,
+                               kmax, NW > 1))
+        return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -397,7 +417,6 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const bool diag = (ti == tj);
     unsigned short *og = out + NW * gd.off;
     float rmax = 0.f;
-    double dsum = 0.0;
     auto value = [&](float t, int r, int c) -> float {
         return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
     };
@@ -443,7 +462,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                         float d = fabsf(t - (r == c ? 1.f : 0.f));
                         if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                         rmax = fmaxf(rmax, d);
-                        if (r == c) dsum += 1.0 - (double)t;
+                        if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                     }
                     v[e] = value(t, r, c) * sc;
                 }
@@ -520,7 +539,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                     float d = fabsf(t - (r == c ? 1.f : 0.f));
                     if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                     rmax = fmaxf(rmax, d);
-                    if (r == c) dsum += 1.0 - (double)t;
+                    if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                 }
                 v[e] = value(t, r, c) * sc;
             }
@@ -575,13 +594,264 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         rm = wave_max(rm);
         if (lane == 0)
             atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
-        if (diag) {
-            // fixed-order reduction of the diagonal partials: lanes, then waves
-            for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
-            if (lane == 0) wsum[wave] = dsum;
-            __syncthreads();
-            if (tid == 0) it.tau_parts[(int64_t)g * it.tau_nt + ti] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+}
+
+// ---- 256 x 256 output tiles (one and two words) ---------------------------
+// The 128 x 128 tile moves 2 nw x (128 + 128) x 32 bytes from L2 into LDS per
+// K step for 128 x 128 x 32 multiply-adds per word product; the operand
+// stream (bounded by the L2 requests a CU keeps in flight) then takes longer
+// than the matrix-core work.  A 256 x 256 tile halves the bytes per product.
+// One workgroup of 512 lanes per CU: eight waves, two per SIMD, wave (wr, wc)
+// holds rows 64 wr .. + 63 and columns 128 wc .. + 127 of the tile (128 FP32
+// accumulators per lane).  Operands are double-buffered in LDS (two stages of
+// 2 nw x 16 KB): the loads of K step t + 1 are in flight while the matrix
+// cores work on step t.  Per output element the sequence of matrix-core
+// operations (K steps in order, word pairs least significant first) is the
+// one of the 128 x 128 kernel, so both tile shapes give the same bits.
+// Blocks of 16 x 16 that lie above the diagonal of a diagonal tile, or
+// outside the matrix, are not computed (their results are never stored).
+constexpr int BM2 = 256;
+constexpr int CST2 = 260;          // column-major staging of a 64-column quarter: 1040-B columns
+
+template <int NW>
+__host__ __device__ constexpr int words256_lds_bytes()
+{
+    return (2 * 2 * NW * BM2 * BK * 2) > (64 * CST2 * 4) ? (2 * 2 * NW * BM2 * BK * 2) : (64 * CST2 * 4);
+}
+
+template <int FMT, int NW, int MODE>
+__global__ __launch_bounds__(512, 1)
+void ns_words256_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
+                        const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
+                        unsigned short *__restrict__ out, IterState it, int k, double switch_tol, int kmax)
+{
+    static_assert(NW == 1 || NW == 2, "two stages of three words do not fit the LDS");
+    __shared__ __attribute__((aligned(16))) unsigned char smem[words256_lds_bytes<NW>()];
+    unsigned short *Ls = reinterpret_cast<unsigned short *>(smem);   // [stage][2 operands][NW][BM2][BK]
+    float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
+
+    const TileDesc td = tiles[blockIdx.x];
+    const int g = td.x;
+    if (g < 0) return;                  // idle slot of the launch order
+    if (it.done[g]) return;
+    const int ti = td.y >> 16, tj = td.y & 0xffff;
+    const GroupDesc gd = groups[g];
+    const int ld = gd.npad;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform: scalar branches
+
+    if (MODE == 1 && bulk_stop(it, gd, g, k, ti == 0 && tj == 0 && tid == 0, lane, switch_tol, kmax, NW > 1))
+        return;
+
+    const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+    const bool diag = (ti == tj);
+
+    // Loads: instruction (operand, word, 16-column group q = wave + 8 qq) fills
+    // 1 KB of LDS; lane l fills slot l % 4 of column 16 q + l / 4 with chunk
+    // (slot ^ swz(column)) of that column's K step.  Column groups that lie
+    // wholly beyond ld are not loaded (their LDS rows feed only products that
+    // reach discarded outputs); single columns beyond ld read column 0.
+    constexpr int PH = BM2 * BK;        // halves per (operand, word) region
+    constexpr int STG = 2 * NW * PH;    // halves per stage
+    const unsigned short *srcA[2], *srcB[2];
+    int kcoff[2];
+#pragma unroll
+    for (int qq = 0; qq < 2; qq++) {
+        const int cl = (wave + 8 * qq) * 16 + lane / CPC;
+        kcoff[qq] = ((lane % CPC) ^ swz(cl)) * 8;
+        srcA[qq] = xin + NW * gd.off + word_pos(NW, ld, 0, ti * BM2 + cl < ld ? ti * BM2 + cl : 0);
+        srcB[qq] = bin + NW * gd.off + word_pos(NW, ld, 0, tj * BM2 + cl < ld ? tj * BM2 + cl : 0);
+    }
+    bool ldA[2], ldB[2];                // wave-uniform: the column group has a column inside the matrix
+#pragma unroll
+    for (int qq = 0; qq < 2; qq++) {
+        ldA[qq] = ti * BM2 + (wave + 8 * qq) * 16 < ld;
+        ldB[qq] = tj * BM2 + (wave + 8 * qq) * 16 < ld;
+    }
+    // load instruction m (0 .. 4 NW - 1: operand m & 1, column group qq = (m >> 1) & 1,
+    // word m >> 2) of K step kt into stage s
+    constexpr int NLD = 4 * NW;
+    auto issue_one = [&](int m, int kt, int s) {
+        const int o = m & 1, qq = (m >> 1) & 1, w = m >> 2;
+        const bool on = o ? ldB[qq] : ldA[qq];
+        if (!on) return;
+        const unsigned short *src = (o ? srcB[qq] : srcA[qq]) + NW * (kt * BK) + 32 * w + kcoff[qq];
+        unsigned short *dst = Ls + s * STG + (o * NW + w) * PH + (wave + 8 * qq) * 16 * BK;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    };
+    auto issue = [&](int kt, int s) {
+#pragma unroll
+        for (int m = 0; m < NLD; m++) issue_one(m, kt, s);
+    };
+
+    // waves whose part of the tile holds an output that is stored: inside the
+    // matrix and, in a diagonal tile, not entirely above the diagonal
+    const int row_w = wr * 64, col_w = wc * 128;          // tile-local
+    const bool wave_live = (ti * BM2 + row_w < ld) && (tj * BM2 + col_w < ld) && !(diag && row_w + 63 < col_w);
+
+    f4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = ld / BK;             // ld is a multiple of 32
+    issue(0, 0);
+    wait_vm0();
+    lds_barrier();
+    for (int kt = 0; kt < nk; kt++) {
+        const int s = kt & 1;
+        const bool more = kt + 1 < nk;   // stage s ^ 1 was last read before the previous barrier
+        if (wave_live) {
+            const unsigned short *La = Ls + s * STG;
+            const unsigned short *Lb = Ls + s * STG + NW * PH;
+            u16x8 av[4][NW], bv[2][NW];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int ca = row_w + i * 16 + li;
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    av[i][w] = *reinterpret_cast<const u16x8 *>(La + w * PH + ca * BK + ((lg ^ swz(ca)) * 8));
+            }
+            auto load_b = [&](int j, u16x8 *dst) {
+                const int cb = col_w + j * 16 + li;
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    dst[w] = *reinterpret_cast<const u16x8 *>(Lb + w * PH + cb * BK + ((lg ^ swz(cb)) * 8));
+            };
+            load_b(0, bv[0]);
+            // the next K step's operand loads are spread over the column blocks
+            // (a wave issues its memory instructions in order, so a burst of
+            // them would hold back its products while the address unit drains);
+            // the B fragments of column block j + 1 are read while the matrix
+            // cores work on block j; the four row blocks interleave so that no
+            // product waits on the one before it
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                if (more && (j * NLD) % 8 == 0) issue_one(j * NLD / 8, kt + 1, s ^ 1);
+                if (j + 1 < 8) load_b(j + 1, bv[(j + 1) & 1]);
+#pragma unroll
+                for (int pr = npairs<NW>() - 1; pr >= 0; pr--)          // least significant products first
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        acc[i][j] = mfma16<FMT>(av[i][pair_p(pr)], bv[j & 1][pair_q(pr)], acc[i][j]);
+            }
+        } else if (more) {
+            issue(kt + 1, s ^ 1);
         }
+        wait_vm0();
+        lds_barrier();                  // step t + 1 is in LDS and every wave is done with step t
+    }
+
+    // ---- epilogue, in four rounds over 64-column quarters of the tile (the
+    // waves with wc == quarter / 2 hold them, in accumulator columns 4 (quarter
+    // % 2) .. + 3).  Lane l, register v of block (i, j) holds row 16 i + 4 (l /
+    // 16) + v and column 16 j + l % 16 of the wave's part.  As in the 128 x 128
+    // kernel: one conversion per element, the words of each element are put
+    // back into the staging for the mirror pass, staging rows XOR-swizzled by
+    // column group so that the mirror's reads are free of bank conflicts.
+    constexpr float inv_s2 = (float)(1.0 / (word_scale<FMT>() * word_scale<FMT>()));
+    constexpr float sc = (float)word_scale<FMT>();
+    const int n = gd.n;
+    unsigned short *og = out + NW * gd.off;
+    float rmax = 0.f;
+    auto value = [&](float t, int r, int c) -> float {
+        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
+    };
+    auto cpos = [](int col, int row) { return col * CST2 + (row ^ (((col >> 3) & 7) << 2)); };
+    unsigned int *Cw = reinterpret_cast<unsigned int *>(Cs);
+#pragma unroll
+    for (int q4 = 0; q4 < 4; q4++) {
+        if (tj * BM2 + q4 * 64 >= ld) break;        // the quarter lies beyond the matrix
+        if (wave_live && wc == (q4 >> 1)) {
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    *reinterpret_cast<f4 *>(&Cs[cpos(j * 16 + li, row_w + i * 16 + lg * 4)]) = acc[i][(q4 & 1) * 4 + j];
+        }
+        __syncthreads();
+        // the tile's own positions: unit (column cl of the quarter, 8-row chunk rc)
+#pragma unroll 2
+        for (int qq = 0; qq < 4; qq++) {
+            const int u = tid + 512 * qq;
+            const int rc = u & 31, cl = u >> 5;
+            const int c = tj * BM2 + q4 * 64 + cl, r0 = ti * BM2 + rc * 8;
+            if (c >= ld || r0 >= ld) continue;
+            if (diag && r0 + 7 < c) continue;
+            const int p0 = cpos(cl, rc * 8), p1 = cpos(cl, rc * 8 + 4);
+            const int sw = rc & 4;
+            const f4 fa = *reinterpret_cast<const f4 *>(Cs + (sw ? p1 : p0));
+            const f4 fb = *reinterpret_cast<const f4 *>(Cs + (sw ? p0 : p1));
+            const f4 lo = sw ? fb : fa, hi = sw ? fa : fb;
+            float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int r = r0 + e;
+                const float t = v[e] * inv_s2;
+                if (MODE == 0 && r < n && c < n && r >= c) {
+                    float d = fabsf(t - (r == c ? 1.f : 0.f));
+                    if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
+                    rmax = fmaxf(rmax, d);
+                    if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
+                }
+                v[e] = value(t, r, c) * sc;
+            }
+            u16x8 wv[NW];
+            split8<FMT, NW>(v, wv);
+#pragma unroll
+            for (int w = 0; w < NW; w++)
+                *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, r0, c) + 32 * w) = wv[w];
+            u4 pa, pb;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                pa[e] = (unsigned int)wv[0][e] | (NW == 2 ? ((unsigned int)wv[NW - 1][e] << 16) : 0u);
+                pb[e] = (unsigned int)wv[0][e + 4] | (NW == 2 ? ((unsigned int)wv[NW - 1][e + 4] << 16) : 0u);
+            }
+            *reinterpret_cast<u4 *>(Cw + p0) = pa;
+            *reinterpret_cast<u4 *>(Cw + p1) = pb;
+        }
+        __syncthreads();                            // every element's words are staged
+        // mirror: tile element (rl, cl) goes to (cl, rl) of the matrix; unit (tile
+        // row rl, 8-column chunk cc); in a diagonal tile only positions above
+        // the diagonal
+#pragma unroll 2
+        for (int qq = 0; qq < 4; qq++) {
+            const int u = tid + 512 * qq;
+            const int cc = u & 7, rl = u >> 3;
+            const int r = ti * BM2 + rl, c0 = tj * BM2 + q4 * 64 + cc * 8;
+            if (r >= ld || c0 >= ld) continue;
+            if (diag && c0 >= r) continue;
+            u16x8 wv[NW];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const unsigned int pk = Cw[cpos(cc * 8 + e, rl)];
+                wv[0][e] = (unsigned short)(pk & 0xffffu);
+                if constexpr (NW == 2) wv[NW - 1][e] = (unsigned short)(pk >> 16);
+            }
+            if (!diag || c0 + 8 <= r) {
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    *reinterpret_cast<u16x8 *>(og + word_pos(NW, ld, c0, r) + 32 * w) = wv[w];
+            } else {
+                for (int e = 0; c0 + e < r; e++)
+#pragma unroll
+                    for (int w = 0; w < NW; w++) og[word_pos(NW, ld, c0, r) + 32 * w + e] = wv[w][e];
+            }
+        }
+        __syncthreads();                            // staging is free for the next quarter
+    }
+
+    if (MODE == 0) {
+        double rm = (double)rmax;
+        rm = wave_max(rm);
+        if (lane == 0)
+            atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
     }
 }
 
@@ -603,7 +873,6 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
                    float *__restrict__ out, IterState it, int k, double switch_tol, int kmax)
 {
     __shared__ __attribute__((aligned(16))) unsigned char smem[f32_lds_bytes()];
-    __shared__ double wsum[4];
     float *Ls = reinterpret_cast<float *>(smem);                     // [2 operands][BM][BK]
     float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
 
@@ -615,29 +884,9 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const GroupDesc gd = groups[g];
     const int ld = gd.npad;
 
-    if (MODE == 1) {
-        const int64_t base = (int64_t)g * it.resid_stride;
-        const double rk = __longlong_as_double((long long)it.resid_bits[base + k]);
-        const int nt = (ld + BM - 1) / BM;
-        double tau = 0.0;
-        for (int t = 0; t < nt; t++) tau += it.tau_parts[(int64_t)g * it.tau_nt + t];
-        const double tp = k > 0 ? it.tau_hist[base + k - 1] : __builtin_huge_val();
-        const bool finite = (rk <= 1.7976931348623157e308) && (fabs(tau) <= 1.7976931348623157e308);
-        // floor of the word format: tau stops halving in the quadratic phase, or
-        // stops falling at all (in the linear phase every 1 - x_i^2 shrinks)
-        const bool stall = ((tau < 0.1) && (tau > 0.5 * tp)) || (tau >= tp);
-        if (ti == 0 && tj == 0 && threadIdx.x == 0) it.tau_hist[base + k] = tau;
-        if (tau <= switch_tol || stall || k >= kmax || !finite) {
-            if (ti == 0 && tj == 0 && threadIdx.x == 0) {
-                it.done[g] = 1;
-                it.kfinal[g] = k;
-                // not converged (bit 0) when the bulk leaves above the switch threshold
-                it.flags[g] = !finite ? 2 : (tau > switch_tol ? 1 : 0);
-                atomicAdd(it.ndone, 1);
-            }
-            return;
-        }
-    }
+    if (MODE == 1 && bulk_stop(it, gd, g, k, ti == 0 && tj == 0 && threadIdx.x == 0, threadIdx.x & 63, switch_tol,
+                               kmax, true))
+        return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -717,7 +966,6 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const bool diag = (ti == tj);
     float *og = out + gd.off;
     float rmax = 0.f;
-    double dsum = 0.0;
     auto value = [&](float t, int r, int c) -> float {
         return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
     };
@@ -749,7 +997,7 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
                     float d = fabsf(t - (r == c ? 1.f : 0.f));
                     if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                     rmax = fmaxf(rmax, d);
-                    if (r == c) dsum += 1.0 - (double)t;
+                    if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                 }
                 v[e] = value(t, r, c);
             }
@@ -796,13 +1044,6 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
         rm = wave_max(rm);
         if (lane == 0)
             atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
-        if (diag) {
-            // fixed-order reduction of the diagonal partials: lanes, then waves
-            for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
-            if (lane == 0) wsum[wave] = dsum;
-            __syncthreads();
-            if (tid == 0) it.tau_parts[(int64_t)g * it.tau_nt + ti] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
-        }
     }
 }
 
@@ -939,6 +1180,21 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int varian
     if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_ns_words256(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
+                              const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
+                              unsigned short *out, const IterState &it, int k, double switch_tol, int kmax)
+{
+    if (ntiles <= 0) return hipSuccess;
+#define SMX_W2(F, N, M) hipLaunchKernelGGL((ns_words256_kernel<F, N, M>), dim3(ntiles), dim3(512), 0, st, tiles, \
+                                           groups, x, b, out, it, k, switch_tol, kmax)
+    if (fmt == 0 && nw == 2) { if (mode == 0) SMX_W2(0, 2, 0); else SMX_W2(0, 2, 1); }
+    else if (fmt == 0 && nw == 1) { if (mode == 0) SMX_W2(0, 1, 0); else SMX_W2(0, 1, 1); }
+    else if (fmt == 1 && nw == 1) { if (mode == 0) SMX_W2(1, 1, 0); else SMX_W2(1, 1, 1); }
+    else return hipErrorInvalidValue;
+#undef SMX_W2
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_words(hipStream_t st, int fmt, int nw, int nchunks, const int2 *chunks,
