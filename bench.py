@@ -99,9 +99,9 @@ def full_sign_report(system, d_values, n_gpu, e_gpu):
 
 def kernel_name(kind, precision):
     """Product kernel of a launch kind (smx_get_launch_profile)."""
-    if kind in (0, 1, 4, 5, 6):
+    if kind in (0, 1, 4, 5, 6, 11):
         return "ns_f64_kernel"
-    if kind in (7, 8):
+    if kind in (7, 8, 10):
         return "ns_words256_kernel"
     return "ns_f32_kernel" if precision == "fp32" else "ns_words_kernel"
 
@@ -230,6 +230,10 @@ def main():
                     help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
     ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1],
                     help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch)")
+    ap.add_argument("--iteration", default="ns2", choices=["ns2", "pade3"],
+                    help="sign iteration of the timed path: second-order Newton-Schulz (two products per step) or "
+                         "third-order Pade (three products per step); the FP64 reference that fixes the flop "
+                         "numerator is always Newton-Schulz")
     ap.add_argument("--tile-shape", type=int, default=None, metavar="NPAD",
                     help="size bucket boundary of the word products: groups with n_pad >= NPAD on 256 x 256 "
                          "tiles (0: 128 x 128 only; default: the library's)")
@@ -282,7 +286,7 @@ def main():
         # the autotuner times whole evaluations of every candidate launch
         # configuration (launch order x step graphs x size bucket boundary) for
         # the timed precision and applies the fastest
-        ctx.configure(precision=args.precision, graph_steps=0)
+        ctx.configure(precision=args.precision, graph_steps=0, iteration=args.iteration)
         g, o, tms = smx.smx_autotune(ctx.handle, reps=2, use_cache=True)
         cfg = {"best_ms": tms, **smx.smx_get_launch_config(ctx.handle)}
         progress(f"autotune {args.precision}: {cfg}")
@@ -290,14 +294,16 @@ def main():
 
     # FP64 path first: the reference D and the iteration counts k_g of the
     # effective-TFLOP/s numerator (the same numerator for every precision)
-    if args.precision == "fp64" and not args.no_autotune:
+    timed_ref = args.precision == "fp64" and args.iteration == "ns2"
+    if timed_ref and not args.no_autotune:
         graph_steps, tuned = autotune()
-    r64 = run_path(smx, ctx, "fp64", args.steps if args.precision == "fp64" else 2, 1, d64,
-                   graph_steps if args.precision == "fp64" else 0)
+    smx.smx_set_iteration(ctx.handle, "ns2")
+    r64 = run_path(smx, ctx, "fp64", args.steps if timed_ref else 2, 1, d64, graph_steps if timed_ref else 0)
     algo = r64["stats"]["algo_flops"]
     run = r64
     d_out = d64
-    if args.precision != "fp64":
+    if not timed_ref:
+        smx.smx_set_iteration(ctx.handle, args.iteration)
         if not args.no_autotune:
             graph_steps, tuned = autotune()
         run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, graph_steps)
@@ -305,7 +311,8 @@ def main():
     backward = None
     if args.backward:
         # dE/dK through the frozen map of one evaluation in the timed precision
-        ctx.configure(precision=args.precision, graph_steps=0)
+        # (the adjoint differentiates the Newton-Schulz map)
+        ctx.configure(precision=args.precision, graph_steps=0, iteration="ns2")
         smx.smx_evaluate(ctx.handle)
         smx.smx_wait(ctx.handle)
         dk = torch.empty(ctx.nvalues, dtype=torch.float64, device="cuda")
@@ -348,7 +355,7 @@ def main():
         "time_share": kms / sum(v[0] for v in run["prof"].values()),
         "issued_mfma_tflops_all_products": stats["exec_flops"] / (stats["time_iterate_ms"] * 1e-3) / 1e12,
     }
-    diff_vs_fp64 = float((d_out - d64).abs().max().item()) if args.precision != "fp64" else 0.0
+    diff_vs_fp64 = float((d_out - d64).abs().max().item()) if not timed_ref else 0.0
 
     out = {
         "metric": METRIC,
@@ -366,6 +373,7 @@ def main():
         "config": {
             "workload": args.workload + ": " + WORKLOADS[args.workload],
             "precision": args.precision,
+            "iteration": args.iteration,
             "basis_functions": int(system.n),
             "submatrices": int(system.ngroups),
             "n_g_min_mean_max": [int(stats["n_min"]), round(stats["n_mean"], 1), int(stats["n_max"])],

@@ -77,6 +77,10 @@ extern "C" {
 #define SMX_FP16_2W   4   /* bulk products as 2-word FP16 splits (3 MFMA f16
                              products, FP32 accumulation), then FP64 polish     */
 
+/* ---- sign iterations (smx_set_iteration) --------------------------------- */
+#define SMX_ITER_NS2    0   /* second-order Newton-Schulz X (3I - X^2) / 2 (Sec. II-B)   */
+#define SMX_ITER_PADE3  1   /* third-order Pade X (15I - 10X^2 + 3X^4) / 8 (Sec. VI-A) */
+
 typedef struct smx_context *smx_ctx;
 
 typedef struct {
@@ -91,7 +95,8 @@ typedef struct {
     double  n_mean;           /* mean n_g                                         */
     double  iters_mean;
     double  resid_max;        /* max over groups of the last computed max|X^2 - I| */
-    double  algo_flops;       /* sum_g 4 n_g^3 k_g (two dense products per step)  */
+    double  algo_flops;       /* sum_g 2 n_g^3 x dense products: two per Newton-
+                                 Schulz step, three per Pade step                  */
     double  exec_flops;       /* flops issued to the matrix cores (padding, half
                                  tiles and multi-word products included)           */
     double  time_gather_ms;   /* device time of the last evaluation, per phase    */
@@ -148,6 +153,20 @@ int32_t smx_set_temperature(smx_ctx ctx, double kT);
 
 /* One of SMX_FP64, SMX_BF16_3W, SMX_BF16_1W, SMX_FP32, SMX_FP16_2W. */
 int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
+
+/*
+ * Sign iteration of the FP64 path and of the reduced-precision bulk:
+ * SMX_ITER_NS2 (default), X_{k+1} = X_k (3I - X_k^2) / 2, two products per
+ * step (Sec. II-B); or SMX_ITER_PADE3, X_{k+1} = X_k (15I - 10X_k^2 +
+ * 3X_k^4) / 8, the third-order Pade iteration of the paper's GPU runs (Sec.
+ * VI-A), three products per step (T = X^2, W = (15I - 10T + 3T^2) / 8,
+ * X W) with cubic convergence.  Same prescaling, stopping rules and
+ * reduced-precision switch; the FP64 polish of the reduced-precision modes
+ * stays Newton-Schulz.  Frozen evaluations, the mu search and the adjoint
+ * follow the Newton-Schulz map only (SMX_E_UNSUPPORTED after a Pade
+ * evaluation).
+ */
+int32_t smx_set_iteration(smx_ctx ctx, int32_t kind);
 
 /*
  * Stopping rule of the iteration: stop at the first k with
@@ -438,7 +457,9 @@ int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
  * every group the launch works on, i.e. one dense n_g x n_g product), and
  * its kind: 0/1 FP64 square/update, 2/3 reduced-precision square/update on
  * 128 x 128 tiles, 4/5 FP64 polish square/update, 6 mu tangent, 7/8
- * reduced-precision square/update on 256 x 256 tiles.  Writes min(cap, count) entries to the host
+ * reduced-precision square/update on 256 x 256 tiles, 9/10 reduced-precision
+ * Pade combine on 128 x 128 / 256 x 256 tiles, 11 FP64 Pade combine (the Pade
+ * square shares the square's kind).  Writes min(cap, count) entries to the host
  * arrays (any may be NULL) and the launch count to *count.  Synchronises.
  */
 int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,

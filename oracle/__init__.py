@@ -212,6 +212,16 @@ def ns_poly(x, k):
     return x
 
 
+def pade_poly(x, k):
+    """k steps of the third-order Pade sign map p(x) = x (15 - 10 x^2 + 3 x^4) / 8
+    (Sec. VI-A) applied to scalars."""
+    x = np.asarray(x, dtype=np.float64).copy()
+    for _ in range(int(k)):
+        x2 = x * x
+        x = x * (15.0 - 10.0 * x2 + 3.0 * x2 * x2) / 8.0
+    return x
+
+
 def ns_poly_deriv(x, k):
     """p_k'(x) by the chain rule through the k steps: prod (3/2)(1 - x_i^2)."""
     x = np.asarray(x, dtype=np.float64).copy()

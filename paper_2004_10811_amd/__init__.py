@@ -36,6 +36,10 @@ SMX_BF16_1W = 2
 SMX_FP32 = 3
 SMX_FP16_2W = 4
 
+SMX_ITER_NS2 = 0
+SMX_ITER_PADE3 = 1
+ITERATIONS = {"ns2": SMX_ITER_NS2, "pade3": SMX_ITER_PADE3}
+
 PRECISIONS = {"fp64": SMX_FP64, "bf16x3": SMX_BF16_3W, "bf16": SMX_BF16_1W, "fp32": SMX_FP32,
               "fp16x2": SMX_FP16_2W}
 
@@ -69,6 +73,7 @@ SIGNATURES = {
     "smx_set_tile_order": (_i32, [_vp, _i32]),
     "smx_set_kernel_variant": (_i32, [_vp, _i32]),
     "smx_set_tile_shape": (_i32, [_vp, _i32]),
+    "smx_set_iteration": (_i32, [_vp, _i32]),
     "smx_get_launch_config": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
     "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
@@ -232,6 +237,11 @@ def smx_set_tile_order(ctx, order=0):
 
 def smx_set_kernel_variant(ctx, variant=0):
     return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
+def smx_set_iteration(ctx, kind="ns2"):
+    k = ITERATIONS[kind] if isinstance(kind, str) else int(kind)
+    return _check(ctx, load_library().smx_set_iteration(ctx, k))
 
 
 def smx_set_tile_shape(ctx, big_min_npad=0):
@@ -436,8 +446,10 @@ class Context:
         return self
 
     def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
-                  mu=None, kT=None, workspace_limit=None, graph_steps=None, tile_shape=None):
+                  mu=None, kT=None, workspace_limit=None, graph_steps=None, tile_shape=None, iteration=None):
         smx_set_precision(self.handle, precision)
+        if iteration is not None:
+            smx_set_iteration(self.handle, iteration)
         if tile_shape is not None:
             smx_set_tile_shape(self.handle, tile_shape)
         if graph_steps is not None:

@@ -152,6 +152,7 @@ struct smx_context {
     // options
     double mu = 0.0, kT = 0.0;
     int32_t precision = SMX_FP64;
+    int32_t iteration = SMX_ITER_NS2;         // sign iteration of the FP64 path and the bulk (smx_set_iteration)
     double tol = 1e-12, switch_tol = 1e-3;
     int32_t max_iter = 100, n_polish = 2;
 
@@ -213,6 +214,7 @@ struct smx_context {
     bool evaluated = false;
     int32_t steps_launched = 0;
     int32_t last_precision = SMX_FP64;
+    int32_t last_iteration = SMX_ITER_NS2;
     int32_t last_stride = 0;
     int32_t last_polish = 0;             // FP64 polish steps after the bulk (0 in FP64 mode)
     int32_t last_max_iter = 0;
@@ -1136,6 +1138,15 @@ int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
     return SMX_OK;
 }
 
+int32_t smx_set_iteration(smx_ctx c, int32_t kind)
+{
+    if (!c) return SMX_E_INVALID;
+    if (kind != SMX_ITER_NS2 && kind != SMX_ITER_PADE3) return fail(c, SMX_E_INVALID, "unknown sign iteration");
+    if (kind != c->iteration) drop_graphs(c);
+    c->iteration = kind;
+    return SMX_OK;
+}
+
 int32_t smx_set_tile_shape(smx_ctx c, int32_t big_min_npad)
 {
     if (!c) return SMX_E_INVALID;
@@ -1181,6 +1192,7 @@ namespace {
 struct EvalMode {
     int fmt = -1, nw = 0;          // storage of the reduced-precision bulk (fmt < 0: FP64)
     bool mixed = false;
+    bool pade = false;             // third-order Pade steps (three products) instead of Newton-Schulz
     bool tangent = false;          // the mu tangent rides along (frozen step counts)
     int32_t stride = 0;            // residual / tau history slots per group
     int32_t kmax = 0;              // last bulk step
@@ -1199,7 +1211,10 @@ int32_t eval_mode(smx_ctx c, EvalMode &m)
     default: return fail(c, SMX_E_UNSUPPORTED, "precision mode not implemented on the GPU path");
     }
     m.mixed = m.fmt >= 0;
+    m.pade = c->iteration == SMX_ITER_PADE3;
     const bool frozen = c->use_kfix || c->use_sfix;
+    if (frozen && m.pade)
+        return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) follows the Newton-Schulz map only");
     if (frozen && m.mixed)
         return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) runs in SMX_FP64 only");
     if (m.mixed && c->max_iter <= c->n_polish)
@@ -1301,7 +1316,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
 {
     const int32_t ng = P.ngroups;
     const int32_t fmt = m.fmt, nw = m.nw;
-    const bool mixed = m.mixed, tangent = m.tangent;
+    const bool mixed = m.mixed, tangent = m.tangent, pade = m.pade;
     const int32_t stride = m.stride, kmax = m.kmax;
     const int32_t nwave = P.nwaves();
     hipStream_t st = c->stream;
@@ -1369,7 +1384,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         const std::vector<uint64_t> sig = {
             c->plan_gen, (uint64_t)c->precision, (uint64_t)c->max_iter, (uint64_t)c->n_polish,
             (uint64_t)c->graph_steps, (uint64_t)tangent, (uint64_t)c->use_sfix, (uint64_t)c->use_kfix,
-            (uint64_t)c->kernel_variant, (uint64_t)(uintptr_t)arena, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
+            (uint64_t)c->kernel_variant, (uint64_t)pade, (uint64_t)(uintptr_t)arena, (uint64_t)(uintptr_t)c->d_tx0.p, (uint64_t)(uintptr_t)c->d_tx1.p,
             (uint64_t)(uintptr_t)c->d_resid.p, (uint64_t)(uintptr_t)c->d_tdiag.p, (uint64_t)(uintptr_t)c->d_tau_hist.p,
             (uint64_t)(uintptr_t)c->d_sfix.p, (uint64_t)(uintptr_t)c->d_kfix.p,
             __builtin_bit_cast(uint64_t, c->tol), __builtin_bit_cast(uint64_t, c->switch_tol)};
@@ -1411,43 +1426,65 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         // each product launch; not inside a graph capture)
         auto step = [&](hipStream_t s, int32_t k, bool time_it) -> hipError_t {
             auto run = [&](int kind, auto &&launch) -> hipError_t { return time_it ? timed(kind, k, launch) : launch(); };
-            hipError_t e;
+            hipError_t e = hipSuccess;
+            // Newton-Schulz: square (W = 1.5 I - 0.5 X^2), update X W.  Pade:
+            // square (T = X^2, into the buffer X_{k+1} will take), combine
+            // (W = (15 I - 10 T + 3 T^2) / 8), update X W.
             if (!mixed) {
-                e = run(0, [&] { return launch_ns_f64(s, 0, ntiles, tl, V.gd, xb[k & 1], xb[k & 1], wslab, it, k,
-                                                      c->tol, c->max_iter, 0); });
+                if (!pade) {
+                    e = run(0, [&] { return launch_ns_f64(s, 0, ntiles, tl, V.gd, xb[k & 1], xb[k & 1], wslab, it, k,
+                                                          c->tol, c->max_iter, 0); });
+                } else {
+                    double *tt = xb[(k + 1) & 1];
+                    e = run(0, [&] { return launch_ns_f64(s, 5, ntiles, tl, V.gd, xb[k & 1], xb[k & 1], tt, it, k,
+                                                          c->tol, c->max_iter, 0); });
+                    if (e == hipSuccess)
+                        e = run(11, [&] { return launch_ns_f64(s, 6, ntiles, tl, V.gd, tt, tt, wslab, it, k, c->tol,
+                                                               c->max_iter, 0); });
+                }
                 if (e == hipSuccess)
                     e = run(1, [&] { return launch_ns_f64(s, 1, ntiles, tl, V.gd, xb[k & 1], wslab, xb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
                 if (e == hipSuccess && tangent)
                     e = run(6, [&] { return launch_ns_f64(s, 2, ntiles, tl, V.gd, tb[k & 1], wslab, tb[(k + 1) & 1],
                                                           it, k, c->tol, c->max_iter, 0); });
-            } else if (!buckets) {
-                e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, ntiles, tl, V.gd, wb[k & 1],
-                                                        wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
-                if (e == hipSuccess)
-                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, ntiles, tl, V.gd,
-                                                            wb[k & 1], wwp, wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
             } else {
-                // squares of both buckets, then their updates (a group's square
-                // always precedes its update; the groups are independent)
-                e = hipSuccess;
-                subset = 1;
-                if (nts > 0)
-                    e = run(2, [&] { return launch_ns_words(s, fmt, nw, 0, variant, nts, tls, V.gd, wb[k & 1],
-                                                            wb[k & 1], wwp, it, k, c->switch_tol, kmax); });
-                subset = 2;
-                if (e == hipSuccess && ntb > 0)
-                    e = run(7, [&] { return launch_ns_words256(s, fmt, nw, 0, ntb, tlb, V.gd, wb[k & 1], wb[k & 1],
-                                                               wwp, it, k, c->switch_tol, kmax); });
-                subset = 1;
-                if (e == hipSuccess && nts > 0)
-                    e = run(3, [&] { return launch_ns_words(s, fmt, nw, 1, variant, nts, tls, V.gd, wb[k & 1], wwp,
-                                                            wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
-                subset = 2;
-                if (e == hipSuccess && ntb > 0)
-                    e = run(8, [&] { return launch_ns_words256(s, fmt, nw, 1, ntb, tlb, V.gd, wb[k & 1], wwp,
-                                                               wb[(k + 1) & 1], it, k, c->switch_tol, kmax); });
-                subset = 0;
+                // one launch per size bucket and product (one bucket of all
+                // groups on 128 x 128 tiles when the mode has no 256 x 256 kernel)
+                struct Bucket {
+                    int n;
+                    const TileDesc *tl;
+                    bool big;
+                    int sub;
+                };
+                const Bucket bk[2] = {buckets ? Bucket{nts, tls, false, 1} : Bucket{ntiles, tl, false, 0},
+                                      Bucket{buckets ? ntb : 0, tlb, true, 2}};
+                unsigned short *tw = wb[(k + 1) & 1];
+                auto prod = [&](const Bucket &b, int mode, int kind128, int kind256, const unsigned short *x,
+                                const unsigned short *y, unsigned short *o) -> hipError_t {
+                    if (b.n <= 0) return hipSuccess;
+                    subset = b.sub;
+                    hipError_t r;
+                    if (b.big)
+                        r = run(kind256, [&] { return launch_ns_words256(s, fmt, nw, mode, b.n, b.tl, V.gd, x, y, o, it,
+                                                                         k, c->switch_tol, kmax); });
+                    else
+                        r = run(kind128, [&] { return launch_ns_words(s, fmt, nw, mode, mode <= 1 ? variant : 0, b.n,
+                                                                      b.tl, V.gd, x, y, o, it, k, c->switch_tol, kmax); });
+                    subset = 0;
+                    return r;
+                };
+                // squares of both buckets, then (Pade) their combines, then their
+                // updates: a group's products keep their order, and the groups
+                // are independent
+                for (const Bucket &b : bk)
+                    if (e == hipSuccess) e = pade ? prod(b, 2, 2, 7, wb[k & 1], wb[k & 1], tw)
+                                                  : prod(b, 0, 2, 7, wb[k & 1], wb[k & 1], wwp);
+                if (pade)
+                    for (const Bucket &b : bk)
+                        if (e == hipSuccess) e = prod(b, 3, 9, 10, tw, tw, wwp);
+                for (const Bucket &b : bk)
+                    if (e == hipSuccess) e = prod(b, 1, 3, 8, wb[k & 1], wwp, wb[(k + 1) & 1]);
             }
             return e;
         };
@@ -1518,6 +1555,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     if (events) HIP_TRY(c, hipEventRecord(c->ev_t3, st));
     c->steps_launched = launched;
     c->last_precision = c->precision;
+    c->last_iteration = c->iteration;
     c->last_stride = stride;
     c->last_polish = mixed ? c->n_polish : 0;
     c->last_fmt = fmt;
@@ -1836,8 +1874,11 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
         nsum += n[g];
         isum += it[g];
         s.resid_max = std::max(s.resid_max, rs[g]);
+        // dense products: two per Newton-Schulz step, three per Pade step (the
+        // polish of the reduced-precision modes is Newton-Schulz)
         const double nd = n[g];
-        s.algo_flops += 4.0 * nd * nd * nd * it[g];
+        const double ppb = c->last_iteration == SMX_ITER_PADE3 ? 3.0 : 2.0;
+        s.algo_flops += 2.0 * nd * nd * nd * (ppb * (it[g] - c->last_polish) + 2.0 * c->last_polish);
     }
     s.n_mean = ng ? nsum / ng : 0;
     s.iters_mean = ng ? isum / ng : 0;
@@ -1849,16 +1890,18 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
         if (c->last_precision == SMX_FP16_2W) npairs = 3;
         if (c->last_precision == SMX_BF16_3W) npairs = 6;
         const bool buckets = c->last_precision == SMX_FP16_2W || c->last_precision == SMX_BF16_1W;
+        const double ppb = c->last_iteration == SMX_ITER_PADE3 ? 3.0 : 2.0;
         for (int32_t g = 0; g < ng; g++) {
             const GroupDesc &d = P.gd[g];
             const double per = (buckets && P.big[g]) ? P.wtiles2[g] * 2.0 * 16 * 16 * d.npad
                                                      : P.wtiles[g] * 2.0 * 64 * 64 * d.npad;
             const double kb = it[g] - c->last_polish;     // bulk steps taken
+            // the last step's square (and Pade combine) precede the stopping decision
             if (c->last_polish == 0) {
-                exec += per * (2.0 * kb + 1.0);
+                exec += per * (ppb * kb + ppb - 1.0);
             } else {
                 // bulk word products, then 3^p - 1 thin FP64 products of the own-column polish
-                exec += per * npairs * (2.0 * kb + 1.0);
+                exec += per * npairs * (ppb * kb + ppb - 1.0);
                 exec += (std::pow(3.0, c->last_polish) - 1.0) * 2.0 * (double)d.n * d.n * d.m_own;
             }
         }
@@ -1915,7 +1958,8 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
                 if (sub == 1 && c->plan.big[g]) continue;     // the launch covers one size bucket
                 if (sub == 2 && !c->plan.big[g]) continue;
                 bool active = true;                           // polish launches work on every group
-                if (kd == 0 || kd == 2 || kd == 7) active = k <= kf[g];  // squares run up to the last step
+                if (kd == 0 || kd == 2 || kd == 7 || kd >= 9) active = k <= kf[g];   // squares (and Pade combines)
+                                                                                      // run up to the last step
                 if (kd == 1 || kd == 3 || kd == 6 || kd == 8) active = k < kf[g];   // updates (and tangents) stop one earlier
                 const double n = c->plan.gd[g].n;
                 if (active) f += 2.0 * n * n * n;
@@ -2003,6 +2047,8 @@ int32_t smx_set_frozen(smx_ctx c, int32_t on)
         return SMX_OK;
     }
     if (int32_t st = need_group_state(c)) return st;
+    if (c->last_iteration != SMX_ITER_NS2)
+        return fail(c, SMX_E_UNSUPPORTED, "the frozen map (derivatives, mu search) is the Newton-Schulz one");
     const int32_t ng = c->plan.ngroups;
     std::vector<int32_t> kf((size_t)ng);
     HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -2192,6 +2238,8 @@ int32_t smx_find_mu(smx_ctx c, double n_target, double tol, int32_t max_steps, d
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (!mu_out || !(tol > 0.0) || max_steps < 1) return fail(c, SMX_E_INVALID, "need mu_out, tol > 0, max_steps >= 1");
     if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "the mu search runs in SMX_FP64");
+    if (c->iteration != SMX_ITER_NS2)
+        return fail(c, SMX_E_UNSUPPORTED, "the mu search follows the frozen Newton-Schulz map");
     if (int32_t st = set_device(c)) return st;
     if (int32_t st = ensure_plan(c)) return st;
     const int32_t ng = c->plan.ngroups;
@@ -2300,6 +2348,8 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     if (!dK_out && !dmu_out) return fail(c, SMX_E_INVALID, "nothing to compute (dK_out and dmu_out are NULL)");
     if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
     if (int32_t st = need_group_state(c)) return st;
+    if (c->last_iteration != SMX_ITER_NS2)
+        return fail(c, SMX_E_UNSUPPORTED, "the adjoint differentiates the Newton-Schulz map");
     if (int32_t st = set_device(c)) return st;
     if (c->plan.nwaves() != 1)
         return fail(c, SMX_E_UNSUPPORTED, "the adjoint needs every submatrix resident at once (one wave); "

@@ -115,6 +115,8 @@ hipError_t launch_gather(hipStream_t st, int nchunks, const int2 *chunks, const 
 //         -1.5 Xb + Z + Z^T - 0.5 acc with Z = aux (= Xb W).
 // mode 4 (full tiles, plain product): out = x b with x symmetric (read by columns)
 //         and b general; every tile of the group is listed.
+// mode 5 (Pade square): T = a^2 X X stored, residual as mode 0.
+// mode 6 (Pade combine): out = (15 I - 10 x + 3 x x) / 8 with x = b = T.
 hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *tiles,
                          const GroupDesc *groups, const double *x, const double *b, double *out,
                          const IterState &it, int k, double tol, int max_iter, int polish,
@@ -152,6 +154,10 @@ __host__ __device__ inline int64_t word_pos(int nw, int ld, int r, int c)
 
 // Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value;
 // fmt 2 = one FP32 value per element, column-major like the FP64 slabs).
+// mode 0: Newton-Schulz square (W = 1.5 I - 0.5 X^2, residual, 1 - T_ii);
+// mode 1: update X_{k+1} = X W after the bulk stopping rule;
+// mode 2: Pade square (T = X^2 stored, residual, 1 - T_ii);
+// mode 3: Pade combine W = (15 I - 10 T + 3 T T) / 8 (x = b = T).
 // variant: operand stream of the word products (0: global_load_lds into LDS one
 // K step at a time; 1: next K step prefetched into registers); results are
 // bitwise the same.

@@ -8,6 +8,11 @@
 //   mode 1 ("update"): X_{k+1} = a X_k W, unless the step-k residual already
 //                      meets the stopping rule (then X_k is the result).
 // a = 1/s_g at k = 0 (Gershgorin prescaling folded into the first step), 1 after.
+// The third-order Pade iteration X_{k+1} = X_k (15I - 10X_k^2 + 3X_k^4) / 8
+// (Sec. VI-A) takes three products per step:
+//   mode 5 ("Pade square"):  T = a^2 X_k X_k and its residual, as mode 0, T stored;
+//   mode 6 ("Pade combine"): W = (15 I - 10 T + 3 T T) / 8 (T read at the output position);
+//   mode 1 ("update") as above.
 //
 // Every iterate is a polynomial in the symmetric A_g, so X, T and W are
 // symmetric and X W = W X.  Each workgroup therefore computes one
@@ -54,13 +59,15 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const int g = td.x;
     if (g < 0) return;                            // idle slot of the launch order
     if (it.kact >= 0 && it.kfix && it.kact >= it.kfix[g]) return;   // group not in this adjoint step
-    if (!polish && MODE <= 2 && it.done[g]) return;                 // finished at an earlier step
+    if (!polish && (MODE <= 2 || MODE >= 5) && it.done[g]) return;  // finished at an earlier step
     const int ti = td.y >> 16, tj = td.y & 0xffff;
     const GroupDesc gd = groups[g];
     const int ld = gd.npad;
 
+    // the prescaling enters the products that read X_0: squares and the update
+    constexpr bool reads_x0 = MODE < 2 || MODE == 5;
     double a = 1.0;
-    if (k == 0 && !polish && MODE < 2) {
+    if (k == 0 && !polish && reads_x0) {
         const double s = __longlong_as_double((long long)it.scale_bits[g]);
         a = s > 0.0 ? 1.0 / s : 0.0;
     }
@@ -172,7 +179,7 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     // I (a scaled padding entry 1/s_g would leave [-1, 1] when s_g < 1 and
     // grow without bound).  The padding never mixes with the true block, so
     // setting it after the product is exact.
-    const bool pad_fix = (k == 0 && !polish && MODE < 2);
+    const bool pad_fix = (k == 0 && !polish && reads_x0);
     double rmax = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
@@ -183,14 +190,19 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             for (int v = 0; v < 4; v++) {
                 const int r = row_w + i * 16 + (lane >> 4) + 4 * v;
                 double val;
-                if (MODE == 0) {
+                if (MODE == 0 || MODE == 5) {
                     const double t = a * a * acc[i][j][v];
                     if (r < n && c < n) {
                         double d = fabs(t - (r == c ? 1.0 : 0.0));
                         if (!(d <= 1.7976931348623157e308)) d = __builtin_huge_val();
                         rmax = fmax(rmax, d);
                     }
-                    val = -0.5 * t + (r == c ? 1.5 : 0.0);
+                    val = MODE == 0 ? -0.5 * t + (r == c ? 1.5 : 0.0) : t;
+                } else if (MODE == 6) {
+                    // W = (15 I - 10 T + 3 T^2) / 8, T = x at this position
+                    val = (r < ld && c < ld)
+                              ? 0.125 * ((r == c ? 15.0 : 0.0) - 10.0 * xin[gd.off + r + (int64_t)c * ld] + 3.0 * acc[i][j][v])
+                              : 0.0;
                 } else if (MODE == 1) {
                     val = a * acc[i][j][v];
                 } else if (MODE == 2) {
@@ -217,7 +229,7 @@ void ns_f64_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             }
         }
     }
-    if (MODE == 0) {
+    if (MODE == 0 || MODE == 5) {
         rmax = wave_max(rmax);
         if (lane == 0) {
             unsigned long long *slot = it.resid_bits + (int64_t)g * it.resid_stride + k;
@@ -242,6 +254,8 @@ hipError_t launch_ns_f64(hipStream_t st, int mode, int ntiles, const TileDesc *t
     case 2: SMX_NS_LAUNCH(2); break;
     case 3: SMX_NS_LAUNCH(3); break;
     case 4: SMX_NS_LAUNCH(4); break;
+    case 5: SMX_NS_LAUNCH(5); break;
+    case 6: SMX_NS_LAUNCH(6); break;
     default: return hipErrorInvalidValue;
     }
 #undef SMX_NS_LAUNCH

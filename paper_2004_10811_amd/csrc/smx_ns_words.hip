@@ -206,6 +206,38 @@ __device__ inline void split8(const float *v, u16x8 *wv)
     }
 }
 
+// Eight consecutive entries (rows r0 .. r0 + 7, r0 a multiple of 8) of column
+// c of a word-stored matrix, unscaled, in FP32 (the sum of the words is exact
+// there): the T that the combine of the third-order Pade step reads at its
+// output positions.
+template <int FMT, int NW>
+__device__ inline void load8_words(const unsigned short *__restrict__ m, int ld, int r0, int c, float *v)
+{
+    const unsigned short *p = m + word_pos(NW, ld, r0, c);
+    u16x8 w[NW];
+#pragma unroll
+    for (int q = 0; q < NW; q++) w[q] = *reinterpret_cast<const u16x8 *>(p + 32 * q);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        float s = 0.f;
+#pragma unroll
+        for (int q = NW - 1; q >= 0; q--) s += from_word_f<FMT>(w[q][e]);
+        v[e] = s * (float)(1.0 / word_scale<FMT>());
+    }
+}
+
+// Output value of a product t at (r, c): MODE 0 (Newton-Schulz square)
+// W = 1.5 I - 0.5 T; MODE 1 (update) and MODE 2 (Pade square) the product
+// itself; MODE 3 (Pade combine, t = (T T)_rc, tv = T_rc)
+// W = (15 I - 10 T + 3 T^2) / 8.
+template <int MODE>
+__device__ inline float out_value(float t, float tv, int r, int c)
+{
+    if constexpr (MODE == 0) return -0.5f * t + (r == c ? 1.5f : 0.f);
+    else if constexpr (MODE == 3) return 0.125f * ((r == c ? 15.f : 0.f) - 10.f * tv + 3.f * t);
+    else return t;
+}
+
 // Operands go straight from global memory into LDS (global_load_lds_dwordx4,
 // no register staging) in K steps of 32: per operand and word a
 // [128 columns][32] halves region, 64 B per column, whose four 16-B chunks are
@@ -417,9 +449,6 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
     const bool diag = (ti == tj);
     unsigned short *og = out + NW * gd.off;
     float rmax = 0.f;
-    auto value = [&](float t, int r, int c) -> float {
-        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
-    };
     if constexpr (NW <= 2) {
         // One conversion per element: the pass over the tile's own positions
         // splits every staged value into its words and writes them back in
@@ -454,17 +483,19 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
                 const f4 fb = *reinterpret_cast<const f4 *>(Cs + (sw ? p0 : p1));
                 const f4 lo = sw ? fb : fa, hi = sw ? fa : fb;
                 float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                float tv[8] = {};
+                if constexpr (MODE == 3) load8_words<FMT, NW>(xin + NW * gd.off, ld, r0, c, tv);
 #pragma unroll
                 for (int e = 0; e < 8; e++) {
                     const int r = r0 + e;
                     const float t = v[e] * inv_s2;
-                    if (MODE == 0 && r < n && c < n && r >= c) {
+                    if ((MODE == 0 || MODE == 2) && r < n && c < n && r >= c) {
                         float d = fabsf(t - (r == c ? 1.f : 0.f));
                         if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                         rmax = fmaxf(rmax, d);
                         if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                     }
-                    v[e] = value(t, r, c) * sc;
+                    v[e] = out_value<MODE>(t, tv[e], r, c) * sc;
                 }
                 u16x8 wv[NW];
                 split8<FMT, NW>(v, wv);
@@ -531,17 +562,19 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (diag && r0 + 7 < c) continue;
             float v[8];
             load8(&Cs[cl * CST + rc * 8], rc & 4, v);
+            float tv[8] = {};
+            if constexpr (MODE == 3) load8_words<FMT, NW>(xin + NW * gd.off, ld, r0, c, tv);
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int r = r0 + e;
                 const float t = v[e] * inv_s2;
-                if (MODE == 0 && r < n && c < n && r >= c) {
+                if ((MODE == 0 || MODE == 2) && r < n && c < n && r >= c) {
                     float d = fabsf(t - (r == c ? 1.f : 0.f));
                     if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                     rmax = fmaxf(rmax, d);
                     if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                 }
-                v[e] = value(t, r, c) * sc;
+                v[e] = out_value<MODE>(t, tv[e], r, c) * sc;
             }
             u16x8 wv[NW];
             split8<FMT, NW>(v, wv);
@@ -572,8 +605,10 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
             if (diag && c0 >= r) continue;
             float v[8];
             load8(&Cs[rl * CSTH + cc * 8], cc & 4, v);
+            float tv[8] = {};     // T is symmetric: T_{r, c0 + e} from column r
+            if constexpr (MODE == 3) load8_words<FMT, NW>(xin + NW * gd.off, ld, c0, r, tv);
 #pragma unroll
-            for (int e = 0; e < 8; e++) v[e] = value(v[e] * inv_s2, r, c0 + e) * sc;
+            for (int e = 0; e < 8; e++) v[e] = out_value<MODE>(v[e] * inv_s2, tv[e], r, c0 + e) * sc;
             u16x8 wv[NW];
             split8<FMT, NW>(v, wv);
             if (!diag || c0 + 8 <= r) {
@@ -589,7 +624,7 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         __syncthreads();
     }
 
-    if (MODE == 0) {
+    if (MODE == 0 || MODE == 2) {
         double rm = (double)rmax;
         rm = wave_max(rm);
         if (lane == 0)
@@ -760,9 +795,6 @@ void ns_words256_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__r
     const int n = gd.n;
     unsigned short *og = out + NW * gd.off;
     float rmax = 0.f;
-    auto value = [&](float t, int r, int c) -> float {
-        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
-    };
     auto cpos = [](int col, int row) { return col * CST2 + (row ^ (((col >> 3) & 7) << 2)); };
     unsigned int *Cw = reinterpret_cast<unsigned int *>(Cs);
 #pragma unroll
@@ -790,17 +822,19 @@ void ns_words256_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__r
             const f4 fb = *reinterpret_cast<const f4 *>(Cs + (sw ? p0 : p1));
             const f4 lo = sw ? fb : fa, hi = sw ? fa : fb;
             float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            float tv[8] = {};
+            if constexpr (MODE == 3) load8_words<FMT, NW>(xin + NW * gd.off, ld, r0, c, tv);
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int r = r0 + e;
                 const float t = v[e] * inv_s2;
-                if (MODE == 0 && r < n && c < n && r >= c) {
+                if ((MODE == 0 || MODE == 2) && r < n && c < n && r >= c) {
                     float d = fabsf(t - (r == c ? 1.f : 0.f));
                     if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                     rmax = fmaxf(rmax, d);
                     if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                 }
-                v[e] = value(t, r, c) * sc;
+                v[e] = out_value<MODE>(t, tv[e], r, c) * sc;
             }
             u16x8 wv[NW];
             split8<FMT, NW>(v, wv);
@@ -847,7 +881,7 @@ void ns_words256_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__r
         __syncthreads();                            // staging is free for the next quarter
     }
 
-    if (MODE == 0) {
+    if (MODE == 0 || MODE == 2) {
         double rm = (double)rmax;
         rm = wave_max(rm);
         if (lane == 0)
@@ -966,9 +1000,6 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
     const bool diag = (ti == tj);
     float *og = out + gd.off;
     float rmax = 0.f;
-    auto value = [&](float t, int r, int c) -> float {
-        return MODE == 0 ? (-0.5f * t + (r == c ? 1.5f : 0.f)) : t;
-    };
     for (int h = 0; h < 2; h++) {
         if (wave_live && wc == h) {
 #pragma unroll
@@ -993,13 +1024,13 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             for (int e = 0; e < 8; e++) {
                 const int r = r0 + e;
                 const float t = v[e];
-                if (MODE == 0 && r < n && c < n && r >= c) {
+                if ((MODE == 0 || MODE == 2) && r < n && c < n && r >= c) {
                     float d = fabsf(t - (r == c ? 1.f : 0.f));
                     if (!(d <= 3.4e38f)) d = __builtin_huge_valf();
                     rmax = fmaxf(rmax, d);
                     if (r == c) it.tdiag[gd.rinfo_off + r] = 1.0 - (double)t;
                 }
-                v[e] = value(t, r, c);
+                v[e] = out_value<MODE>(t, MODE == 3 ? xin[gd.off + r + (int64_t)c * ld] : 0.f, r, c);
             }
             *reinterpret_cast<f4 *>(og + r0 + (int64_t)c * ld) = f4{v[0], v[1], v[2], v[3]};
             *reinterpret_cast<f4 *>(og + r0 + 4 + (int64_t)c * ld) = f4{v[4], v[5], v[6], v[7]};
@@ -1028,7 +1059,7 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
             float v[8];
             load8(&Cs[rl * CSTH + cc * 8], cc & 4, v);
 #pragma unroll
-            for (int e = 0; e < 8; e++) v[e] = value(v[e], r, c0 + e);
+            for (int e = 0; e < 8; e++) v[e] = out_value<MODE>(v[e], MODE == 3 ? xin[gd.off + c0 + e + (int64_t)r * ld] : 0.f, r, c0 + e);
             if (!diag || c0 + 8 <= r) {
                 *reinterpret_cast<f4 *>(og + c0 + (int64_t)r * ld) = f4{v[0], v[1], v[2], v[3]};
                 *reinterpret_cast<f4 *>(og + c0 + 4 + (int64_t)r * ld) = f4{v[4], v[5], v[6], v[7]};
@@ -1039,7 +1070,7 @@ void ns_f32_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restri
         __syncthreads();
     }
 
-    if (MODE == 0) {
+    if (MODE == 0 || MODE == 2) {
         double rm = (double)rmax;
         rm = wave_max(rm);
         if (lane == 0)
@@ -1148,10 +1179,14 @@ hipError_t launch_words_t(hipStream_t st, int mode, int variant, int ntiles, con
 {
 #define SMX_WK(M, R) hipLaunchKernelGGL((ns_words_kernel<FMT, NW, M, R>), dim3(ntiles), dim3(256), 0, st, tiles, \
                                         groups, x, b, out, it, k, switch_tol, kmax)
-    if (mode == 0) {
-        if (variant == 1) SMX_WK(0, 1); else SMX_WK(0, 0);
-    } else {
-        if (variant == 1) SMX_WK(1, 1); else SMX_WK(1, 0);
+    // the register-prefetch stream serves the Newton-Schulz products; the
+    // Pade products always use the direct stream
+    switch (mode) {
+    case 0: if (variant == 1) SMX_WK(0, 1); else SMX_WK(0, 0); break;
+    case 1: if (variant == 1) SMX_WK(1, 1); else SMX_WK(1, 0); break;
+    case 2: SMX_WK(2, 0); break;
+    case 3: SMX_WK(3, 0); break;
+    default: return hipErrorInvalidValue;
     }
 #undef SMX_WK
     return hipGetLastError();
@@ -1167,12 +1202,16 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int varian
     if (fmt == 2) {
         const float *xf = reinterpret_cast<const float *>(x), *bf = reinterpret_cast<const float *>(b);
         float *of = reinterpret_cast<float *>(out);
-        if (mode == 0)
-            hipLaunchKernelGGL(ns_f32_kernel<0>, dim3(ntiles), dim3(256), 0, st, tiles, groups, xf, bf, of, it, k,
-                               switch_tol, kmax);
-        else
-            hipLaunchKernelGGL(ns_f32_kernel<1>, dim3(ntiles), dim3(256), 0, st, tiles, groups, xf, bf, of, it, k,
-                               switch_tol, kmax);
+#define SMX_F32(M) hipLaunchKernelGGL(ns_f32_kernel<M>, dim3(ntiles), dim3(256), 0, st, tiles, groups, xf, bf, of, it, \
+                                      k, switch_tol, kmax)
+        switch (mode) {
+        case 0: SMX_F32(0); break;
+        case 1: SMX_F32(1); break;
+        case 2: SMX_F32(2); break;
+        case 3: SMX_F32(3); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef SMX_F32
         return hipGetLastError();
     }
     if (fmt == 0 && nw == 1) return launch_words_t<0, 1>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
@@ -1189,10 +1228,18 @@ hipError_t launch_ns_words256(hipStream_t st, int fmt, int nw, int mode, int nti
     if (ntiles <= 0) return hipSuccess;
 #define SMX_W2(F, N, M) hipLaunchKernelGGL((ns_words256_kernel<F, N, M>), dim3(ntiles), dim3(512), 0, st, tiles, \
                                            groups, x, b, out, it, k, switch_tol, kmax)
-    if (fmt == 0 && nw == 2) { if (mode == 0) SMX_W2(0, 2, 0); else SMX_W2(0, 2, 1); }
-    else if (fmt == 0 && nw == 1) { if (mode == 0) SMX_W2(0, 1, 0); else SMX_W2(0, 1, 1); }
-    else if (fmt == 1 && nw == 1) { if (mode == 0) SMX_W2(1, 1, 0); else SMX_W2(1, 1, 1); }
+#define SMX_W2M(F, N) switch (mode) {                                           \
+        case 0: SMX_W2(F, N, 0); break;                                             \
+        case 1: SMX_W2(F, N, 1); break;                                             \
+        case 2: SMX_W2(F, N, 2); break;                                             \
+        case 3: SMX_W2(F, N, 3); break;                                             \
+        default: return hipErrorInvalidValue;                                       \
+        }
+    if (fmt == 0 && nw == 2) { SMX_W2M(0, 2) }
+    else if (fmt == 0 && nw == 1) { SMX_W2M(0, 1) }
+    else if (fmt == 1 && nw == 1) { SMX_W2M(1, 1) }
     else return hipErrorInvalidValue;
+#undef SMX_W2M
 #undef SMX_W2
     return hipGetLastError();
 }
