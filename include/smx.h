@@ -77,6 +77,10 @@ extern "C" {
 #define SMX_FP16_2W   4   /* bulk products as 2-word FP16 splits (3 MFMA f16
                              products, FP32 accumulation), then FP64 polish     */
 
+/* ---- solvers (smx_set_solver) --------------------------------------------- */
+#define SMX_SOLVER_ITERATIVE 0   /* sign by Newton-Schulz / Pade products (kT = 0 only) */
+#define SMX_SOLVER_EIG       1   /* diagonalisation of every submatrix (Sec. IV-F)     */
+
 /* ---- sign iterations (smx_set_iteration) --------------------------------- */
 #define SMX_ITER_NS2    0   /* second-order Newton-Schulz X (3I - X^2) / 2 (Sec. II-B)   */
 #define SMX_ITER_PADE3  1   /* third-order Pade X (15I - 10X^2 + 3X^4) / 8 (Sec. VI-A) */
@@ -147,9 +151,28 @@ int32_t smx_set_groups(smx_ctx ctx, int32_t ngroups, const int32_t *grp_ptr,
 /* Chemical potential mu (Hartree) of D = (I - sign(K - mu I)) / 2. */
 int32_t smx_set_mu(smx_ctx ctx, double mu);
 
-/* Electronic temperature kT in Hartree.  Only kT == 0 (the sign function) is
- * implemented on the GPU; kT > 0 makes smx_evaluate return SMX_E_UNSUPPORTED. */
+/* Electronic temperature kT in Hartree.  kT = 0: D = (I - sign(K - mu I)) / 2.
+ * kT > 0: D_g = Q f(Lambda) Q^T with the Fermi function f(x) = 1 / (1 +
+ * exp(x / kT)) of the eigenvalues of K_sub - mu I (Sec. IV-F); the
+ * evaluation then diagonalises every submatrix (see smx_set_solver). */
 int32_t smx_set_temperature(smx_ctx ctx, double kT);
+
+/*
+ * Solver of the submatrix function.  SMX_SOLVER_ITERATIVE (default): the
+ * sign by matrix products (smx_set_iteration, smx_set_precision); needs
+ * kT = 0.  SMX_SOLVER_EIG: diagonalisation of every submatrix, the paper's
+ * production path (Sec. IV-F), at any kT, in FP64: Householder reduction to
+ * tridiagonal form (one workgroup per submatrix), eigenvalues by bisection on
+ * Sturm counts, eigenvectors by twisted factorisations (clusters of
+ * eigenvalues closer than 1e-8 ||T|| by inverse iteration with
+ * orthogonalisation), then only the own columns of D, as
+ * Q diag(f) Q^T E through thin products.  At kT = 0 an eigenvalue with
+ * |lambda - mu| <= 1e-14 ||A_g||_inf gets weight 1/2 (Eq. signevext).  kT > 0
+ * always uses this path.  Limit: n_g <= 3072 (SMX_E_UNSUPPORTED beyond).
+ * Iteration histories, the frozen map, the
+ * adjoint and smx_evaluate_static do not apply to it.
+ */
+int32_t smx_set_solver(smx_ctx ctx, int32_t solver);
 
 /* One of SMX_FP64, SMX_BF16_3W, SMX_BF16_1W, SMX_FP32, SMX_FP16_2W. */
 int32_t smx_set_precision(smx_ctx ctx, int32_t mode);
@@ -426,6 +449,31 @@ int32_t smx_dn_dmu(smx_ctx ctx, double *out);
  */
 int32_t smx_find_mu(smx_ctx ctx, double n_target, double tol, int32_t max_steps,
                     double *mu_out, int32_t *steps_out);
+
+/*
+ * Chemical potential by the paper's Algorithm 1 (Sec. IV-G): every submatrix
+ * is diagonalised once at the current mu (as SMX_SOLVER_EIG, at the current
+ * kT), which gives its eigenvalues lambda_gl and weights w_gl = sum over the
+ * own columns c of Q_cl^2; then N(mu) = sum_g sum_l w_gl f(lambda_gl - mu)
+ * (monotone in mu) is bisected without solving again, 128 trial values per
+ * step inside the bracket of K's Gershgorin interval (widened by 40 kT),
+ * until |N - n_target| <= tol or max_steps steps.  D, N and E are then formed
+ * at mu_out from the stored decompositions (with more than one wave, by a new
+ * evaluation at mu_out), and the context is left at mu_out.  *steps_out
+ * (nullable) = bisection steps.  At kT = 0 N(mu) is a staircase and may step
+ * over n_target: SMX_E_NOT_CONVERGED (mu_out at the step, D still formed).
+ */
+int32_t smx_find_mu_eig(smx_ctx ctx, double n_target, double tol, int32_t max_steps,
+                        double *mu_out, int32_t *steps_out);
+
+/*
+ * Spectrum of the last diagonalisation (smx_evaluate with SMX_SOLVER_EIG or
+ * kT > 0, or smx_find_mu_eig): for every group g in order, its n_g
+ * eigenvalues of K[R(g), R(g)] (no shift; ascending within each unreduced
+ * block of the tridiagonal form) and Algorithm 1's weights w_gl.  Host arrays
+ * of sum_g n_g entries, each nullable.  Synchronises.
+ */
+int32_t smx_get_spectrum(smx_ctx ctx, double *lam, double *w);
 
 /*
  * Reverse-mode derivative of L = gE E + gN N + <gD, D> (gD nullable, K's

@@ -36,6 +36,9 @@ SMX_BF16_1W = 2
 SMX_FP32 = 3
 SMX_FP16_2W = 4
 
+SMX_SOLVER_ITERATIVE = 0
+SMX_SOLVER_EIG = 1
+
 SMX_ITER_NS2 = 0
 SMX_ITER_PADE3 = 1
 ITERATIONS = {"ns2": SMX_ITER_NS2, "pade3": SMX_ITER_PADE3}
@@ -74,6 +77,9 @@ SIGNATURES = {
     "smx_set_kernel_variant": (_i32, [_vp, _i32]),
     "smx_set_tile_shape": (_i32, [_vp, _i32]),
     "smx_set_iteration": (_i32, [_vp, _i32]),
+    "smx_set_solver": (_i32, [_vp, _i32]),
+    "smx_find_mu_eig": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
+    "smx_get_spectrum": (_i32, [_vp, _vp, _vp]),
     "smx_get_launch_config": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
     "smx_autotune": (_i32, [_vp, _i32, _i32, _P(_i32), _P(_i32), _P(_f64)]),
     "smx_evaluate": (_i32, [_vp]),
@@ -237,6 +243,32 @@ def smx_set_tile_order(ctx, order=0):
 
 def smx_set_kernel_variant(ctx, variant=0):
     return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
+def smx_set_solver(ctx, solver="iterative"):
+    k = {"iterative": SMX_SOLVER_ITERATIVE, "eig": SMX_SOLVER_EIG}[solver] if isinstance(solver, str) else int(solver)
+    return _check(ctx, load_library().smx_set_solver(ctx, k))
+
+
+def smx_find_mu_eig(ctx, n_target: float, tol: float = 1e-8, max_steps: int = 20, allow_not_converged=False):
+    """(mu, bisection steps, status): Algorithm 1 on the stored decompositions."""
+    mu, steps = _f64(), _i32()
+    st = load_library().smx_find_mu_eig(ctx, float(n_target), float(tol), int(max_steps), ctypes.byref(mu),
+                                        ctypes.byref(steps))
+    if not (allow_not_converged and st == SMX_E_NOT_CONVERGED):
+        _check(ctx, st)
+    return mu.value, steps.value, st
+
+
+def smx_get_spectrum(ctx):
+    """(eigenvalues, weights) of every group's submatrix, concatenated by group."""
+    ng, _ = smx_get_sizes(ctx)
+    info = smx_get_group_info(ctx)
+    tot = int(info["n"].sum())
+    lam = np.zeros(tot)
+    w = np.zeros(tot)
+    _check(ctx, load_library().smx_get_spectrum(ctx, lam.ctypes.data, w.ctypes.data))
+    return lam, w
 
 
 def smx_set_iteration(ctx, kind="ns2"):
@@ -446,8 +478,11 @@ class Context:
         return self
 
     def configure(self, precision="fp64", tol=1e-12, max_iter=100, n_polish=2, switch_tol=1e-3,
-                  mu=None, kT=None, workspace_limit=None, graph_steps=None, tile_shape=None, iteration=None):
+                  mu=None, kT=None, workspace_limit=None, graph_steps=None, tile_shape=None, iteration=None,
+                  solver=None):
         smx_set_precision(self.handle, precision)
+        if solver is not None:
+            smx_set_solver(self.handle, solver)
         if iteration is not None:
             smx_set_iteration(self.handle, iteration)
         if tile_shape is not None:

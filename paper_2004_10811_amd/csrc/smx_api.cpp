@@ -153,6 +153,7 @@ struct smx_context {
     double mu = 0.0, kT = 0.0;
     int32_t precision = SMX_FP64;
     int32_t iteration = SMX_ITER_NS2;         // sign iteration of the FP64 path and the bulk (smx_set_iteration)
+    int32_t solver = SMX_SOLVER_ITERATIVE;    // smx_set_solver; kT > 0 always diagonalises
     double tol = 1e-12, switch_tol = 1e-3;
     int32_t max_iter = 100, n_polish = 2;
 
@@ -188,6 +189,9 @@ struct smx_context {
     DevBuf<int32_t> d_kfix;
     DevBuf<unsigned long long> d_sfix, d_scale_scratch;
     DevBuf<double> d_tx0, d_tx1, d_dnp, d_dn;    // mu tangent of the iterates, its reduction
+    // eigensolver (finite temperature, Algorithm 1): per-row arrays indexed like the row tables
+    DevBuf<double> d_ed, d_ee, d_etau, d_elam, d_elabs, d_ew, d_mus, d_npart, d_nval;
+    DevBuf<int32_t> d_ebs, d_ebe;
     // adjoint
     DevBuf<TileDesc> d_tiles_full;
     DevBuf<int64_t> d_cptr;
@@ -215,6 +219,8 @@ struct smx_context {
     int32_t steps_launched = 0;
     int32_t last_precision = SMX_FP64;
     int32_t last_iteration = SMX_ITER_NS2;
+    bool last_eig = false;                     // last evaluation diagonalised the submatrices
+    double last_kT = 0.0;
     int32_t last_stride = 0;
     int32_t last_polish = 0;             // FP64 polish steps after the bulk (0 in FP64 mode)
     int32_t last_max_iter = 0;
@@ -934,6 +940,11 @@ int32_t smx_destroy(smx_ctx c)
     c->d_dk.release();
     c->d_dmu.release();
     c->d_tpool.release();
+    for (auto *b : {&c->d_ed, &c->d_ee, &c->d_etau, &c->d_elam, &c->d_elabs, &c->d_ew, &c->d_mus, &c->d_npart,
+                    &c->d_nval})
+        b->release();
+    c->d_ebs.release();
+    c->d_ebe.release();
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_ndone) (void)hipHostFree(c->h_ndone);
@@ -1138,6 +1149,14 @@ int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
     return SMX_OK;
 }
 
+int32_t smx_set_solver(smx_ctx c, int32_t solver)
+{
+    if (!c) return SMX_E_INVALID;
+    if (solver != SMX_SOLVER_ITERATIVE && solver != SMX_SOLVER_EIG) return fail(c, SMX_E_INVALID, "unknown solver");
+    c->solver = solver;
+    return SMX_OK;
+}
+
 int32_t smx_set_iteration(smx_ctx c, int32_t kind)
 {
     if (!c) return SMX_E_INVALID;
@@ -1193,6 +1212,7 @@ struct EvalMode {
     int fmt = -1, nw = 0;          // storage of the reduced-precision bulk (fmt < 0: FP64)
     bool mixed = false;
     bool pade = false;             // third-order Pade steps (three products) instead of Newton-Schulz
+    bool eig = false;              // diagonalisation path (kT > 0, or SMX_SOLVER_EIG)
     bool tangent = false;          // the mu tangent rides along (frozen step counts)
     int32_t stride = 0;            // residual / tau history slots per group
     int32_t kmax = 0;              // last bulk step
@@ -1201,7 +1221,15 @@ struct EvalMode {
 int32_t eval_mode(smx_ctx c, EvalMode &m)
 {
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
-    if (c->kT > 0.0) return fail(c, SMX_E_UNSUPPORTED, "finite temperature (kT > 0) is not implemented on the GPU path");
+    m.eig = c->kT > 0.0 || c->solver == SMX_SOLVER_EIG;
+    if (m.eig) {
+        if (c->precision != SMX_FP64)
+            return fail(c, SMX_E_UNSUPPORTED, "the diagonalisation path (kT > 0 or SMX_SOLVER_EIG) runs in SMX_FP64");
+        if (c->use_kfix || c->use_sfix)
+            return fail(c, SMX_E_UNSUPPORTED, "frozen iteration (derivatives, mu search) follows the Newton-Schulz map");
+        m.stride = c->max_iter + 2 + c->n_polish;
+        return SMX_OK;
+    }
     switch (c->precision) {
     case SMX_FP64: break;
     case SMX_FP16_2W: m.fmt = 0; m.nw = 2; break;
@@ -1258,6 +1286,15 @@ int32_t eval_prepare(smx_ctx c, const EvalMode &m)
         c->ev_wave.push_back(ev);
     }
     if (c->use_sfix) HIP_TRY(c, c->d_scale_scratch.ensure((size_t)std::max(ng, 1)));
+    if (m.eig) {
+        if (P.max_npad > kEigMaxN)
+            return fail(c, SMX_E_UNSUPPORTED, "the diagonalisation path takes submatrices up to n = " +
+                                                  std::to_string(kEigMaxN));
+        const size_t nr = std::max<size_t>(P.rinfo.size(), 1);
+        for (auto *b : {&c->d_ed, &c->d_ee, &c->d_etau, &c->d_elam, &c->d_elabs, &c->d_ew}) HIP_TRY(c, b->ensure(nr));
+        HIP_TRY(c, c->d_ebs.ensure(nr));
+        HIP_TRY(c, c->d_ebe.ensure(nr));
+    }
     if (m.tangent) {
         HIP_TRY(c, c->d_tx0.ensure((size_t)P.work_elems));
         HIP_TRY(c, c->d_tx1.ensure((size_t)P.work_elems));
@@ -1562,10 +1599,108 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     c->last_nw = nw;
     c->last_max_iter = c->max_iter;
     c->last_mu = c->mu;
+    c->last_eig = false;
+    c->last_kT = 0.0;
     c->evaluated = true;
     return SMX_OK;
 }
 
+// ---- diagonalisation path (finite temperature, Algorithm 1) -----------------
+EigVecs eig_vecs(smx_ctx c)
+{
+    return EigVecs{c->d_ed.p, c->d_ee.p, c->d_etau.p, c->d_elam.p, c->d_elabs.p, c->d_ew.p, c->d_ebs.p, c->d_ebe.p};
+}
+
+// Decompose the groups of one wave at the context's mu: gather A_g - mu I
+// into slab 0 (and its Gershgorin norm), tridiagonalise (reflectors stay in
+// slab 0), eigenvalues and eigenvectors of T (slab 1, slab 2 as scratch),
+// Y = Q^T E (thin block 0), C = S^T Y (thin block 1) with the weights and the
+// unshifted eigenvalues.
+int32_t eig_decompose_wave(smx_ctx c, const Plan &P, const DevView &V, double *arena, double *pool, int32_t wave)
+{
+    hipStream_t st = c->stream;
+    const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
+    const int64_t E = P.work_elems;
+    double *a = arena, *s = arena + E, *scr = arena + 2 * E;
+    double *y = pool, *cb = pool + P.thin_elems;
+    const EigVecs ev = eig_vecs(c);
+    const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
+    HIP_TRY(c, launch_gather(st, nch, V.chunks + P.chunk_beg[wave], V.gd, V.rinfo, V.bmap, V.boffs, c->d_valoff.p,
+                             c->d_k.p, c->mu, a, V.scale));
+    HIP_TRY(c, launch_eig_tridiag(st, g0, wng, V.gd, a, ev));
+    HIP_TRY(c, launch_eig_values_vectors(st, g0, wng, P.max_npad, V.gd, ev, s, scr));
+    HIP_TRY(c, launch_eig_own_select(st, g0, wng, P.max_npad, P.max_own, V.gd, V.own, y));
+    HIP_TRY(c, launch_eig_reflect(st, 1, g0, wng, P.max_own, V.gd, a, ev, y));
+    HIP_TRY(c, launch_eig_thin(st, 0, g0, wng, P.max_npad, P.max_own, V.gd, ev, s, y, cb, c->mu, 0.0, c->kT, V.scale));
+    return SMX_OK;
+}
+
+// D's own columns of the decomposed wave at mu0 + dmu: Z = S diag(g) C
+// (thin block 2), G = Q Z, scatter of (E - G) / 2 with the energy and trace
+// partials of the wave's stored blocks.
+int32_t eig_apply_wave(smx_ctx c, const Plan &P, const DevView &V, double *arena, double *pool, int32_t wave,
+                       double dmu)
+{
+    hipStream_t st = c->stream;
+    const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
+    const int64_t E = P.work_elems;
+    double *a = arena, *s = arena + E;
+    double *cb = pool + P.thin_elems, *z = pool + 2 * P.thin_elems;
+    const EigVecs ev = eig_vecs(c);
+    HIP_TRY(c, launch_eig_thin(st, 1, g0, wng, P.max_npad, P.max_own, V.gd, ev, s, cb, z, c->mu, dmu, c->kT, V.scale));
+    HIP_TRY(c, launch_eig_reflect(st, 0, g0, wng, P.max_own, V.gd, a, ev, z));
+    IterState it{};
+    it.scale_bits = V.scale;
+    it.kfinal = V.kfinal;
+    const int nwave = P.nwaves();
+    const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
+    const int64_t *pl = nwave > 1 ? V.plist + P.plist_beg[wave] : nullptr;
+    HIP_TRY(c, launch_scatter(st, nsc, pl, V.scat, c->d_valoff.p, V.gd, z, nullptr, it, c->d_k.p, c->d_d.p, V.pe,
+                              V.pn, 1));
+    return SMX_OK;
+}
+
+// One evaluation on the diagonalisation path (all waves), then N and E.
+int32_t eig_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView &V, double *arena, double *pool)
+{
+    hipStream_t st = c->stream;
+    const int32_t ng = P.ngroups;
+    HIP_TRY(c, hipEventRecord(c->ev_t0, st));
+    HIP_TRY(c, hipMemsetAsync(V.scale, 0, sizeof(unsigned long long) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(V.resid, 0, sizeof(unsigned long long) * (size_t)ng * m.stride, st));
+    HIP_TRY(c, hipMemsetAsync(V.done, 0, sizeof(int32_t) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(V.kfinal, 0, sizeof(int32_t) * ng, st));
+    HIP_TRY(c, hipMemsetAsync(V.flags, 0, sizeof(int32_t) * ng, st));
+    c->launch_step.clear();
+    c->launch_kind.clear();
+    c->launch_wave.clear();
+    c->launch_subset.clear();
+    for (int32_t wave = 0; wave < P.nwaves(); wave++) {
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
+        if (int32_t e = eig_decompose_wave(c, P, V, arena, pool, wave)) return e;
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
+        if (int32_t e = eig_apply_wave(c, P, V, arena, pool, wave, 0.0)) return e;
+        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
+    }
+    HIP_TRY(c, launch_reduce(st, c->nnzb, V.pe, V.pn, V.ne));
+    HIP_TRY(c, hipEventRecord(c->ev_t3, st));
+    c->have_tangent = false;
+    c->last_sfix = false;
+    c->steps_launched = 0;
+    c->last_precision = SMX_FP64;
+    c->last_iteration = c->iteration;
+    c->last_stride = m.stride;
+    c->last_polish = 0;
+    c->last_fmt = -1;
+    c->last_nw = 0;
+    c->last_max_iter = c->max_iter;
+    c->last_mu = c->mu;
+    c->last_eig = true;
+    c->last_kT = c->kT;
+    c->evaluated = true;
+    return SMX_OK;
+}
 
 // ---- static scratch layout (smx_evaluate_static) ---------------------------
 // The whole work memory of a static evaluation lies in the fixed scratch
@@ -1674,7 +1809,9 @@ int32_t smx_evaluate(smx_ctx c)
     c->evaluated = false;
     c->eval_static = false;
     if (int32_t st = eval_prepare(c, m)) return st;
-    if (int32_t st = ensure_arena(c, m.mixed)) return st;
+    if (int32_t st = ensure_arena(c, m.mixed || m.eig)) return st;
+    if (m.eig) return eig_enqueue(c, m, c->plan, ctx_view(c), arena_base(c), pool_base(c));
+    c->last_eig = false;
     return eval_enqueue(c, m, c->plan, ctx_view(c), arena_base(c), pool_base(c), true, true, true, c->host_poll != 0);
 }
 
@@ -1686,6 +1823,8 @@ int32_t smx_evaluate_static(smx_ctx c)
     if (int32_t st = eval_mode(c, m)) return st;
     if (c->use_kfix || c->use_sfix)
         return fail(c, SMX_E_UNSUPPORTED, "frozen evaluations (derivatives, mu search) do not run in the static scratch");
+    if (m.eig)
+        return fail(c, SMX_E_UNSUPPORTED, "the diagonalisation path (kT > 0) does not run in the static scratch");
     if (int32_t st = set_device(c)) return st;
     void *sp = nullptr;
     {
@@ -1880,6 +2019,15 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
         const double ppb = c->last_iteration == SMX_ITER_PADE3 ? 3.0 : 2.0;
         s.algo_flops += 2.0 * nd * nd * nd * (ppb * (it[g] - c->last_polish) + 2.0 * c->last_polish);
     }
+    if (c->last_eig) {
+        // Householder reduction (4/3 n^3) and the four thin passes over n x n
+        // matrices with the m_own own columns (2 n^2 m_own each)
+        s.algo_flops = 0;
+        for (int32_t g = 0; g < ng; g++) {
+            const double nd = n[g];
+            s.algo_flops += 4.0 / 3.0 * nd * nd * nd + 8.0 * nd * nd * c->plan.gd[g].m_own;
+        }
+    }
     s.n_mean = ng ? nsum / ng : 0;
     s.iters_mean = ng ? isum / ng : 0;
     // issued matrix-core flops of the product kernels (live wave tiles, padding included)
@@ -1906,7 +2054,7 @@ int32_t smx_get_stats(smx_ctx c, smx_stats *out)
             }
         }
     }
-    s.exec_flops = exec;
+    s.exec_flops = c->last_eig ? s.algo_flops : exec;
     // phase times summed over the waves (the first wave's start includes the
     // state clears, the final reductions count as scatter)
     const int32_t nwave = c->plan.nwaves();
@@ -2047,7 +2195,7 @@ int32_t smx_set_frozen(smx_ctx c, int32_t on)
         return SMX_OK;
     }
     if (int32_t st = need_group_state(c)) return st;
-    if (c->last_iteration != SMX_ITER_NS2)
+    if (c->last_iteration != SMX_ITER_NS2 || c->last_eig)
         return fail(c, SMX_E_UNSUPPORTED, "the frozen map (derivatives, mu search) is the Newton-Schulz one");
     const int32_t ng = c->plan.ngroups;
     std::vector<int32_t> kf((size_t)ng);
@@ -2308,6 +2456,137 @@ int32_t smx_find_mu(smx_ctx c, double n_target, double tol, int32_t max_steps, d
 
 // Per stored block of K, the groups whose submatrix contains it, with the
 // block's offsets there (the transpose of the gather), ascending in group.
+int32_t smx_find_mu_eig(smx_ctx c, double n_target, double tol, int32_t max_steps, double *mu_out,
+                        int32_t *steps_out)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
+    if (!mu_out || !(tol > 0.0) || max_steps < 1) return fail(c, SMX_E_INVALID, "need mu_out, tol > 0, max_steps >= 1");
+    if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "the diagonalisation path runs in SMX_FP64");
+    if (c->use_kfix || c->use_sfix) return fail(c, SMX_E_UNSUPPORTED, "unfreeze first (smx_set_frozen(ctx, 0))");
+    if (int32_t st = set_device(c)) return st;
+    EvalMode m;
+    m.eig = true;
+    m.stride = c->max_iter + 2 + c->n_polish;
+    c->evaluated = false;
+    c->eval_static = false;
+    if (int32_t st = eval_prepare(c, m)) return st;
+    if (int32_t st = ensure_arena(c, true)) return st;
+    const Plan &P = c->plan;
+    const DevView V = ctx_view(c);
+    const int32_t ng = P.ngroups;
+    hipStream_t st = c->stream;
+    double *arena = arena_base(c), *pool = pool_base(c);
+    // 1. every group's eigenvalues and Algorithm 1's weights, at mu0
+    const double mu0 = c->mu;
+    HIP_TRY(c, hipMemsetAsync(V.scale, 0, sizeof(unsigned long long) * ng, st));
+    for (int32_t wave = 0; wave < P.nwaves(); wave++)
+        if (int32_t e = eig_decompose_wave(c, P, V, arena, pool, wave)) return e;
+    // 2. multisection on N(mu) = sum_g sum_l w_gl f(lambda_gl - mu), monotone in
+    // mu: kM trial points per round inside the bracket, which every eigenvalue
+    // (of every principal submatrix of K, by interlacing) lies in
+    constexpr int kM = 128;
+    double lo, hi;
+    if (int32_t e = gershgorin_interval(c, &lo, &hi)) return e;
+    lo -= 40.0 * c->kT + 1e-12 * std::max(1.0, std::fabs(lo));
+    hi += 40.0 * c->kT + 1e-12 * std::max(1.0, std::fabs(hi));
+    HIP_TRY(c, c->d_mus.ensure(kM));
+    HIP_TRY(c, c->d_nval.ensure(kM));
+    HIP_TRY(c, c->d_npart.ensure((size_t)std::max(ng, 1) * kM));
+    std::vector<double> mus(kM), nv(kM);
+    double best_mu = 0.5 * (lo + hi), best_n = NAN;
+    int32_t steps = 0;
+    bool found = false;
+    while (steps < max_steps && !found) {
+        for (int q = 0; q < kM; q++) mus[q] = lo + (hi - lo) * (q + 1) / (kM + 1);
+        HIP_TRY(c, hipMemcpyAsync(c->d_mus.p, mus.data(), sizeof(double) * kM, hipMemcpyHostToDevice, st));
+        HIP_TRY(c, launch_n_of_mu(st, ng, V.gd, eig_vecs(c), c->d_mus.p, kM, c->kT, V.scale, c->d_npart.p,
+                                  c->d_nval.p));
+        HIP_TRY(c, hipMemcpyAsync(nv.data(), c->d_nval.p, sizeof(double) * kM, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        steps++;
+        int first = kM;                               // first trial point with N >= target
+        for (int q = 0; q < kM; q++) {
+            if (!std::isfinite(nv[q])) return fail(c, SMX_E_NONFINITE, "N(mu) is not finite");
+            if (std::fabs(nv[q] - n_target) < (std::isnan(best_n) ? INFINITY : std::fabs(best_n - n_target))) {
+                best_n = nv[q];
+                best_mu = mus[q];
+            }
+            if (std::fabs(nv[q] - n_target) <= tol) found = true;
+            if (first == kM && nv[q] >= n_target) first = q;
+        }
+        if (found) break;
+        const double nlo = first > 0 ? mus[first - 1] : lo, nhi = first < kM ? mus[first] : hi;
+        if (!(nhi - nlo > 2.220446049250313e-16 * std::max(std::fabs(nlo), std::fabs(nhi)))) break;
+        lo = nlo;
+        hi = nhi;
+    }
+    // 3. D at mu* from the stored decompositions (one wave), or a new
+    // evaluation at mu* (the decompositions of earlier waves are gone)
+    c->mu = best_mu;
+    *mu_out = best_mu;
+    if (steps_out) *steps_out = steps;
+    if (P.nwaves() == 1) {
+        const double mu_dec = c->mu;
+        c->mu = mu0;                                  // the decomposition's shift
+        HIP_TRY(c, hipEventRecord(c->ev_t0, st));
+        HIP_TRY(c, hipMemsetAsync(V.kfinal, 0, sizeof(int32_t) * ng, st));
+        HIP_TRY(c, hipMemsetAsync(V.flags, 0, sizeof(int32_t) * ng, st));
+        HIP_TRY(c, hipMemsetAsync(V.resid, 0, sizeof(unsigned long long) * (size_t)ng * m.stride, st));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[0], st));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[1], st));
+        HIP_TRY(c, hipEventRecord(c->ev_wave[2], st));
+        int32_t e = eig_apply_wave(c, P, V, arena, pool, 0, mu_dec - mu0);
+        c->mu = mu_dec;
+        if (e) return e;
+        HIP_TRY(c, hipEventRecord(c->ev_wave[3], st));
+        HIP_TRY(c, launch_reduce(st, c->nnzb, V.pe, V.pn, V.ne));
+        HIP_TRY(c, hipEventRecord(c->ev_t3, st));
+        c->launch_step.clear();
+        c->launch_kind.clear();
+        c->launch_wave.clear();
+        c->launch_subset.clear();
+        c->have_tangent = false;
+        c->last_sfix = false;
+        c->last_precision = SMX_FP64;
+        c->last_iteration = c->iteration;
+        c->last_stride = m.stride;
+        c->last_polish = 0;
+        c->last_fmt = -1;
+        c->last_nw = 0;
+        c->last_max_iter = c->max_iter;
+        c->last_mu = c->mu;
+        c->last_eig = true;
+        c->last_kT = c->kT;
+        c->evaluated = true;
+    } else {
+        if (int32_t e = eig_enqueue(c, m, P, V, arena, pool)) return e;
+    }
+    if (!found)
+        return fail(c, SMX_E_NOT_CONVERGED, "N(mu) = " + std::to_string(best_n) + " does not reach the target " +
+                                                std::to_string(n_target) + " within tol (a step of N at T = 0?)");
+    return SMX_OK;
+}
+
+int32_t smx_get_spectrum(smx_ctx c, double *lam, double *w)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = need_group_state(c)) return st;
+    if (!c->last_eig) return fail(c, SMX_E_STATE, "the last evaluation did not diagonalise the submatrices");
+    const Plan &P = c->plan;
+    const size_t nr = P.rinfo.size();
+    std::vector<double> hl(nr), hw(nr);
+    HIP_TRY(c, hipMemcpy(hl.data(), c->d_elabs.p, nr * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(hw.data(), c->d_ew.p, nr * sizeof(double), hipMemcpyDeviceToHost));
+    size_t o = 0;
+    for (const GroupDesc &d : P.gd)
+        for (int32_t i = 0; i < d.n; i++, o++) {
+            if (lam) lam[o] = hl[(size_t)d.rinfo_off + i];
+            if (w) w[o] = hw[(size_t)d.rinfo_off + i];
+        }
+    return SMX_OK;
+}
+
 static int32_t ensure_contrib(smx_ctx c)
 {
     if (c->contrib_ready) return SMX_OK;
@@ -2348,7 +2627,7 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
     if (!dK_out && !dmu_out) return fail(c, SMX_E_INVALID, "nothing to compute (dK_out and dmu_out are NULL)");
     if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
     if (int32_t st = need_group_state(c)) return st;
-    if (c->last_iteration != SMX_ITER_NS2)
+    if (c->last_iteration != SMX_ITER_NS2 || c->last_eig)
         return fail(c, SMX_E_UNSUPPORTED, "the adjoint differentiates the Newton-Schulz map");
     if (int32_t st = set_device(c)) return st;
     if (c->plan.nwaves() != 1)
@@ -2534,6 +2813,7 @@ int32_t smx_get_history(smx_ctx c, int32_t cap, double *resid, double *tau, int3
     if (!c) return SMX_E_INVALID;
     if (cap < 0) return fail(c, SMX_E_INVALID, "cap must be >= 0");
     if (int32_t st = need_group_state(c)) return st;
+    if (c->last_eig) return fail(c, SMX_E_STATE, "the diagonalisation path has no iteration history");
     const int32_t ng = c->plan.ngroups;
     const int32_t stride = c->last_stride;
     std::vector<int32_t> kf((size_t)ng);

@@ -241,4 +241,45 @@ hipError_t launch_check_values(hipStream_t st, int64_t nblocks, const int64_t *v
                                const int32_t *blk_rows, const int32_t *blk_cols,
                                const int64_t *mirror, const double *kvals, double *out2);
 
+// ---- batched symmetric eigensolver (finite temperature, Algorithm 1) --------
+// Largest submatrix dimension of the eigensolver path (its workgroups keep
+// two vectors of this length in LDS and 64-row column strips in registers).
+constexpr int kEigMaxN = 3072;
+
+// Per-row arrays of the eigensolver, indexed like the row tables
+// (GroupDesc::rinfo_off + i): T's diagonal d and off-diagonal e (e_i couples
+// rows i and i + 1; 0 where T splits), the reflector scalars tau, the
+// eigenvalues of A_g - mu0 I (ascending within each unreduced block of T)
+// and of A_g + 0 (lam_abs = lam + mu0), Algorithm 1's weights
+// w_l = sum_{c in own} Q_cl^2, and each row's unreduced block [bs, be).
+struct EigVecs {
+    double *d, *e, *tau, *lam, *lam_abs, *w;
+    int32_t *bs, *be;
+};
+
+// Householder reduction of each group's slab (A_g - mu0 I, column-major) to
+// tridiagonal form, reflectors left below the subdiagonal; then the split.
+hipError_t launch_eig_tridiag(hipStream_t st, int g0, int ngroups, const GroupDesc *groups, double *a,
+                              const EigVecs &ev);
+// Eigenvalues (bisection) and eigenvectors (twisted factorisations, then
+// Gram-Schmidt inside tight clusters) of T: s[i * n_pad + l] = component i of
+// eigenvector l; scratch: one more slab.
+hipError_t launch_eig_values_vectors(hipStream_t st, int g0, int ngroups, int max_npad, const GroupDesc *groups,
+                                     const EigVecs &ev, double *s, double *scratch);
+// y = the own-column selector (n_pad x m_own blocks at thin_off).
+hipError_t launch_eig_own_select(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
+                                 const GroupDesc *groups, const int32_t *own_list, double *y);
+// y <- Q^T y (forward != 0) or Q y, with Q from the reflectors in a.
+hipError_t launch_eig_reflect(hipStream_t st, int forward, int g0, int ngroups, int max_own, const GroupDesc *groups,
+                              const double *a, const EigVecs &ev, double *y);
+// mode 0: out = S^T in, with weights and lam_abs = lam + mu0;
+// mode 1: out = S diag(g(lam - dmu)) in, g = tanh(x / 2kT) (signum at T = 0).
+hipError_t launch_eig_thin(hipStream_t st, int mode, int g0, int ngroups, int max_npad, int max_own,
+                           const GroupDesc *groups, const EigVecs &ev, const double *s, const double *in, double *out,
+                           double mu0, double dmu, double kT, const unsigned long long *scale_bits);
+// out[m] = N(mus[m]) = sum_g sum_l w_gl (1 - g(lam_abs_gl - mus[m])) / 2 over all groups
+// (part: ngroups * nmu scratch).
+hipError_t launch_n_of_mu(hipStream_t st, int ngroups, const GroupDesc *groups, const EigVecs &ev, const double *mus,
+                          int nmu, double kT, const unsigned long long *scale_bits, double *part, double *out);
+
 }  // namespace smx
