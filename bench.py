@@ -47,13 +47,13 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, gpu_d, stats_iters, n_g, nthreads, n_sample, seed=2024):
+def cpu_baseline(system, gpu_d, stats_iters, n_g, nthreads, n_sample, seed=2024, kT=0.0):
     """Time the CPU oracle on a seeded sample of groups and compare with the GPU D there."""
     import oracle
     rng = np.random.default_rng(seed)
     pick = np.sort(rng.choice(system.ngroups, size=min(n_sample, system.ngroups), replace=False))
     t0 = time.perf_counter()
-    ref = oracle.submatrix(system, which=pick, nthreads=nthreads)
+    ref = oracle.submatrix(system, which=pick, nthreads=nthreads, kT=kT)
     dt = time.perf_counter() - t0
     ok = ~np.isnan(ref.d_values)
     err = float(np.abs(gpu_d[ok] - ref.d_values[ok]).max())
@@ -103,6 +103,8 @@ def kernel_name(kind, precision):
         return "ns_f64_kernel"
     if kind in (7, 8, 10):
         return "ns_words256_kernel"
+    if kind == 12:
+        return "tridiag_kernel"
     return "ns_f32_kernel" if precision == "fp32" else "ns_words_kernel"
 
 
@@ -162,7 +164,8 @@ DTYPES = {"fp64": "f64", "fp16x2": "f16x2 words, f32 accumulation; f64 polish",
           "bf16": "bf16 words, f32 accumulation; f64 polish",
           "fp32": "f32, f32 accumulation; f64 polish"}
 PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf16", 2516.6),
-                  "ns_words256_kernel": ("fp16/bf16", 2516.6), "ns_f32_kernel": ("fp32", 157.3)}
+                  "ns_words256_kernel": ("fp16/bf16", 2516.6), "ns_f32_kernel": ("fp32", 157.3),
+                  "tridiag_kernel": ("HBM", 8000.0)}
 
 # HBM bytes per launch of the dominant kernel on water1024, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration; the
@@ -230,6 +233,8 @@ def main():
                     help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
     ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1],
                     help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch)")
+    ap.add_argument("--kT", type=float, default=0.0,
+                    help="electronic temperature in Hartree; kT > 0 times the diagonalisation path (Fermi D, FP64)")
     ap.add_argument("--iteration", default="ns2", choices=["ns2", "pade3"],
                     help="sign iteration of the timed path: second-order Newton-Schulz (two products per step) or "
                          "third-order Pade (three products per step); the FP64 reference that fixes the flop "
@@ -257,6 +262,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
         return
 
+    if args.kT > 0 and args.precision != "fp64":
+        ap.error("--kT > 0 runs the diagonalisation path, which is FP64 (use --precision fp64)")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -294,7 +301,7 @@ def main():
 
     # FP64 path first: the reference D and the iteration counts k_g of the
     # effective-TFLOP/s numerator (the same numerator for every precision)
-    timed_ref = args.precision == "fp64" and args.iteration == "ns2"
+    timed_ref = args.precision == "fp64" and args.iteration == "ns2" and args.kT == 0.0
     if timed_ref and not args.no_autotune:
         graph_steps, tuned = autotune()
     smx.smx_set_iteration(ctx.handle, "ns2")
@@ -304,7 +311,9 @@ def main():
     d_out = d64
     if not timed_ref:
         smx.smx_set_iteration(ctx.handle, args.iteration)
-        if not args.no_autotune:
+        if args.kT > 0:
+            smx.smx_set_temperature(ctx.handle, args.kT)
+        elif not args.no_autotune:
             graph_steps, tuned = autotune()
         run = run_path(smx, ctx, args.precision, args.steps, args.warmup, d_mix, graph_steps)
         d_out = d_mix
@@ -337,12 +346,18 @@ def main():
     kname, (kms, kfl, kn) = max(run["prof"].items(), key=lambda kv: kv[1][0])
     pdt, peak = PEAK_BY_KERNEL[kname]
     achieved = kfl / (kms * 1e-3) / 1e12
+    bound, unit = "mfma", "TFLOP/s"
+    if kname == "tridiag_kernel":
+        # BLAS2-bound: each reduction step reads and writes the trailing block once
+        # at least, 16 n^3 / 3 bytes per group = 4 bytes per counted flop (4/3 n^3)
+        bound, unit = "hbm", "GB/s"
+        achieved = 4.0 * kfl / (kms * 1e-3) / 1e9
     traffic, traffic_src, busy = measured_traffic(args.workload, kname)
     roofline = {
-        "bound": "mfma",
+        "bound": bound,
         "achieved": achieved,
         "peak": peak,
-        "unit": "TFLOP/s",
+        "unit": unit,
         "frac": achieved / peak,
         "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-calibrated)",
@@ -353,9 +368,10 @@ def main():
         "launches": kn,
         "avg_launch_ms": kms / max(kn, 1),
         "time_share": kms / sum(v[0] for v in run["prof"].values()),
-        "issued_mfma_tflops_all_products": stats["exec_flops"] / (stats["time_iterate_ms"] * 1e-3) / 1e12,
+        "issued_mfma_tflops_all_products": (stats["exec_flops"] / (stats["time_iterate_ms"] * 1e-3) / 1e12
+                                            if stats["time_iterate_ms"] > 0 else None),
     }
-    diff_vs_fp64 = float((d_out - d64).abs().max().item()) if not timed_ref else 0.0
+    diff_vs_fp64 = float((d_out - d64).abs().max().item()) if not timed_ref and args.kT == 0.0 else None
 
     out = {
         "metric": METRIC,
@@ -374,6 +390,9 @@ def main():
             "workload": args.workload + ": " + WORKLOADS[args.workload],
             "precision": args.precision,
             "iteration": args.iteration,
+            "kT_hartree": args.kT,
+            "solver": "diagonalisation (Householder + bisection + twisted factorisations)" if args.kT > 0
+                      else "matrix sign by products",
             "basis_functions": int(system.n),
             "submatrices": int(system.ngroups),
             "n_g_min_mean_max": [int(stats["n_min"]), round(stats["n_mean"], 1), int(stats["n_max"])],
@@ -404,7 +423,9 @@ def main():
 
     d_host = d_out.cpu().numpy()
     out["max_abs_D_minus_DT"] = d_asymmetry(system, d_host)
-    if args.full_sign or system.n <= 8000:
+    if args.kT > 0:
+        out["vs_full_matrix_sign"] = "not computed: the exact reference is the sign (T = 0)"
+    elif args.full_sign or system.n <= 8000:
         progress(f"exact sign of the whole K ({system.n} x {system.n})")
         out["vs_full_matrix_sign"] = full_sign_report(system, d_host, run["n_elec"], run["energy"])
     else:
@@ -414,7 +435,7 @@ def main():
         nth = min(16, os.cpu_count() or 1)
         progress(f"CPU oracle on a sample of {args.cpu_sample or nth} submatrices, {nth} threads")
         base, err, pick = cpu_baseline(system, d_out.cpu().numpy(), r64["info"]["iters"], r64["info"]["n"],
-                                       nth, args.cpu_sample or nth)
+                                       nth, args.cpu_sample or nth, kT=args.kT)
         out["cpu_baseline"] = base
         out["max_abs_dD_vs_oracle_on_sample"] = err
     print(json.dumps(out), flush=True)

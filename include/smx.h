@@ -495,6 +495,42 @@ int32_t smx_get_spectrum(smx_ctx ctx, double *lam, double *w);
 int32_t smx_backward(smx_ctx ctx, double gE, double gN, const double *gD, int32_t gD_on_device,
                      double *dK_out, int32_t dK_on_device, double *dmu_out);
 
+/*
+ * Group selection (Sec. IV-C, "Generating Submatrices From Multiple Block
+ * Columns").  Context-free host functions on a block pattern (the layout of
+ * smx_load_k, values not needed); errors are described by
+ * smx_group_last_error().
+ *
+ * smx_group_speedup: the estimated additional speedup of Eq.
+ * estimatedspeedup, S = sum over the single block columns j of n_j^3 divided
+ * by sum over the given groups g of n_g^3, n the dimension of the submatrix
+ * (the sizes of the union of the stored block rows of the columns); the
+ * evaluation of each submatrix is taken to cost O(n^3).  *work_out
+ * (nullable) = sum_g n_g^3.
+ */
+int32_t smx_group_speedup(int32_t nblk, const int32_t *blk_size, const int64_t *col_ptr,
+                          const int32_t *row_idx, int32_t ngroups, const int32_t *grp_ptr,
+                          const int32_t *grp_blocks, double *s_out, double *work_out);
+
+/*
+ * smx_group_kmeans: block columns that sit close together in space are
+ * combined (the paper clusters the atoms' positions with k-means, one
+ * position per block column).  coords: nblk x 3 (row-major) positions; box
+ * > 0: cubic periodic box of that edge (minimum-image distances, circular
+ * means), box = 0: plain Euclidean space.  k-means++ seeding from `seed`
+ * (deterministic), at most max_iter Lloyd iterations (nearest centre, lowest
+ * index on ties).  Output: *ngroups_out <= nclusters non-empty groups in the
+ * order of their first block column, block columns ascending inside each, as
+ * grp_ptr_out (nclusters + 1 entries of room) and grp_blocks_out (nblk),
+ * ready for smx_set_groups.
+ */
+int32_t smx_group_kmeans(int32_t nblk, const double *coords, double box, int32_t nclusters,
+                         int32_t seed, int32_t max_iter, int32_t *ngroups_out,
+                         int32_t *grp_ptr_out, int32_t *grp_blocks_out);
+
+/* Message for the last failing group-selection call (never NULL). */
+const char *smx_group_last_error(void);
+
 /* Number of groups and stored values of the loaded problem. */
 int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
 
@@ -507,7 +543,8 @@ int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
  * 128 x 128 tiles, 4/5 FP64 polish square/update, 6 mu tangent, 7/8
  * reduced-precision square/update on 256 x 256 tiles, 9/10 reduced-precision
  * Pade combine on 128 x 128 / 256 x 256 tiles, 11 FP64 Pade combine (the Pade
- * square shares the square's kind).  Writes min(cap, count) entries to the host
+ * square shares the square's kind), 12 Householder reduction of the
+ * diagonalisation path (algo_flops 4/3 n_g^3 per group).  Writes min(cap, count) entries to the host
  * arrays (any may be NULL) and the launch count to *count.  Synchronises.
  */
 int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,

@@ -78,6 +78,9 @@ SIGNATURES = {
     "smx_set_tile_shape": (_i32, [_vp, _i32]),
     "smx_set_iteration": (_i32, [_vp, _i32]),
     "smx_set_solver": (_i32, [_vp, _i32]),
+    "smx_group_speedup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _vp, _P(_f64), _P(_f64)]),
+    "smx_group_kmeans": (_i32, [_i32, _vp, _f64, _i32, _i32, _i32, _P(_i32), _vp, _vp]),
+    "smx_group_last_error": (ctypes.c_char_p, []),
     "smx_find_mu_eig": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
     "smx_get_spectrum": (_i32, [_vp, _vp, _vp]),
     "smx_get_launch_config": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
@@ -243,6 +246,38 @@ def smx_set_tile_order(ctx, order=0):
 
 def smx_set_kernel_variant(ctx, variant=0):
     return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
+def _group_check(st):
+    if st != SMX_OK:
+        raise SmxError(st, load_library().smx_group_last_error().decode())
+
+
+def group_speedup(system, grp_ptr=None, grp_blocks=None):
+    """(S, sum_g n_g^3) of Eq. estimatedspeedup for groups of the system's block
+    columns (default: the system's own groups)."""
+    gp = np.ascontiguousarray(system.grp_ptr if grp_ptr is None else grp_ptr, dtype=np.int32)
+    gb = np.ascontiguousarray(system.grp_blocks if grp_blocks is None else grp_blocks, dtype=np.int32)
+    bs = np.ascontiguousarray(system.blk_size, dtype=np.int32)
+    cp = np.ascontiguousarray(system.col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(system.row_idx, dtype=np.int32)
+    s, w = _f64(), _f64()
+    _group_check(load_library().smx_group_speedup(int(len(bs)), bs.ctypes.data, cp.ctypes.data, ri.ctypes.data,
+                                                  int(len(gp) - 1), gp.ctypes.data, gb.ctypes.data, ctypes.byref(s),
+                                                  ctypes.byref(w)))
+    return s.value, w.value
+
+
+def group_kmeans(coords, nclusters, box=0.0, seed=0, max_iter=100):
+    """(grp_ptr, grp_blocks): k-means clusters of the block columns' positions."""
+    xyz = np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
+    nb = xyz.shape[0]
+    gp = np.zeros(int(nclusters) + 1, np.int32)
+    gb = np.zeros(nb, np.int32)
+    ng = _i32()
+    _group_check(load_library().smx_group_kmeans(int(nb), xyz.ctypes.data, float(box), int(nclusters), int(seed),
+                                                 int(max_iter), ctypes.byref(ng), gp.ctypes.data, gb.ctypes.data))
+    return gp[:ng.value + 1].copy(), gb
 
 
 def smx_set_solver(ctx, solver="iterative"):

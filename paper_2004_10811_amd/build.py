@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsmx.so")
 
-SOURCES = ["smx_api.cpp", "smx_kernels.hip", "smx_ns_f64.hip", "smx_ns_words.hip", "smx_adjoint.hip", "smx_eig.hip"]
+SOURCES = ["smx_api.cpp", "smx_kernels.hip", "smx_ns_f64.hip", "smx_ns_words.hip", "smx_adjoint.hip", "smx_eig.hip", "smx_groups.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

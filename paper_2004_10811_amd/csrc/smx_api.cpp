@@ -1616,7 +1616,8 @@ EigVecs eig_vecs(smx_ctx c)
 // slab 0), eigenvalues and eigenvectors of T (slab 1, slab 2 as scratch),
 // Y = Q^T E (thin block 0), C = S^T Y (thin block 1) with the weights and the
 // unshifted eigenvalues.
-int32_t eig_decompose_wave(smx_ctx c, const Plan &P, const DevView &V, double *arena, double *pool, int32_t wave)
+int32_t eig_decompose_wave(smx_ctx c, const Plan &P, const DevView &V, double *arena, double *pool, int32_t wave,
+                           hipEvent_t after_gather = nullptr)
 {
     hipStream_t st = c->stream;
     const int32_t g0 = P.wave_g[wave], wng = P.wave_g[wave + 1] - g0;
@@ -1627,7 +1628,23 @@ int32_t eig_decompose_wave(smx_ctx c, const Plan &P, const DevView &V, double *a
     const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
     HIP_TRY(c, launch_gather(st, nch, V.chunks + P.chunk_beg[wave], V.gd, V.rinfo, V.bmap, V.boffs, c->d_valoff.p,
                              c->d_k.p, c->mu, a, V.scale));
-    HIP_TRY(c, launch_eig_tridiag(st, g0, wng, V.gd, a, ev));
+    if (after_gather) HIP_TRY(c, hipEventRecord(after_gather, st));
+    {
+        // the Householder reduction dominates the path: timed like the product launches
+        const size_t idx = c->launch_step.size();
+        while (c->ev_launch.size() < 2 * (idx + 1)) {
+            hipEvent_t evt;
+            HIP_TRY(c, hipEventCreate(&evt));
+            c->ev_launch.push_back(evt);
+        }
+        HIP_TRY(c, hipEventRecord(c->ev_launch[2 * idx], st));
+        HIP_TRY(c, launch_eig_tridiag(st, g0, wng, V.gd, a, ev));
+        HIP_TRY(c, hipEventRecord(c->ev_launch[2 * idx + 1], st));
+        c->launch_step.push_back(0);
+        c->launch_kind.push_back(12);
+        c->launch_wave.push_back(wave);
+        c->launch_subset.push_back(0);
+    }
     HIP_TRY(c, launch_eig_values_vectors(st, g0, wng, P.max_npad, V.gd, ev, s, scr));
     HIP_TRY(c, launch_eig_own_select(st, g0, wng, P.max_npad, P.max_own, V.gd, V.own, y));
     HIP_TRY(c, launch_eig_reflect(st, 1, g0, wng, P.max_own, V.gd, a, ev, y));
@@ -1677,8 +1694,7 @@ int32_t eig_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView &
     c->launch_subset.clear();
     for (int32_t wave = 0; wave < P.nwaves(); wave++) {
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
-        if (int32_t e = eig_decompose_wave(c, P, V, arena, pool, wave)) return e;
-        HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
+        if (int32_t e = eig_decompose_wave(c, P, V, arena, pool, wave, c->ev_wave[4 * wave + 1])) return e;
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
         if (int32_t e = eig_apply_wave(c, P, V, arena, pool, wave, 0.0)) return e;
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
@@ -2110,7 +2126,8 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
                                                                                       // run up to the last step
                 if (kd == 1 || kd == 3 || kd == 6 || kd == 8) active = k < kf[g];   // updates (and tangents) stop one earlier
                 const double n = c->plan.gd[g].n;
-                if (active) f += 2.0 * n * n * n;
+                if (kd == 12) f += 4.0 / 3.0 * n * n * n;     // Householder reduction to tridiagonal form
+                else if (active) f += 2.0 * n * n * n;
             }
             algo_flops[l] = f;
         }
