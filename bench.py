@@ -97,6 +97,29 @@ def full_sign_report(system, d_values, n_gpu, e_gpu):
             "method": "numpy.linalg.eigh of the dense K - mu I", "seconds": time.perf_counter() - t0}
 
 
+def literal_bf16_report(smx, stream_handle, reps=20):
+    """The paper's plain-BF16 mode on water16 (one BF16 word per value, FP32
+    accumulation, then the FP64 own-column polish): device time per D against
+    the FP64 path, and its D against the FP64 GPU D.  Returns (report, D)."""
+    from waterbox import water_config
+    s = water_config("water16")
+    out, dvals = {"workload": "water16: " + WORKLOADS["water16"]}, {}
+    for prec in ("fp64", "bf16"):
+        ctx = smx.Context(0, stream=stream_handle).load(s).configure(precision=prec)
+        ms = []
+        for _ in range(reps + 3):
+            res = ctx.evaluate(allow_not_converged=True)
+            ms.append(ctx.stats()["time_total_ms"])
+        dvals[prec] = res
+        out[f"{prec}_ms_per_D"] = float(np.median(ms[3:]))
+        out[f"{prec}_status"] = int(res.status)
+        ctx.close()
+    out["speedup_over_fp64"] = out["fp64_ms_per_D"] / out["bf16_ms_per_D"]
+    out["max_abs_dD_vs_fp64_gpu"] = float(np.abs(dvals["bf16"].d_values - dvals["fp64"].d_values).max())
+    out["dN_vs_fp64_gpu"] = dvals["bf16"].n_elec - dvals["fp64"].n_elec
+    return out, s, dvals["bf16"]
+
+
 def kernel_name(kind, precision):
     """Product kernel of a launch kind (smx_get_launch_profile)."""
     if kind in (0, 1, 4, 5, 6, 11):
@@ -121,6 +144,17 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
         smx.smx_evaluate(ctx.handle)
         smx.smx_wait(ctx.handle)
 
+    def record(prof):
+        # per kernel: [device ms, algorithmic flops, launches, issued matrix-core flops]
+        ms, fl, kd = ctx.launch_profile()
+        iss = smx.smx_get_launch_issued(ctx.handle)
+        for m, f, k, q in zip(ms, fl, kd, iss):
+            e = prof.setdefault(kernel_name(k, precision), [0.0, 0.0, 0, 0.0])
+            e[0] += m
+            e[1] += f
+            e[2] += 1
+            e[3] += q
+
     for w in range(warmup):
         step()
         progress(f"{precision}: warm-up step {w + 1}/{warmup} done")
@@ -130,13 +164,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-        ms, fl, kd = ctx.launch_profile()
-        for m, f, k in zip(ms, fl, kd):
-            key = kernel_name(k, precision)
-            e = prof.setdefault(key, [0.0, 0.0, 0])
-            e[0] += m
-            e[1] += f
-            e[2] += 1
+        record(prof)
         dev_ms.append(ctx.stats()["time_total_ms"])
         if dev_ms[-1] > 2000:
             progress(f"{precision}: timed step {len(dev_ms)}/{steps} done ({dev_ms[-1]:.0f} ms)")
@@ -148,13 +176,7 @@ def run_path(smx, ctx, precision, steps, warmup, d_out, graph_steps=0):
     if graph_steps:
         ctx.configure(precision=precision, graph_steps=0)
         step()
-        ms, fl, kd = ctx.launch_profile()
-        for m, f, k in zip(ms, fl, kd):
-            key = kernel_name(k, precision)
-            e = prof.setdefault(key, [0.0, 0.0, 0])
-            e[0] += m
-            e[1] += f
-            e[2] += 1
+        record(prof)
     return dict(ms_per_step=wall / steps * 1e3, dev_ms=dev_ms, prof=prof, stats=stats, info=info,
                 n_elec=smx.smx_trace(ctx.handle), energy=smx.smx_energy(ctx.handle))
 
@@ -343,7 +365,7 @@ def main():
     ms_per_step = run["ms_per_step"]
     value = algo / (ms_per_step * 1e-3) / 1e12
     # dominant product kernel by device time
-    kname, (kms, kfl, kn) = max(run["prof"].items(), key=lambda kv: kv[1][0])
+    kname, (kms, kfl, kn, kiss) = max(run["prof"].items(), key=lambda kv: kv[1][0])
     pdt, peak = PEAK_BY_KERNEL[kname]
     achieved = kfl / (kms * 1e-3) / 1e12
     bound, unit = "mfma", "TFLOP/s"
@@ -368,6 +390,10 @@ def main():
         "launches": kn,
         "avg_launch_ms": kms / max(kn, 1),
         "time_share": kms / sum(v[0] for v in run["prof"].values()),
+        # issued matrix-core flops (word products, padding and half tiles included)
+        # over the launch time and the same peak: the matrix-core utilisation proper
+        "issued_frac": (kiss / (kms * 1e-3) / 1e12 / peak) if bound == "mfma" else None,
+        "issued_per_algorithmic": kiss / kfl if kfl > 0 else None,
         "issued_mfma_tflops_all_products": (stats["exec_flops"] / (stats["time_iterate_ms"] * 1e-3) / 1e12
                                             if stats["time_iterate_ms"] > 0 else None),
     }
@@ -431,6 +457,11 @@ def main():
     else:
         out["vs_full_matrix_sign"] = f"not computed: dense eigendecomposition of a {system.n} x {system.n} matrix " \
                                      "(use --full-sign)"
+    if args.workload == "water1024" and args.kT == 0.0:
+        progress("plain BF16 on water16")
+        import torch as _t
+        lit, lit_sys, lit_res = literal_bf16_report(smx, _t.cuda.current_stream().cuda_stream)
+        out["literal_bf16_water16"] = lit
     if not args.no_cpu_baseline:
         nth = min(16, os.cpu_count() or 1)
         progress(f"CPU oracle on a sample of {args.cpu_sample or nth} submatrices, {nth} threads")
@@ -438,6 +469,11 @@ def main():
                                        nth, args.cpu_sample or nth, kT=args.kT)
         out["cpu_baseline"] = base
         out["max_abs_dD_vs_oracle_on_sample"] = err
+        if "literal_bf16_water16" in out:
+            import oracle
+            ref = oracle.submatrix(lit_sys)
+            out["literal_bf16_water16"]["max_abs_dD_vs_oracle"] = float(np.abs(lit_res.d_values - ref.d_values).max())
+            out["literal_bf16_water16"]["dN_vs_oracle"] = lit_res.n_elec - ref.n_elec
     print(json.dumps(out), flush=True)
 
 

@@ -550,6 +550,20 @@ int32_t smx_get_sizes(smx_ctx ctx, int32_t *ngroups, int64_t *nvalues);
 int32_t smx_get_launch_profile(smx_ctx ctx, int32_t cap, float *ms, double *algo_flops,
                                int32_t *kind, int32_t *count);
 
+/*
+ * Issued matrix-core flops of each launch of smx_get_launch_profile, in the
+ * same order: 2 x 64 x 64 x n_pad per live 64 x 64 wave tile of a 128 x 128
+ * tile (2 x 16 x 16 x n_pad per live 16 x 16 block of a 256 x 256 tile),
+ * times the word products per algorithmic product (3 for SMX_FP16_2W, 6 for
+ * SMX_BF16_3W, else 1), padding included, for every group the launch works
+ * on; kind 12 (vector units only) repeats its algorithmic flops.  Divided by
+ * the launch time and the matrix-core peak of the format this is the
+ * fraction of the matrix cores the launch kept busy.  Writes min(cap, count)
+ * entries (issued_flops may be NULL) and the launch count to *count.
+ * Synchronises.
+ */
+int32_t smx_get_launch_issued(smx_ctx ctx, int32_t cap, double *issued_flops, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

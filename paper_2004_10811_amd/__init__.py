@@ -95,6 +95,7 @@ SIGNATURES = {
     "smx_get_group_info": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "smx_get_sizes": (_i32, [_vp, _P(_i32), _P(_i64)]),
     "smx_get_launch_profile": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(_i32)]),
+    "smx_get_launch_issued": (_i32, [_vp, _i32, _vp, _P(_i32)]),
     "smx_get_submatrix": (_i32, [_vp, _i32, _i32, _vp, _i32, _P(_i32)]),
     "smx_set_frozen": (_i32, [_vp, _i32]),
     "smx_dn_dmu": (_i32, [_vp, _P(_f64)]),
@@ -395,6 +396,15 @@ def smx_get_launch_profile(ctx):
     _check(ctx, load_library().smx_get_launch_profile(ctx, n, ms.ctypes.data, fl.ctypes.data,
                                                        kd.ctypes.data, ctypes.byref(cnt)))
     return ms.astype(np.float64), fl, kd
+
+
+def smx_get_launch_issued(ctx):
+    """Issued matrix-core flops per product-kernel launch (order of smx_get_launch_profile)."""
+    cnt = _i32()
+    _check(ctx, load_library().smx_get_launch_issued(ctx, 0, None, ctypes.byref(cnt)))
+    out = np.zeros(cnt.value)
+    _check(ctx, load_library().smx_get_launch_issued(ctx, cnt.value, out.ctypes.data, ctypes.byref(cnt)))
+    return out
 
 
 def smx_get_submatrix(ctx, g: int, what: int = 1) -> np.ndarray:

@@ -2135,6 +2135,45 @@ int32_t smx_get_launch_profile(smx_ctx c, int32_t cap, float *ms, double *algo_f
     return SMX_OK;
 }
 
+int32_t smx_get_launch_issued(smx_ctx c, int32_t cap, double *issued_flops, int32_t *count)
+{
+    if (!c) return SMX_E_INVALID;
+    if (int32_t st = need_group_state(c)) return st;
+    const int32_t nl = (int32_t)c->launch_step.size();
+    if (count) *count = nl;
+    if (!issued_flops) return SMX_OK;
+    std::vector<int32_t> kf((size_t)c->plan.ngroups);
+    HIP_TRY(c, hipMemcpy(kf.data(), c->d_kfinal.p, kf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const Plan &P = c->plan;
+    int npairs = 1;
+    if (c->last_precision == SMX_FP16_2W) npairs = 3;
+    if (c->last_precision == SMX_BF16_3W) npairs = 6;
+    for (int32_t l = 0; l < nl && l < cap; l++) {
+        const int32_t kd = c->launch_kind[l], k = c->launch_step[l], w = c->launch_wave[l];
+        const int32_t sub = c->launch_subset[l];
+        double f = 0;
+        for (int32_t g = P.wave_g[w]; g < P.wave_g[w + 1]; g++) {
+            if (sub == 1 && P.big[g]) continue;
+            if (sub == 2 && !P.big[g]) continue;
+            bool active = true;
+            if (kd == 0 || kd == 2 || kd == 7 || kd >= 9) active = k <= kf[g];
+            if (kd == 1 || kd == 3 || kd == 6 || kd == 8) active = k < kf[g];
+            const GroupDesc &d = P.gd[g];
+            if (kd == 12) {
+                const double n = d.n;
+                f += 4.0 / 3.0 * n * n * n;              // vector-unit work, no matrix cores
+            } else if (active) {
+                const bool word = kd == 2 || kd == 3 || kd == 7 || kd == 8 || kd == 9 || kd == 10;
+                const double per = (kd == 7 || kd == 8 || kd == 10) ? P.wtiles2[g] * 2.0 * 16 * 16 * d.npad
+                                                                     : P.wtiles[g] * 2.0 * 64 * 64 * d.npad;
+                f += per * (word ? npairs : 1);
+            }
+        }
+        issued_flops[l] = f;
+    }
+    return SMX_OK;
+}
+
 int32_t smx_get_submatrix(smx_ctx c, int32_t g, int32_t what, double *out, int32_t ld, int32_t *n_out)
 {
     if (!c) return SMX_E_INVALID;
