@@ -358,6 +358,18 @@ int32_t smx_evaluate(smx_ctx ctx);
 #define SMX_STATIC_SCRATCH_BYTES (1024ull * 1024ull * 1024ull)
 int32_t smx_evaluate_static(smx_ctx ctx);
 
+/*
+ * D of the last evaluation written into another layout of n_out stored
+ * values: out[index[q]] = D_q for every stored value q of the loaded problem
+ * and 0 at every other position (the split problem of smx_split_columns back
+ * in K's layout, index = its e_src: elements the split dropped get D = 0).
+ * index: host, nvalues entries, each in [0, n_out) and pairwise distinct
+ * (SMX_E_INVALID otherwise).  out: host, or device when out_on_device != 0.
+ * Synchronises.
+ */
+int32_t smx_get_d_expanded(smx_ctx ctx, const int64_t *index, int64_t n_out, double *out,
+                           int32_t out_on_device);
+
 /* Wait for the last evaluation.  SMX_E_NONFINITE if an iterate was not
  * finite; SMX_E_NOT_CONVERGED (D is still written) if any group did not
  * converge:
@@ -527,6 +539,32 @@ int32_t smx_group_speedup(int32_t nblk, const int32_t *blk_size, const int64_t *
 int32_t smx_group_kmeans(int32_t nblk, const double *coords, double box, int32_t nclusters,
                          int32_t seed, int32_t max_iter, int32_t *ngroups_out,
                          int32_t *grp_ptr_out, int32_t *grp_blocks_out);
+
+/*
+ * Splitting submatrices (Sec. IV-C, "Splitting up submatrices"): a dense
+ * submatrix may still be sparse element by element, and applying the
+ * submatrix method to it a second time, for the columns it owns only, gives
+ * one smaller sub-submatrix per column.  The sub-submatrix of column c keeps
+ * the rows r with r = c or |K_rc| > eps (r in a stored block of c's block
+ * column); it does not depend on the group of c's block column, so the whole
+ * split problem is the submatrix method on K at the level of single elements.
+ * This call builds that problem, ready for smx_load_k / smx_set_groups:
+ * n (the sum of the block sizes) columns, each a block of size 1; e_col_ptr (n + 1),
+ * e_row_idx and e_values (nnz, rows ascending per column) the kept elements;
+ * e_src (nnz) the position of each kept element in `values`; groups
+ * e_grp_ptr (ngroups + 1) / e_grp_cols (n): single columns, or with merge != 0
+ * runs of consecutive columns of one block column that keep the same rows
+ * (one sub-submatrix serves them all; the result is the same).  Call once
+ * with e_col_ptr = NULL for *n_out, *nnz_out and *ngroups_out, then with
+ * arrays of those sizes.  values: host, K's layout (smx_load_k).  D of the
+ * split problem goes back to K's layout with smx_get_d_expanded(e_src).
+ * Errors as the group-selection calls (smx_group_last_error).
+ */
+int32_t smx_split_columns(int32_t nblk, const int32_t *blk_size, const int64_t *col_ptr,
+                          const int32_t *row_idx, const double *values, double eps, int32_t merge,
+                          int32_t *n_out, int64_t *nnz_out, int32_t *ngroups_out, int64_t *e_col_ptr,
+                          int32_t *e_row_idx, double *e_values, int64_t *e_src, int32_t *e_grp_ptr,
+                          int32_t *e_grp_cols);
 
 /* Message for the last failing group-selection call (never NULL). */
 const char *smx_group_last_error(void);

@@ -379,3 +379,73 @@ def symmetric_part(s, dk):
         b = dk[voff[q]:voff[q + 1]].reshape(bj, bi, order="F")
         out[voff[p]:voff[p + 1]] = (a + b.T).reshape(-1, order="F")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Splitting submatrices into sub-submatrices (Sec. IV-C, "Splitting up
+# submatrices"): the dense submatrix of a block column may still be sparse
+# element by element, so the submatrix method is applied to it a second time,
+# column by column, and only for the columns the block column owns.  For own
+# column c of A_g = K[R, R] - mu I the sub-submatrix keeps the rows r of A_g
+# whose element (r, c) is non-zero -- here |K_rc| > eps, plus r = c -- and
+# D's column c is the matching column of the density of that sub-submatrix
+# (zero at the rows it drops).  Plain loops and the Jacobi density above, for
+# small cases only.
+# ---------------------------------------------------------------------------
+
+def split_submatrix(s, eps: float, mu: float | None = None, kT: float = 0.0, which=None) -> OracleResult:
+    """D of the sub-submatrix method (K's layout; NaN outside the processed
+    groups' columns), N = Tr D and E = Tr(DK) over the processed columns."""
+    mu = s.mu if mu is None else mu
+    vals = _f64(s.values)
+    boff = np.concatenate([[0], np.cumsum(np.asarray(s.blk_size, dtype=np.int64))])
+    voff = s.val_off()
+    # stored blocks: (block row, block col) -> storage position
+    where = {}
+    for j in range(s.nblk):
+        for p in range(int(s.col_ptr[j]), int(s.col_ptr[j + 1])):
+            where[(int(s.row_idx[p]), j)] = p
+    groups = range(s.ngroups) if which is None else [int(g) for g in which]
+    d = np.full(vals.shape, np.nan)
+    n_e = e_e = 0.0
+    for g in groups:
+        cols = [int(b) for b in s.grp_blocks[s.grp_ptr[g]:s.grp_ptr[g + 1]]]
+        # step 1: R(g), the block rows stored in any of the group's block columns
+        rblk = sorted({int(i) for j in cols for i in s.row_idx[s.col_ptr[j]:s.col_ptr[j + 1]]})
+        rows = np.concatenate([np.arange(boff[i], boff[i + 1]) for i in rblk])
+        loc = {int(r): t for t, r in enumerate(rows)}
+        n = len(rows)
+        # step 2: the dense submatrix A_g = K[R, R] - mu I, and which of its
+        # elements lie in stored blocks
+        a = np.zeros((n, n))
+        stored = np.zeros((n, n), dtype=bool)
+        for bi in rblk:
+            for bj in rblk:
+                p = where.get((bi, bj))
+                if p is None:
+                    continue
+                blk = vals[voff[p]:voff[p + 1]].reshape(s.blk_size[bi], s.blk_size[bj], order="F")
+                r0, c0 = loc[int(boff[bi])], loc[int(boff[bj])]
+                a[r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]] = blk
+                stored[r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]] = True
+        a_k = a.copy()
+        a -= mu * np.eye(n)
+        # step 3: one sub-submatrix per own column
+        for j in cols:
+            for c in range(int(boff[j]), int(boff[j + 1])):
+                lc = loc[c]
+                keep = [r for r in range(n) if r == lc or (stored[r, lc] and abs(a_k[r, lc]) > eps)]
+                sub = a[np.ix_(keep, keep)]
+                dsub = dense_density(sub, kT)
+                dcol = np.zeros(n)
+                dcol[keep] = dsub[:, keep.index(lc)]
+                # write column c of every stored block (I, j) of the block column
+                for p in range(int(s.col_ptr[j]), int(s.col_ptr[j + 1])):
+                    i = int(s.row_idx[p])
+                    bi = int(s.blk_size[i])
+                    r0 = loc[int(boff[i])]
+                    cc = c - int(boff[j])
+                    d[voff[p] + cc * bi:voff[p] + (cc + 1) * bi] = dcol[r0:r0 + bi]
+                    e_e += float(dcol[r0:r0 + bi] @ vals[voff[p] + cc * bi:voff[p] + (cc + 1) * bi])
+                n_e += float(dcol[lc])
+    return OracleResult(d, n_e, e_e, [], np.asarray(list(groups), dtype=np.int32))

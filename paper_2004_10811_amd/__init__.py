@@ -81,6 +81,9 @@ SIGNATURES = {
     "smx_group_speedup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _vp, _P(_f64), _P(_f64)]),
     "smx_group_kmeans": (_i32, [_i32, _vp, _f64, _i32, _i32, _i32, _P(_i32), _vp, _vp]),
     "smx_group_last_error": (ctypes.c_char_p, []),
+    "smx_split_columns": (_i32, [_i32, _vp, _vp, _vp, _vp, _f64, _i32, _P(_i32), _P(_i64), _P(_i32), _vp, _vp,
+                                 _vp, _vp, _vp, _vp]),
+    "smx_get_d_expanded": (_i32, [_vp, _vp, _i64, _vp, _i32]),
     "smx_find_mu_eig": (_i32, [_vp, _f64, _f64, _i32, _P(_f64), _P(_i32)]),
     "smx_get_spectrum": (_i32, [_vp, _vp, _vp]),
     "smx_get_launch_config": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
@@ -279,6 +282,54 @@ def group_kmeans(coords, nclusters, box=0.0, seed=0, max_iter=100):
     _group_check(load_library().smx_group_kmeans(int(nb), xyz.ctypes.data, float(box), int(nclusters), int(seed),
                                                  int(max_iter), ctypes.byref(ng), gp.ctypes.data, gb.ctypes.data))
     return gp[:ng.value + 1].copy(), gb
+
+
+@dataclass
+class SplitProblem:
+    """The element-level problem of smx_split_columns (the BSC fields Context.load
+    reads) and src, the position of each of its values in the block layout."""
+    blk_size: np.ndarray
+    col_ptr: np.ndarray
+    row_idx: np.ndarray
+    values: np.ndarray
+    grp_ptr: np.ndarray
+    grp_blocks: np.ndarray
+    mu: float
+    src: np.ndarray
+    nvalues_block: int
+
+
+def split_columns(system, eps, merge=True):
+    """Sub-submatrices of single columns (smx_split_columns) as a SplitProblem."""
+    bs = np.ascontiguousarray(system.blk_size, dtype=np.int32)
+    cp = np.ascontiguousarray(system.col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(system.row_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(system.values, dtype=np.float64)
+    n, nnz, ng = _i32(), _i64(), _i32()
+    lib = load_library()
+    _group_check(lib.smx_split_columns(len(bs), bs.ctypes.data, cp.ctypes.data, ri.ctypes.data, vals.ctypes.data,
+                                       float(eps), int(bool(merge)), ctypes.byref(n), ctypes.byref(nnz),
+                                       ctypes.byref(ng), None, None, None, None, None, None))
+    ecp = np.zeros(n.value + 1, np.int64)
+    eri = np.zeros(nnz.value, np.int32)
+    ev = np.zeros(nnz.value)
+    es = np.zeros(nnz.value, np.int64)
+    egp = np.zeros(ng.value + 1, np.int32)
+    egc = np.zeros(n.value, np.int32)
+    _group_check(lib.smx_split_columns(len(bs), bs.ctypes.data, cp.ctypes.data, ri.ctypes.data, vals.ctypes.data,
+                                       float(eps), int(bool(merge)), ctypes.byref(n), ctypes.byref(nnz),
+                                       ctypes.byref(ng), ecp.ctypes.data, eri.ctypes.data, ev.ctypes.data,
+                                       es.ctypes.data, egp.ctypes.data, egc.ctypes.data))
+    return SplitProblem(np.ones(n.value, np.int32), ecp, eri, ev, egp, egc, float(system.mu), es, len(vals))
+
+
+def smx_get_d_expanded(ctx, index, n_out, out=None):
+    """D of the last evaluation in another layout: out[index[q]] = D_q, 0 elsewhere."""
+    idx = np.ascontiguousarray(index, dtype=np.int64)
+    if out is None:
+        out = np.empty(int(n_out))
+    _check(ctx, load_library().smx_get_d_expanded(ctx, idx.ctypes.data, int(n_out), _ptr(out), _on_device(out)))
+    return out
 
 
 def smx_set_solver(ctx, solver="iterative"):

@@ -198,6 +198,9 @@ struct smx_context {
     DevBuf<int4> d_contrib;
     DevBuf<double> d_adj, d_dk, d_dmu;
     bool contrib_ready = false;
+    // D in another layout (smx_get_d_expanded)
+    DevBuf<int64_t> d_xidx;
+    DevBuf<double> d_xout;
     DevBuf<double> d_tpool;                      // own-column blocks of the FP64 polish (2 n_polish + 1)
     DevBuf<int64_t> d_plist;
 
@@ -903,6 +906,8 @@ int32_t smx_destroy(smx_ctx c)
     for (auto *b : {&c->d_k, &c->d_d, &c->d_arena, &c->d_pe, &c->d_pn, &c->d_ne, &c->d_check})
         b->release();
     c->d_fsum.release();
+    c->d_xidx.release();
+    c->d_xout.release();
     c->d_plist.release();
     c->d_valoff.release();
     c->d_mirror.release();
@@ -1946,6 +1951,37 @@ int32_t smx_get_d(smx_ctx c, double *out, int32_t out_on_device)
     if (c->nvals > 0)
         HIP_TRY(c, hipMemcpyAsync(out, c->d_d.p, (size_t)c->nvals * sizeof(double),
                                   out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SMX_OK;
+}
+
+int32_t smx_get_d_expanded(smx_ctx c, const int64_t *index, int64_t n_out, double *out, int32_t out_on_device)
+{
+    if (!c) return SMX_E_INVALID;
+    if (!out || (!index && c->nvals > 0)) return fail(c, SMX_E_INVALID, "index and out must not be NULL");
+    if (n_out < 0) return fail(c, SMX_E_INVALID, "n_out < 0");
+    if (int32_t st = need_sync_results(c)) return st;
+    {
+        std::vector<char> seen((size_t)n_out, 0);
+        for (int64_t q = 0; q < c->nvals; q++) {
+            const int64_t d = index[q];
+            if (d < 0 || d >= n_out) return fail(c, SMX_E_INVALID, "index out of range at " + std::to_string(q));
+            if (seen[(size_t)d]) return fail(c, SMX_E_INVALID, "index repeats position " + std::to_string(d));
+            seen[(size_t)d] = 1;
+        }
+    }
+    HIP_TRY(c, c->d_xidx.ensure((size_t)c->nvals));
+    if (c->nvals > 0)
+        HIP_TRY(c, hipMemcpyAsync(c->d_xidx.p, index, (size_t)c->nvals * sizeof(int64_t), hipMemcpyHostToDevice,
+                                  c->stream));
+    double *dst = out;
+    if (!out_on_device) {
+        HIP_TRY(c, c->d_xout.ensure((size_t)n_out));
+        dst = c->d_xout.p;
+    }
+    HIP_TRY(c, launch_expand_values(c->stream, c->nvals, c->d_xidx.p, c->d_d.p, n_out, dst));
+    if (!out_on_device && n_out > 0)
+        HIP_TRY(c, hipMemcpyAsync(out, dst, (size_t)n_out * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SMX_OK;
 }

@@ -1,9 +1,13 @@
-// Group selection (Sec. IV-C, "Generating Submatrices From Multiple Block
-// Columns"): the estimated additional speedup S of combining block columns
-// into submatrices (Eq. estimatedspeedup), and a k-means clustering of the
-// block columns' positions in space that proposes such combinations.  Host
-// code only: both act on the sparsity pattern and on coordinates, before any
-// submatrix exists.
+// Shapes of the submatrices (Sec. IV-C, "Minimization of Floating-Point
+// Operations"), host code that acts on the sparsity pattern, the values'
+// magnitudes and coordinates before any submatrix exists:
+//  * group selection ("Generating Submatrices From Multiple Block Columns"):
+//    the estimated additional speedup S of combining block columns into
+//    submatrices (Eq. estimatedspeedup), and a k-means clustering of the block
+//    columns' positions in space that proposes such combinations;
+//  * splitting ("Splitting up submatrices"): the problem of the
+//    sub-submatrices, one per single column, each holding the rows where that
+//    column is non-zero element by element.
 #include "smx.h"
 
 #include <algorithm>
@@ -231,6 +235,79 @@ int32_t smx_group_kmeans(int32_t nblk, const double *coords, double box, int32_t
     std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
     for (int32_t i = 0; i < nblk; i++) grp_blocks_out[pos[order[asg[i]]]++] = i;
     *ngroups_out = ng;
+    return SMX_OK;
+}
+
+// The element-level problem: block sizes 1, column c keeps row r where r = c
+// or where r lies in a stored block of c's block column and |K_rc| > eps.  For
+// every own column c of a block-column submatrix A_g (c's block column in g)
+// the rows of A_g that are non-zero in column c are exactly these rows, so the
+// submatrix of element column c is the sub-submatrix of c (whatever group c's
+// block column was in), and D's column c comes out of it.  Groups: single
+// columns, or (merge != 0) runs of consecutive columns of one block column
+// that keep the same rows, which share one sub-submatrix.
+int32_t smx_split_columns(int32_t nblk, const int32_t *blk_size, const int64_t *col_ptr, const int32_t *row_idx,
+                          const double *values, double eps, int32_t merge, int32_t *n_out, int64_t *nnz_out,
+                          int32_t *ngroups_out, int64_t *e_col_ptr, int32_t *e_row_idx, double *e_values,
+                          int64_t *e_src, int32_t *e_grp_ptr, int32_t *e_grp_cols)
+{
+    if (int32_t st = check_pattern(nblk, blk_size, col_ptr, row_idx)) return st;
+    if (!values || !n_out || !nnz_out || !ngroups_out) return fail(SMX_E_INVALID, "need values and the size outputs");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SMX_E_INVALID, "eps must be finite and >= 0");
+    const bool fill = e_col_ptr != nullptr;
+    if (fill && (!e_row_idx || !e_values || !e_src || !e_grp_ptr || !e_grp_cols))
+        return fail(SMX_E_INVALID, "the fill call needs every output array");
+    std::vector<int64_t> boff((size_t)nblk + 1, 0), voff((size_t)col_ptr[nblk] + 1, 0);
+    for (int32_t j = 0; j < nblk; j++) boff[j + 1] = boff[j] + blk_size[j];
+    for (int32_t j = 0; j < nblk; j++)
+        for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; p++)
+            voff[p + 1] = voff[p] + (int64_t)blk_size[row_idx[p]] * blk_size[j];
+    for (int32_t j = 0; j < nblk; j++)
+        for (int64_t p = col_ptr[j] + 1; p < col_ptr[j + 1]; p++)
+            if (row_idx[p] <= row_idx[p - 1]) return fail(SMX_E_INVALID, "row_idx must ascend within a column");
+    const int64_t n = boff[nblk];
+    if (n > INT32_MAX) return fail(SMX_E_INVALID, "more than 2^31 - 1 columns");
+    int64_t nnz = 0;
+    int32_t ngroups = 0;
+    std::vector<int32_t> rows, prev_rows;
+    for (int32_t j = 0; j < nblk; j++) {
+        const int32_t bj = blk_size[j];
+        for (int32_t cc = 0; cc < bj; cc++) {
+            const int64_t c = boff[j] + cc;
+            rows.clear();
+            if (fill) e_col_ptr[c] = nnz;
+            for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; p++) {
+                const int32_t i = row_idx[p];
+                const int32_t bi = blk_size[i];
+                const double *col = values + voff[p] + (int64_t)cc * bi;
+                for (int32_t a = 0; a < bi; a++) {
+                    const int64_t r = boff[i] + a;
+                    if (r != c && !(std::fabs(col[a]) > eps)) continue;
+                    if (fill) {
+                        e_row_idx[nnz] = (int32_t)r;
+                        e_values[nnz] = col[a];
+                        e_src[nnz] = voff[p] + (int64_t)cc * bi + a;
+                    }
+                    rows.push_back((int32_t)r);
+                    nnz++;
+                }
+            }
+            const bool same = merge && cc > 0 && rows == prev_rows;
+            if (!same) {
+                if (fill) e_grp_ptr[ngroups] = (int32_t)c;
+                ngroups++;
+            }
+            if (fill) e_grp_cols[c] = (int32_t)c;
+            prev_rows.swap(rows);
+        }
+    }
+    if (fill) {
+        e_col_ptr[n] = nnz;
+        e_grp_ptr[ngroups] = (int32_t)n;
+    }
+    *n_out = (int32_t)n;
+    *nnz_out = nnz;
+    *ngroups_out = ngroups;
     return SMX_OK;
 }
 

@@ -227,6 +227,9 @@ hipError_t launch_reduce(hipStream_t st, int64_t n, const double *part_e, const 
                          double *out2);
 // out2[0] / out2[1] = number of groups with flag bit 0 / bit 1 set.
 hipError_t launch_count_flags(hipStream_t st, int ngroups, const int32_t *flags, int32_t *out2);
+// dst[0 .. n_dst) = 0, then dst[idx[q]] = src[q] for q < n_src (idx checked on the host).
+hipError_t launch_expand_values(hipStream_t st, int64_t n_src, const int64_t *idx, const double *src, int64_t n_dst,
+                                double *dst);
 
 // Xd_0 = -a I on the true n_g x n_g block (a = 1/s_g), zero elsewhere: the mu tangent
 // of X_0 = (K_sub - mu I) / s_g with s_g frozen.

@@ -623,6 +623,24 @@ hipError_t launch_polish_flags(hipStream_t st, int g0, int ngroups, const IterSt
     return hipGetLastError();
 }
 
+// D in another layout of stored values: dst[idx[q]] = src[q] for every q
+// (dst was cleared before; the host checked that the indices are in range and
+// pairwise distinct).  Grid-stride over q.
+__global__ __launch_bounds__(256)
+void expand_values_kernel(int64_t n, const int64_t *__restrict__ idx, const double *__restrict__ src,
+                          double *__restrict__ dst)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[idx[q]] = src[q];
+}
+
+__global__ __launch_bounds__(256)
+void clear_values_kernel(int64_t n, double *__restrict__ dst)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[q] = 0.0;
+}
+
 hipError_t launch_count_flags(hipStream_t st, int ngroups, const int32_t *flags, int32_t *out2)
 {
     hipLaunchKernelGGL(count_flags_kernel, dim3(1), dim3(1024), 0, st, ngroups, flags, out2);
@@ -648,4 +666,15 @@ hipError_t launch_check_values(hipStream_t st, int64_t nblocks, const int64_t *v
     return hipGetLastError();
 }
 
+hipError_t launch_expand_values(hipStream_t st, int64_t n_src, const int64_t *idx, const double *src, int64_t n_dst,
+                                double *dst)
+{
+    const int64_t nb_dst = std::min<int64_t>((n_dst + 255) / 256, 8192);
+    if (n_dst > 0) hipLaunchKernelGGL(clear_values_kernel, dim3((unsigned)nb_dst), dim3(256), 0, st, n_dst, dst);
+    const int64_t nb = std::min<int64_t>((n_src + 255) / 256, 8192);
+    if (n_src > 0) hipLaunchKernelGGL(expand_values_kernel, dim3((unsigned)nb), dim3(256), 0, st, n_src, idx, src, dst);
+    return hipGetLastError();
+}
+
 }  // namespace smx
+

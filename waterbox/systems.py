@@ -29,6 +29,15 @@ DECAY_LENGTH = 1.5      # K_IJ = exp(-d_IJ / DECAY_LENGTH) * G
 DIAG_SIGMA = 0.05       # std of the symmetric noise on diagonal blocks
 ONSITE = 0.5            # on-site energies alternate -ONSITE / +ONSITE
 
+# Element-wise decay (opt-in, ``elem_decay=True``): every basis function has a
+# range, from compact (core-like) to diffuse, and the off-diagonal element
+# (a, b) of block (I, J) decays as exp(-d_IJ / lambda_ab) with lambda_ab the
+# mean of the two ranges.  Elements whose magnitude falls to ``eps_filter`` or
+# below are set to zero, as the paper's element cutoff does (Sec. V-C, element-
+# wise sparsity of the submatrices); the block pattern is unchanged.
+O_RANGES = (0.2, 0.2, 0.25, 0.25, 0.25, 0.35, 0.35, 0.35, 0.5, 0.5, 0.5, 0.8, 0.8)
+H_RANGES = (0.25, 0.25, 0.35, 0.5, 0.8)
+
 
 @dataclasses.dataclass
 class BlockSparse:
@@ -241,6 +250,10 @@ WATER_CONFIGS = {
     "water256": dict(n_mol=256, box=19.7, r_cut=6.0, seed=4),
     # 6912 molecules, 158976 basis functions
     "water6912": dict(n_mol=6912, box=59.6, r_cut=7.0, seed=5),
+    # element-sparse variants: same geometry, per-function ranges, element cutoff 1e-5
+    "water16e": dict(n_mol=16, box=7.8, r_cut=4.0, seed=1, elem_decay=True, eps_filter=1e-5),
+    "water256e": dict(n_mol=256, box=19.7, r_cut=6.0, seed=4, elem_decay=True, eps_filter=1e-5),
+    "water1024e": dict(n_mol=1024, box=31.3, r_cut=6.0, seed=2, elem_decay=True, eps_filter=1e-5),
 }
 
 
@@ -291,7 +304,8 @@ def _min_image_pairs(pos: np.ndarray, box: float, r_cut: float):
 
 
 def water_system(n_mol: int, box: float, r_cut: float, seed: int,
-                 pattern: str = "cutoff") -> BlockSparse:
+                 pattern: str = "cutoff", elem_decay: bool = False,
+                 eps_filter: float = 0.0) -> BlockSparse:
     """Seeded water-like block-sparse K (one block per atom, groups = molecules).
 
     Recipe (all draws from ``default_rng(seed)``, in this order):
@@ -310,11 +324,15 @@ def water_system(n_mol: int, box: float, r_cut: float, seed: int,
     5. Off-diagonal values: one ``normal(0, 0.1, total)`` call covers all
        stored upper blocks (I < J) in storage order (columns ascending, rows
        ascending), each block column-major; K_IJ = exp(-d_IJ/1.5) * G and
-       K_JI = K_IJ^T.
+       K_JI = K_IJ^T.  With ``elem_decay`` the factor is exp(-d_IJ/lambda_ab)
+       per element instead (lambda_ab the mean of the two basis functions'
+       ranges, O_RANGES / H_RANGES); the draws are the same.
     6. Diagonal blocks: one ``normal(0, 0.05, total)`` call gives the upper
        triangle (diagonal included, column by column) of a symmetric noise
        block for every atom in order; on-site energies are -0.5 Ha for even
        global basis index and +0.5 Ha for odd ones, so exactly n/2 of each.
+    7. Element cutoff: every stored value with magnitude <= eps_filter is
+       set to zero (eps_filter = 0: none).
     """
     rng = np.random.default_rng(seed)
     n_side = 1
@@ -359,8 +377,17 @@ def water_system(n_mol: int, box: float, r_cut: float, seed: int,
     up_off = np.zeros(len(pi) + 1, dtype=np.int64)
     np.cumsum(up_sz, out=up_off[1:])
     g_off = rng.normal(0.0, OFFDIAG_SIGMA, size=int(up_off[-1]))
-    scale = np.repeat(np.exp(-pd / DECAY_LENGTH), up_sz)
-    g_off *= scale
+    if elem_decay:
+        ranges = {O_BLOCK: np.array(O_RANGES), H_BLOCK: np.array(H_RANGES)}
+        for (bsi, bsj) in {(int(x), int(y)) for x, y in zip(bi, bj)}:
+            sel = np.nonzero((bi == bsi) & (bj == bsj))[0]
+            # lambda of element (a, b) of a bsi x bsj block, column-major
+            lam = (0.5 * (ranges[bsi][:, None] + ranges[bsj][None, :])).reshape(-1, order="F")
+            idx = up_off[sel][:, None] + np.arange(bsi * bsj)[None, :]
+            g_off[idx] *= np.exp(-pd[sel][:, None] / lam[None, :])
+    else:
+        scale = np.repeat(np.exp(-pd / DECAY_LENGTH), up_sz)
+        g_off *= scale
 
     # Diagonal noise, upper triangle incl. diagonal, column by column.
     tri = blk_size.astype(np.int64) * (blk_size + 1) // 2
@@ -417,11 +444,14 @@ def water_system(n_mol: int, box: float, r_cut: float, seed: int,
             vals[:, on_diag] += onsite
             values[dst] = vals
 
+    if eps_filter > 0.0:
+        values[np.abs(values) <= eps_filter] = 0.0
+
     grp_ptr = np.arange(0, natom + 1, 3, dtype=np.int32)
     grp_blocks = np.arange(natom, dtype=np.int32)
     out = BlockSparse(blk_size=blk_size, col_ptr=col_ptr, row_idx=all_i.astype(np.int32),
                       values=values, grp_ptr=grp_ptr, grp_blocks=grp_blocks, mu=0.0,
                       coords=pos)
     out.meta = dict(kind="water", n_mol=n_mol, box=box, r_cut=r_cut, seed=seed,
-                    pattern=pattern)
+                    pattern=pattern, elem_decay=elem_decay, eps_filter=eps_filter)
     return out
