@@ -241,6 +241,20 @@ int32_t smx_set_tile_order(smx_ctx ctx, int32_t order);
 int32_t smx_set_kernel_variant(smx_ctx ctx, int32_t variant);
 
 /*
+ * Debug checks (0 off, the default; 1 on), for tracking down indexing errors:
+ * smx_evaluate first validates every plan table on the host against the sizes
+ * it indexes (slab, own-column and row-table offsets, block maps and offsets,
+ * product tiles inside each group's lower triangle, gather chunks, scatter
+ * blocks inside their submatrix; SMX_E_INVALID naming the table), and writes
+ * a 64-KB guard pattern right after the extent the evaluation may write in
+ * the arena, the polish pool and D (device memory the library owns); smx_wait
+ * reads the guards back and returns SMX_E_HIP naming the buffer if a byte
+ * changed.  Results are bitwise those without the checks.  Not applied to
+ * smx_evaluate_static or to a caller work space (smx_set_workspace).
+ */
+int32_t smx_set_debug_checks(smx_ctx ctx, int32_t on);
+
+/*
  * Size buckets of the 2-word FP16 and 1-word BF16 products (the paper
  * balances submatrices of uneven size over workers, Sec. IV-E; here the
  * uneven submatrices of one launch are split by size): groups whose padded

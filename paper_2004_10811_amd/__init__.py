@@ -75,6 +75,7 @@ SIGNATURES = {
     "smx_set_graph": (_i32, [_vp, _i32]),
     "smx_set_tile_order": (_i32, [_vp, _i32]),
     "smx_set_kernel_variant": (_i32, [_vp, _i32]),
+    "smx_set_debug_checks": (_i32, [_vp, _i32]),
     "smx_set_tile_shape": (_i32, [_vp, _i32]),
     "smx_set_iteration": (_i32, [_vp, _i32]),
     "smx_set_solver": (_i32, [_vp, _i32]),
@@ -250,6 +251,10 @@ def smx_set_tile_order(ctx, order=0):
 
 def smx_set_kernel_variant(ctx, variant=0):
     return _check(ctx, load_library().smx_set_kernel_variant(ctx, int(variant)))
+
+
+def smx_set_debug_checks(ctx, on=True):
+    return _check(ctx, load_library().smx_set_debug_checks(ctx, int(bool(on))))
 
 
 def _group_check(st):

@@ -10,6 +10,8 @@
 #include "smx.h"
 #include "smx_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -33,6 +35,39 @@ using namespace smx;
 __device__ __align__(256) unsigned char smx_static_scratch[SMX_STATIC_SCRATCH_BYTES];
 
 namespace {
+
+// Marker ranges (roctx) around the entry points and the phases they enqueue,
+// for rocprofv3 --marker-trace; host-side spans (with host polling the
+// iteration range lasts until the last step is launched).  Ranges still open
+// when the scope ends (an early error return) are closed then.
+struct TraceScope {
+    int depth = 0;
+    TraceScope() = default;
+    explicit TraceScope(const char *name) { push(name); }
+    void push(const char *name)
+    {
+        roctxRangePushA(name);
+        depth++;
+    }
+    void pop()
+    {
+        if (depth > 0) {
+            roctxRangePop();
+            depth--;
+        }
+    }
+    void next(const char *name)
+    {
+        pop();
+        push(name);
+    }
+    ~TraceScope()
+    {
+        while (depth > 0) pop();
+    }
+    TraceScope(const TraceScope &) = delete;
+    TraceScope &operator=(const TraceScope &) = delete;
+};
 
 template <typename T>
 struct DevBuf {
@@ -232,6 +267,8 @@ struct smx_context {
     bool have_tangent = false;                 // last evaluation computed dN/dmu
     bool last_sfix = false;                    // last evaluation ran on the frozen scales
     bool eval_static = false;                  // last evaluation ran in the static scratch array
+    int32_t debug_checks = 0;                  // smx_set_debug_checks
+    bool guards_armed = false;                 // guard regions written before the last evaluation
     double last_mu = 0.0;                      // mu of the last evaluation (the adjoint's A_g)
 
     // step graphs (smx_set_graph)
@@ -1145,6 +1182,15 @@ int32_t smx_set_tile_order(smx_ctx c, int32_t order)
     return SMX_OK;
 }
 
+int32_t smx_set_debug_checks(smx_ctx c, int32_t on)
+{
+    if (!c) return SMX_E_INVALID;
+    if (on != 0 && on != 1) return fail(c, SMX_E_INVALID, "on must be 0 or 1");
+    c->debug_checks = on;
+    c->guards_armed = false;
+    return SMX_OK;
+}
+
 int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
 {
     if (!c) return SMX_E_INVALID;
@@ -1314,8 +1360,123 @@ int32_t ensure_arena(smx_ctx c, bool pool)
 {
     if (c->ws_ptr) return SMX_OK;
     const Plan &P = c->plan;
-    HIP_TRY(c, c->d_arena.ensure((size_t)(arena_bytes(P) / 8)));
-    if (pool) HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1)));
+    const size_t guard = c->debug_checks ? kGuardElems : 0;
+    HIP_TRY(c, c->d_arena.ensure((size_t)(arena_bytes(P) / 8) + guard));
+    if (pool)
+        HIP_TRY(c, c->d_tpool.ensure((size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(P.thin_elems, 1) +
+                                     guard));
+    return SMX_OK;
+}
+
+// ---- debug checks (smx_set_debug_checks) -------------------------------------
+// Host validation of every plan table against the sizes it indexes, and guard
+// regions of kGuardElems doubles, filled with a byte pattern, right after the
+// extent an evaluation may write in the arena, the polish pool and D; smx_wait
+// reads them back and reports any changed byte.
+
+bool plan_tables_valid(const Plan &P, int64_t nnzb, int32_t big_tile, std::string &why)
+{
+    auto bad = [&](const std::string &s) {
+        why = s;
+        return false;
+    };
+    const int32_t ng = P.ngroups;
+    for (int32_t g = 0; g < ng; g++) {
+        const GroupDesc &d = P.gd[g];
+        const std::string tag = "group " + std::to_string(g) + ": ";
+        if (d.npad % 32 || d.n < 1 || d.n > d.npad || d.npad > P.max_npad) return bad(tag + "dimensions");
+        if (d.off < 0 || d.off + (int64_t)d.npad * d.npad > P.work_elems) return bad(tag + "slab beyond the arena");
+        if (d.thin_off < 0 || d.thin_off + (int64_t)d.npad * d.m_own > std::max<int64_t>(P.thin_elems, 1))
+            return bad(tag + "own-column block beyond the pool");
+        if (d.rinfo_off < 0 || d.rinfo_off + d.npad > (int64_t)P.rinfo.size()) return bad(tag + "row table");
+        if (d.own_off < 0 || d.own_off + d.m_own > (int64_t)P.own_list.size() || d.m_own > P.max_own)
+            return bad(tag + "own-column list");
+        for (int32_t c = 0; c < d.m_own; c++)
+            if (P.own_list[d.own_off + c] < 0 || P.own_list[d.own_off + c] >= d.n) return bad(tag + "own column");
+        if (d.map_off < 0 || d.map_off + (int64_t)d.m * d.m > (int64_t)P.bmap.size()) return bad(tag + "block map");
+        for (int64_t q = 0; q < (int64_t)d.m * d.m; q++) {
+            const int32_t v = P.bmap[d.map_off + q];
+            if (v < -1 || v >= nnzb) return bad(tag + "block map entry");
+        }
+        if (d.boff_off < 0 || d.boff_off + d.m + 1 > (int64_t)P.boffs.size()) return bad(tag + "block offsets");
+        if (P.boffs[d.boff_off] != 0 || P.boffs[d.boff_off + d.m] != d.n) return bad(tag + "block offsets");
+        for (int32_t b = 0; b < d.m; b++)
+            if (P.boffs[d.boff_off + b + 1] <= P.boffs[d.boff_off + b]) return bad(tag + "block offsets");
+        for (int32_t r = 0; r < d.n; r++) {
+            const RowInfo ri = P.rinfo[d.rinfo_off + r];
+            if (ri.x < 0 || ri.x >= d.m || (ri.y & 0xffff) >= (ri.y >> 16)) return bad(tag + "row table entry");
+        }
+    }
+    auto tiles_ok = [&](const std::vector<TileDesc> &tl, int tile, const char *name) {
+        for (const TileDesc &td : tl) {
+            if (td.x < 0) continue;                              // idle slot
+            if (td.x >= ng) return bad(std::string(name) + ": group out of range");
+            const int32_t ti = td.y >> 16, tj = td.y & 0xffff, nt = (P.gd[td.x].npad + tile - 1) / tile;
+            if (ti >= nt || tj > ti) return bad(std::string(name) + ": tile outside the lower triangle");
+        }
+        return true;
+    };
+    if (!tiles_ok(P.tiles, kTile, "tiles") || !tiles_ok(P.tiles_s, kTile, "128-tiles") ||
+        !tiles_ok(P.tiles_b, big_tile, "256-tiles"))
+        return false;
+    for (const int2 &ch : P.chunks)
+        if (ch.x < 0 || ch.x >= ng || ch.y < 0 || ch.y >= P.gd[ch.x].npad) return bad("gather chunk out of range");
+    for (size_t q = 0; q < P.scat.size(); q++) {
+        const ScatterDesc &s = P.scat[q];
+        if (s.g < 0 || s.g >= ng) return bad("scatter descriptor " + std::to_string(q) + ": group");
+        const GroupDesc &d = P.gd[s.g];
+        const int32_t bi = s.bij & 0xffff, bj = s.bij >> 16;
+        if (s.oi < 0 || s.oi + bi > d.n || s.oj < 0 || s.oj + bj > d.n || s.ocol < 0 || s.ocol + bj > d.m_own)
+            return bad("scatter descriptor " + std::to_string(q) + ": block outside its submatrix");
+    }
+    return true;
+}
+
+constexpr unsigned char kGuardByte = 0xA5;
+
+int32_t arm_guards(smx_ctx c, bool pool)
+{
+    c->guards_armed = false;
+    if (!c->debug_checks) return SMX_OK;
+    std::string why;
+    if (!plan_tables_valid(c->plan, c->nnzb, kTile2, why)) return fail(c, SMX_E_INVALID, "debug check: plan table: " + why);
+    HIP_TRY(c, c->d_d.ensure((size_t)std::max<int64_t>(c->nvals, 1) + kGuardElems));
+    HIP_TRY(c, hipMemsetAsync(c->d_d.p + c->nvals, kGuardByte, kGuardElems * 8, c->stream));
+    if (!c->ws_ptr) {
+        HIP_TRY(c, hipMemsetAsync(c->d_arena.p + arena_bytes(c->plan) / 8, kGuardByte, kGuardElems * 8, c->stream));
+        if (pool) {
+            const size_t used = (size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(c->plan.thin_elems, 1);
+            HIP_TRY(c, hipMemsetAsync(c->d_tpool.p + used, kGuardByte, kGuardElems * 8, c->stream));
+        }
+    }
+    c->guards_armed = true;
+    return SMX_OK;
+}
+
+int32_t check_guards(smx_ctx c)
+{
+    if (!c->guards_armed) return SMX_OK;
+    c->guards_armed = false;
+    std::vector<unsigned char> h(kGuardElems * 8);
+    struct G {
+        const double *p;
+        const char *name;
+    };
+    std::vector<G> gs = {{c->d_d.p + c->nvals, "D"}};
+    if (!c->ws_ptr) {
+        gs.push_back({c->d_arena.p + arena_bytes(c->plan) / 8, "arena"});
+        if (c->d_tpool.p && c->d_tpool.cap >= (size_t)(2 * c->n_polish + 1) *
+                                                   (size_t)std::max<int64_t>(c->plan.thin_elems, 1) + kGuardElems)
+            gs.push_back({c->d_tpool.p + (size_t)(2 * c->n_polish + 1) * (size_t)std::max<int64_t>(c->plan.thin_elems, 1),
+                          "polish pool"});
+    }
+    for (const G &g : gs) {
+        HIP_TRY(c, hipMemcpy(h.data(), g.p, h.size(), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < h.size(); i++)
+            if (h[i] != kGuardByte)
+                return fail(c, SMX_E_HIP, std::string("debug check: the guard after the ") + g.name +
+                                              " was overwritten at byte " + std::to_string(i));
+    }
     return SMX_OK;
 }
 
@@ -1376,6 +1537,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     it.resid_stride = stride;
     if (c->use_sfix) it.scale_bits = c->d_sfix.p;           // the kernels read the frozen scales
     unsigned long long *gather_scale = c->use_sfix ? c->d_scale_scratch.p : it.scale_bits;
+    TraceScope tr;
     if (events) HIP_TRY(c, hipEventRecord(c->ev_t0, st));
     HIP_TRY(c, hipMemsetAsync(gather_scale, 0, sizeof(unsigned long long) * ng, st));
     HIP_TRY(c, hipMemsetAsync(it.resid_bits, 0, sizeof(unsigned long long) * (size_t)ng * stride, st));
@@ -1448,6 +1610,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         const int nts = (int)(P.tiles_s_beg[wave + 1] - P.tiles_s_beg[wave]);
         const int ntb = (int)(P.tiles_b_beg[wave + 1] - P.tiles_b_beg[wave]);
         const TileDesc *tls = V.tiles_s + P.tiles_s_beg[wave], *tlb = V.tiles_b + P.tiles_b_beg[wave];
+        tr.push("smx gather");
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
         const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
@@ -1464,6 +1627,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         }
         if (tangent) HIP_TRY(c, launch_tangent_init(st, g0, wng, P.max_npad, V.gd, it.scale_bits, tb[0]));
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 1], st));
+        tr.next("smx iterate");
         // one Newton-Schulz step of the wave on stream s (timed: HIP events around
         // each product launch; not inside a graph capture)
         auto step = [&](hipStream_t s, int32_t k, bool time_it) -> hipError_t {
@@ -1573,11 +1737,13 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
             // read from its words (converted exactly on the fly)
             const XSource xs{nullptr, wb[0], wb[1], it.kfinal, fmt, nw};
             int32_t res = -1;
+            tr.next("smx polish");
             if (int32_t e = own_polish(c, P, V, pool, g0, wng, xs, it, &res)) return e;
             thin_result = pool + (size_t)res * (size_t)P.thin_elems;
             HIP_TRY(c, launch_polish_flags(st, g0, wng, it, c->max_iter + c->n_polish, c->tol));
         }
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
+        tr.next("smx scatter");
         const int64_t nsc = nwave > 1 ? P.plist_beg[wave + 1] - P.plist_beg[wave] : c->nnzb;
         const int64_t *pl = nwave > 1 ? V.plist + P.plist_beg[wave] : nullptr;
         if (mixed)
@@ -1589,6 +1755,7 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         if (tangent)
             HIP_TRY(c, launch_own_trace(st, g0, wng, V.gd, V.own, tb[0], tb[1], it.kfinal, c->d_dnp.p));
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
+        tr.pop();
     }
     HIP_TRY(c, launch_reduce(st, c->nnzb, V.pe, V.pn, V.ne));
     if (tangent) HIP_TRY(c, launch_reduce(st, ng, c->d_dnp.p, c->d_dnp.p, c->d_dn.p));
@@ -1698,9 +1865,11 @@ int32_t eig_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView &
     c->launch_wave.clear();
     c->launch_subset.clear();
     for (int32_t wave = 0; wave < P.nwaves(); wave++) {
+        TraceScope tr("smx diagonalise");
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         if (int32_t e = eig_decompose_wave(c, P, V, arena, pool, wave, c->ev_wave[4 * wave + 1])) return e;
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 2], st));
+        tr.next("smx own columns of D");
         if (int32_t e = eig_apply_wave(c, P, V, arena, pool, wave, 0.0)) return e;
         HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave + 3], st));
     }
@@ -1824,6 +1993,7 @@ extern "C" {
 int32_t smx_evaluate(smx_ctx c)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_evaluate");
     EvalMode m;
     if (int32_t st = eval_mode(c, m)) return st;
     if (int32_t st = set_device(c)) return st;
@@ -1831,6 +2001,7 @@ int32_t smx_evaluate(smx_ctx c)
     c->eval_static = false;
     if (int32_t st = eval_prepare(c, m)) return st;
     if (int32_t st = ensure_arena(c, m.mixed || m.eig)) return st;
+    if (int32_t st = arm_guards(c, m.mixed || m.eig)) return st;
     if (m.eig) return eig_enqueue(c, m, c->plan, ctx_view(c), arena_base(c), pool_base(c));
     c->last_eig = false;
     return eval_enqueue(c, m, c->plan, ctx_view(c), arena_base(c), pool_base(c), true, true, true, c->host_poll != 0);
@@ -1840,6 +2011,7 @@ int32_t smx_evaluate(smx_ctx c)
 int32_t smx_evaluate_static(smx_ctx c)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_evaluate_static");
     EvalMode m;
     if (int32_t st = eval_mode(c, m)) return st;
     if (c->use_kfix || c->use_sfix)
@@ -1921,6 +2093,7 @@ int32_t smx_wait(smx_ctx c)
 {
     if (!c) return SMX_E_INVALID;
     if (int32_t st = need_sync_results(c)) return st;
+    if (int32_t st = check_guards(c)) return st;
     int nc = 0, nf = 0;
     if (c->eval_static) {
         int32_t cnt[2] = {0, 0};
@@ -2341,6 +2514,7 @@ int32_t smx_autotune(smx_ctx c, int32_t reps, int32_t use_cache, int32_t *graph_
                      double *best_ms_out)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_autotune");
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (reps < 1 || reps > 100) return fail(c, SMX_E_INVALID, "reps must be 1..100");
     if (int32_t st = set_device(c)) return st;
@@ -2475,6 +2649,7 @@ static int32_t scales_at(smx_ctx c, double mu, std::vector<double> &out)
 int32_t smx_find_mu(smx_ctx c, double n_target, double tol, int32_t max_steps, double *mu_out, int32_t *steps_out)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_find_mu");
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (!mu_out || !(tol > 0.0) || max_steps < 1) return fail(c, SMX_E_INVALID, "need mu_out, tol > 0, max_steps >= 1");
     if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "the mu search runs in SMX_FP64");
@@ -2552,6 +2727,7 @@ int32_t smx_find_mu_eig(smx_ctx c, double n_target, double tol, int32_t max_step
                         int32_t *steps_out)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_find_mu_eig");
     if (!c->loaded) return fail(c, SMX_E_STATE, "smx_load_k must come first");
     if (!mu_out || !(tol > 0.0) || max_steps < 1) return fail(c, SMX_E_INVALID, "need mu_out, tol > 0, max_steps >= 1");
     if (c->precision != SMX_FP64) return fail(c, SMX_E_UNSUPPORTED, "the diagonalisation path runs in SMX_FP64");
@@ -2716,6 +2892,7 @@ int32_t smx_backward(smx_ctx c, double gE, double gN, const double *gD, int32_t 
                      int32_t dK_on_device, double *dmu_out)
 {
     if (!c) return SMX_E_INVALID;
+    TraceScope tr("smx_backward");
     if (!dK_out && !dmu_out) return fail(c, SMX_E_INVALID, "nothing to compute (dK_out and dmu_out are NULL)");
     if (!std::isfinite(gE) || !std::isfinite(gN)) return fail(c, SMX_E_INVALID, "seeds must be finite");
     if (int32_t st = need_group_state(c)) return st;

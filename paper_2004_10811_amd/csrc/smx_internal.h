@@ -168,6 +168,8 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int varian
 // << 16 | tile column) in units of 256; fmt 0 / 1 with nw = 1 or 2 only).
 // Results are bitwise those of the 128 x 128 tiles.
 constexpr int kTile2 = 256;
+// guard region of the debug checks (doubles after the arena, the polish pool and D)
+constexpr size_t kGuardElems = 8192;
 hipError_t launch_ns_words256(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,
                               const GroupDesc *groups, const unsigned short *x, const unsigned short *b,
                               unsigned short *out, const IterState &it, int k, double switch_tol, int kmax);
