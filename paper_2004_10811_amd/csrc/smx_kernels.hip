@@ -10,6 +10,8 @@ namespace smx {
 namespace {
 
 typedef double d2v __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 __device__ inline void atomic_max_nonneg(unsigned long long *addr, double v)
 {
@@ -170,8 +172,14 @@ __device__ inline int64_t x_col_stride(int ld)
     return (int64_t)ld * ((K == X_F64 || K == X_F32) ? 1 : x_nw<K>());
 }
 
-// X[r, c] and X[r + 1, c] (r even) at offset e = x_row(r) + c * x_col_stride(ld).
+// Power-of-two scale of the stored words (FP16 words hold x * 2^15).
 template <int K>
+__device__ constexpr double x_word_scale() { return K == X_F16x2 ? 1.0 / 32768.0 : 1.0; }
+
+// X[r, c] and X[r + 1, c] (r even) at offset e = x_row(r) + c * x_col_stride(ld);
+// UNSCALED: without the factor x_word_scale (the caller applies it exactly,
+// e.g. to the other operand of a product).
+template <int K, bool UNSCALED = false>
 __device__ inline d2v x_pair(const void *base, int64_t e)
 {
     if constexpr (K == X_F64) {
@@ -182,15 +190,20 @@ __device__ inline d2v x_pair(const void *base, int64_t e)
     } else {
         const unsigned short *w = reinterpret_cast<const unsigned short *>(base);
         constexpr int NW = x_nw<K>();
-        d2v v = {0.0, 0.0};
+        d2v v;
 #pragma unroll
         for (int q = NW - 1; q >= 0; q--) {
             const unsigned int u = *reinterpret_cast<const unsigned int *>(w + 32 * q + e);
             const unsigned short lo = (unsigned short)(u & 0xffffu), hi = (unsigned short)(u >> 16);
-            v.x += K == X_F16x2 ? f16w(lo) : bf16w(lo);
-            v.y += K == X_F16x2 ? f16w(hi) : bf16w(hi);
+            const double a = K == X_F16x2 ? f16w(lo) : bf16w(lo), b = K == X_F16x2 ? f16w(hi) : bf16w(hi);
+            if (q == NW - 1) {
+                v = d2v{a, b};
+            } else {
+                v.x += a;
+                v.y += b;
+            }
         }
-        if constexpr (K == X_F16x2) v *= (1.0 / 32768.0);
+        if constexpr (K == X_F16x2 && !UNSCALED) v *= x_word_scale<K>();
         return v;
     }
 }
@@ -245,7 +258,9 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
             for (int t = threadIdx.x; t < KC * MW; t += 256) {
                 const int kk = t % KC, cc = t / KC;
                 const int kr = k0 + kk;
-                zs[kk][cc] = (kr < gd.n && cc < nc) ? z[gd.thin_off + kr + (int64_t)(c0 + cc) * npad] : 0.0;
+                // the word scale goes onto z (a power of two: every product is unchanged)
+                zs[kk][cc] = (kr < gd.n && cc < nc) ? z[gd.thin_off + kr + (int64_t)(c0 + cc) * npad] * x_word_scale<K>()
+                                                    : 0.0;
             }
             __syncthreads();
             const int kend = min(KC, gd.n - k0);
@@ -255,7 +270,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                 for (; kk + U <= kend; kk += U) {
                     d2v xv[U];
 #pragma unroll
-                    for (int u = 0; u < U; u++) xv[u] = x_pair<K>(xg, e0 + (int64_t)(kk + u) * cs);
+                    for (int u = 0; u < U; u++) xv[u] = x_pair<K, true>(xg, e0 + (int64_t)(kk + u) * cs);
 #pragma unroll
                     for (int u = 0; u < U; u++)
 #pragma unroll
@@ -268,7 +283,7 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                         }
                 }
                 for (; kk < kend; kk++) {
-                    const d2v xv = x_pair<K>(xg, e0 + (int64_t)kk * cs);
+                    const d2v xv = x_pair<K, true>(xg, e0 + (int64_t)kk * cs);
 #pragma unroll
                     for (int c = 0; c < MW; c += 2) {
                         const d2v zv = *reinterpret_cast<const d2v *>(&zs[kk][c]);
@@ -292,6 +307,154 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
                 }
                 *reinterpret_cast<d2v *>(y + idx) = v;
             }
+        }
+    }
+}
+
+// The same thin products on the matrix cores (v_mfma_f64_16x16x4_f64, FP64)
+// for a bulk result held as words or FP32.  X is symmetric, so row r of X is
+// its column r, whose K-consecutive entries are contiguous: a lane reads 8
+// consecutive rows of one column per word (one 16-B load each; eight values
+// per 16 B for FP32 reads two) and the wave's output rows need no LDS for
+// X.  Wave w of a workgroup owns output rows 32 w .. + 31 of the workgroup's
+// 128 (two 16-row blocks b) and 32 output columns per pass (two 16-column
+// blocks), 4 accumulators of 16 x 16.  Per K step of 32: lane l supplies, for
+// product t (0 .. 7), A[i][kk] = X[r0 + 16 b + l % 16, k0 + 8 kk + t] with
+// kk = l / 16 and B[kk][j] = Z[k0 + 8 kk + t, 16 cb + l % 16] from LDS, so the
+// eight products of a block cover its 32 K values once.  Z goes to LDS 128
+// rows at a time with the storage's power-of-two word scale on it (every
+// product unchanged, the words are read unscaled).  The next K step's words
+// are loaded while the matrix cores work on the current one.  Rows of Z at
+// or beyond n are zero (X's padding never contributes); output rows at or
+// beyond n come out exactly zero (identity padding times zero rows of Z).
+template <int K>
+__device__ constexpr int tm_loads() { return K == X_F32 ? 2 : x_nw<K>(); }
+// 16-row blocks per wave: two keep the kernel at three waves per SIMD (four
+// took two waves per SIMD and ran 0.9% slower per D on water1024)
+constexpr int kThinRB = 2;
+constexpr int kThinRows = 64 * kThinRB;                // output rows per workgroup
+
+// Element t (0 .. 7) of the 8 consecutive rows a lane loaded, as the unscaled
+// FP64 sum of its words (exact).
+template <int K>
+__device__ inline double tm_value(const u4 *raw, int t)
+{
+    if constexpr (K == X_F32) {
+        const unsigned int u = raw[t >> 2][t & 3];
+        return (double)__builtin_bit_cast(float, u);
+    } else {
+        constexpr int NW = x_nw<K>();
+        double v = 0.0;
+#pragma unroll
+        for (int w = NW - 1; w >= 0; w--) {
+            const unsigned int u = raw[w][t >> 1];
+            const unsigned short h = (t & 1) ? (unsigned short)(u >> 16) : (unsigned short)(u & 0xffffu);
+            const double a = K == X_F16x2 ? f16w(h) : bf16w(h);
+            v = (w == NW - 1) ? a : v + a;
+        }
+        return v;
+    }
+}
+
+template <int MODE, int K>
+__global__ __launch_bounds__(256)
+void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const double *__restrict__ z,
+                      const double *__restrict__ o, double *__restrict__ y, int g0)
+{
+    constexpr int KC = 128;                           // rows of Z per LDS stage
+    constexpr int ZS = 33;                            // LDS row stride of the staged Z (doubles)
+    constexpr int NL = tm_loads<K>();
+    constexpr int RB = kThinRB;
+    __shared__ double zs[KC * ZS];
+    const int g = g0 + blockIdx.y;
+    const GroupDesc gd = groups[g];
+    const int npad = gd.npad;
+    const int row0 = blockIdx.x * (64 * RB);
+    if (row0 >= npad) return;                         // whole workgroup beyond this group
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rw = row0 + 16 * RB * wave;             // first output row of this wave
+    const bool live = rw < npad;                      // wave-uniform
+    const int li = lane & 15, q = lane >> 4;
+    const void *xg = x_base<K>(xs, gd, g);
+    // word layout: column c starts at c * npad * NW halves, K step s at s * 32 * NW, word w at + 32 w
+    auto src = [&](int b, int k0, int w) -> const u4 * {
+        const int c = min(rw + 16 * b + li, npad - 1);    // rows beyond n_pad are never stored
+        if constexpr (K == X_F32)
+            return reinterpret_cast<const u4 *>(reinterpret_cast<const float *>(xg) + (int64_t)c * npad + k0 + 8 * q +
+                                                4 * w);
+        else
+            return reinterpret_cast<const u4 *>(reinterpret_cast<const unsigned short *>(xg) +
+                                                (int64_t)c * npad * x_nw<K>() + (int64_t)k0 * x_nw<K>() + 32 * w + 8 * q);
+    };
+    constexpr double zscale = x_word_scale<K>();
+    const int nk = npad / 32;
+    for (int c0 = 0; c0 < gd.m_own; c0 += 32) {
+        f64x4 acc[RB][2];
+#pragma unroll
+        for (int b = 0; b < RB; b++)
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++) acc[b][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+        u4 ra[RB][NL], rb[RB][NL];
+        if (live) {
+#pragma unroll
+            for (int b = 0; b < RB; b++)
+#pragma unroll
+                for (int w = 0; w < NL; w++) ra[b][w] = *src(b, 0, w);
+        }
+        // one K step with the words in rc, the next step's loaded into rn
+        auto kstep = [&](int kt, u4 (&rc)[RB][NL], u4 (&rn)[RB][NL]) {
+            if (kt % (KC / 32) == 0) {
+                const int ks = kt * 32;
+                __syncthreads();                      // every wave is done with the previous stage
+                for (int u = tid; u < KC * 32; u += 256) {
+                    const int kk = u >> 5, cc = u & 31, kr = ks + kk, col = c0 + cc;
+                    zs[kk * ZS + cc] = (kr < gd.n && col < gd.m_own) ? z[gd.thin_off + kr + (int64_t)col * npad] * zscale
+                                                                     : 0.0;
+                }
+                __syncthreads();
+            }
+            if (!live) return;
+            if (kt + 1 < nk) {
+#pragma unroll
+                for (int b = 0; b < RB; b++)
+#pragma unroll
+                    for (int w = 0; w < NL; w++) rn[b][w] = *src(b, (kt + 1) * 32, w);
+            }
+            const double *zr = zs + ((kt % (KC / 32)) * 32 + 8 * q) * ZS + li;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const double b0 = zr[t * ZS], b1 = zr[t * ZS + 16];
+#pragma unroll
+                for (int b = 0; b < RB; b++) {
+                    const double a = tm_value<K>(rc[b], t);
+                    acc[b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[b][0], 0, 0, 0);
+                    acc[b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[b][1], 0, 0, 0);
+                }
+            }
+        };
+        for (int kt = 0; kt < nk; kt += 2) {
+            kstep(kt, ra, rb);
+            if (kt + 1 < nk) kstep(kt + 1, rb, ra);
+        }
+        if (live) {
+            // lane l, register v of block (b, cb): row 16 b + l / 16 + 4 v, column 16 cb + l % 16
+#pragma unroll
+            for (int b = 0; b < RB; b++)
+#pragma unroll
+                for (int cb = 0; cb < 2; cb++) {
+                    const int col = c0 + 16 * cb + li;
+                    if (col >= gd.m_own) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int r = rw + 16 * b + q + 4 * v;
+                        if (r >= npad) continue;
+                        const int64_t idx = gd.thin_off + r + (int64_t)col * npad;
+                        double val = acc[b][cb][v];
+                        if (MODE == 1) val = 1.5 * o[idx] - 0.5 * val;
+                        y[idx] = val;
+                    }
+                }
         }
     }
 }
@@ -584,14 +747,26 @@ hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int ma
     if (ngroups <= 0 || max_own <= 0) return hipSuccess;
     const dim3 grid((unsigned)((max_npad + 511) / 512), (unsigned)ngroups);
     const int mw = max_own <= 8 ? 8 : (max_own <= 16 ? 16 : (max_own <= 24 ? 24 : 32));
+    // the bulk's words (or FP32 values) go through the matrix cores; an FP64
+    // slab through the vector units
+    const dim3 grid_m((unsigned)((max_npad + kThinRows - 1) / kThinRows), (unsigned)ngroups);
+#define SMX_TMM(KK)                                                                                          \
+    do {                                                                                                     \
+        if (mode == 0)                                                                                       \
+            hipLaunchKernelGGL((thin_mfma_kernel<0, KK>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((thin_mfma_kernel<1, KK>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+        return hipGetLastError();                                                                            \
+    } while (0)
     switch (x_kind(xs)) {
     case X_F64: return thin_mul_k<X_F64>(st, mode, mw, grid, g0, groups, xs, z, o, y);
-    case X_F16x2: return thin_mul_k<X_F16x2>(st, mode, mw, grid, g0, groups, xs, z, o, y);
-    case X_BF16x3: return thin_mul_k<X_BF16x3>(st, mode, mw, grid, g0, groups, xs, z, o, y);
-    case X_BF16x1: return thin_mul_k<X_BF16x1>(st, mode, mw, grid, g0, groups, xs, z, o, y);
-    case X_F32: return thin_mul_k<X_F32>(st, mode, mw, grid, g0, groups, xs, z, o, y);
+    case X_F16x2: SMX_TMM(X_F16x2);
+    case X_BF16x3: SMX_TMM(X_BF16x3);
+    case X_BF16x1: SMX_TMM(X_BF16x1);
+    case X_F32: SMX_TMM(X_F32);
     default: return hipErrorInvalidValue;
     }
+#undef SMX_TMM
 }
 
 hipError_t launch_thin_combine(hipStream_t st, int g0, int ngroups, int max_npad, int max_own,
