@@ -370,10 +370,10 @@ def main():
     achieved = kfl / (kms * 1e-3) / 1e12
     bound, unit = "mfma", "TFLOP/s"
     if kname == "tridiag_kernel":
-        # BLAS2-bound: each reduction step reads and writes the trailing block once
-        # at least, 16 n^3 / 3 bytes per group = 4 bytes per counted flop (4/3 n^3)
+        # BLAS2-bound: each reduction step reads the trailing block at least once
+        # (p = tau A22 v), 8 n^3 / 3 bytes per group = 2 bytes per counted flop (4/3 n^3)
         bound, unit = "hbm", "GB/s"
-        achieved = 4.0 * kfl / (kms * 1e-3) / 1e9
+        achieved = 2.0 * kfl / (kms * 1e-3) / 1e9
     traffic, traffic_src, busy = measured_traffic(args.workload, kname)
     roofline = {
         "bound": bound,

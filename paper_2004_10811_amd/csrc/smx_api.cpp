@@ -1810,7 +1810,7 @@ int32_t eig_decompose_wave(smx_ctx c, const Plan &P, const DevView &V, double *a
             c->ev_launch.push_back(evt);
         }
         HIP_TRY(c, hipEventRecord(c->ev_launch[2 * idx], st));
-        HIP_TRY(c, launch_eig_tridiag(st, g0, wng, V.gd, a, ev));
+        HIP_TRY(c, launch_eig_tridiag(st, g0, wng, V.gd, a, s, ev));     // s is free until the eigenvectors
         HIP_TRY(c, hipEventRecord(c->ev_launch[2 * idx + 1], st));
         c->launch_step.push_back(0);
         c->launch_kind.push_back(12);

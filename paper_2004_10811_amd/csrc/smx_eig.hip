@@ -53,62 +53,180 @@ __device__ inline double wave_sum0(double v)
 // ---- 1. Householder tridiagonalisation --------------------------------------
 // Step k (0 <= k < n - 2): x = A[k+1:, k]; the reflector H_k = I - tau v v^T
 // (v_0 = 1) maps x to beta e_1 (beta = -sign(x_0) ||x||, tau = (beta - x_0) /
-// beta); then with p = tau A22 v and w = p - (tau / 2)(p^T v) v the trailing
-// block becomes A22 - v w^T - w v^T.  d_k = A_kk, e_k = beta; v is stored in
+// beta); with p = tau A22 v and w = p - (tau / 2)(p^T v) v the trailing block
+// becomes A22 - v w^T - w v^T.  d_k = A_kk, e_k = beta; v is stored in
 // A[k+1:, k].  A is column-major with leading dimension n_pad (full storage).
+//
+// Blocked as in LAPACK's sytrd: the steps of a panel of kPanel columns leave
+// the trailing block as it was at the panel's start (A_s) and keep their
+// vectors V (in A's columns) and W (n_pad x kPanel, in the second slab); a
+// step first brings its own column up to date, A[:, k] -= V W[k, :]^T + W
+// V[k, :]^T, and forms p = tau (A_s v - V (W^T v) - W (V^T v)); after the
+// panel one pass applies A22 -= V W^T + W V^T to the trailing block.  Each
+// step then reads the trailing block once instead of reading it twice and
+// writing it once.
+// sum over columns jj in [jb, je) of row[jj * ld] * v[jj], with eight partial
+// sums in flight (eight independent loads per lane) added in a fixed order
+__device__ inline double row_dot(const double *__restrict__ row, int ld, const double *v, int jb, int je)
+{
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int jj = jb;
+    for (; jj + 7 < je; jj += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) a[u] += row[(int64_t)(jj + u) * ld] * v[jj + u];
+    }
+    for (; jj < je; jj++) a[0] += row[(int64_t)jj * ld] * v[jj];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+constexpr int kPanel = 16;
+constexpr int kTrailCols = 64;      // columns of V and W rows staged per trailing-update pass
+
 __global__ __launch_bounds__(kEigBlock)
-void tridiag_kernel(const GroupDesc *__restrict__ groups, int g0, double *__restrict__ abase, EigVecs ev)
+void tridiag_kernel(const GroupDesc *__restrict__ groups, int g0, double *__restrict__ abase,
+                    double *__restrict__ wbase, EigVecs ev)
 {
     __shared__ double vs[kEigMaxN];
     __shared__ double ws[kEigMaxN];
     __shared__ double red[kEigBlock / 64];
+    __shared__ double rowk[2 * kPanel];               // V[k, t], W[k, t] of the panel's earlier steps
+    __shared__ double dots[2 * kPanel];               // W[:, t]^T v, V[:, t]^T v
+    __shared__ double vwc[kTrailCols][2 * kPanel];    // V[c, t], W[c, t] of a run of trailing columns
+    __shared__ double psum[kEigBlock];                // column-part sums of A_s v
     const int g = g0 + blockIdx.x;
     const GroupDesc gd = groups[g];
     const int n = gd.n, ld = gd.npad, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     double *A = abase + gd.off;
+    double *W = wbase + gd.off;                       // W[:, t] at W + t * ld (kPanel <= 32 <= n_pad)
     double *d = ev.d + gd.rinfo_off, *e = ev.e + gd.rinfo_off, *tau = ev.tau + gd.rinfo_off;
-    for (int k = 0; k + 2 < n; k++) {
-        double *col = A + (int64_t)k * ld;
-        const double x0 = col[k + 1];             // read by every lane before the barrier in
-        double part = 0.0;                        // block_sum; lane 0 overwrites it with v_0 below
-        for (int i = k + 2 + tid; i < n; i += kEigBlock) part += col[i] * col[i];
-        const double sigma = block_sum(part, red);
-        double beta = x0, t = 0.0, sc = 0.0;
-        if (sigma > 0.0) {
-            const double nrm = sqrt(x0 * x0 + sigma);
-            beta = x0 >= 0.0 ? -nrm : nrm;
-            t = (beta - x0) / beta;
-            sc = 1.0 / (x0 - beta);
-        }
-        for (int i = k + 1 + tid; i < n; i += kEigBlock) {
-            const double vi = (i == k + 1) ? 1.0 : col[i] * sc;
-            vs[i] = vi;
-            col[i] = vi;
-        }
-        if (tid == 0) {
-            d[k] = col[k];
-            e[k] = beta;
-            tau[k] = t;
-        }
-        __syncthreads();
-        if (t != 0.0) {
-            // p = tau A22 v: lane i owns row i; for each column j the lanes read
-            // consecutive rows (coalesced)
-            for (int i = k + 1 + tid; i < n; i += kEigBlock) {
-                double s = 0.0;
-                for (int j = k + 1; j < n; j++) s += A[i + (int64_t)j * ld] * vs[j];
-                ws[i] = t * s;
+    for (int kp = 0; kp + 2 < n; kp += kPanel) {
+        const int nb = min(kPanel, n - 2 - kp);
+        const double *V = A + (int64_t)kp * ld;       // V[:, t] = A[:, kp + t] below its subdiagonal
+        bool any = false;                             // a reflector of the panel is not the identity
+        for (int j = 0; j < nb; j++) {
+            const int k = kp + j;
+            double *col = A + (int64_t)k * ld;
+            // column k (rows k ..) up to date with the panel's steps 0 .. j - 1
+            if (tid < j) {
+                rowk[tid] = V[k + (int64_t)tid * ld];
+                rowk[kPanel + tid] = W[k + (int64_t)tid * ld];
             }
             __syncthreads();
-            double pv = 0.0;
-            for (int i = k + 1 + tid; i < n; i += kEigBlock) pv += ws[i] * vs[i];
-            const double kk = -0.5 * t * block_sum(pv, red);
-            for (int i = k + 1 + tid; i < n; i += kEigBlock) ws[i] += kk * vs[i];
+            if (j > 0)
+                for (int i = k + tid; i < n; i += kEigBlock) {
+                    double s = col[i];
+                    for (int q = 0; q < j; q++)
+                        s -= V[i + (int64_t)q * ld] * rowk[kPanel + q] + W[i + (int64_t)q * ld] * rowk[q];
+                    col[i] = s;
+                }
             __syncthreads();
-            for (int j = k + 1; j < n; j++) {
-                const double vj = vs[j], wj = ws[j];
-                double *cj = A + (int64_t)j * ld;
-                for (int i = k + 1 + tid; i < n; i += kEigBlock) cj[i] -= vs[i] * wj + ws[i] * vj;
+            const double x0 = col[k + 1];             // read by every lane before the barrier in
+            double part = 0.0;                        // block_sum; lane 0 overwrites it with v_0 below
+            for (int i = k + 2 + tid; i < n; i += kEigBlock) part += col[i] * col[i];
+            const double sigma = block_sum(part, red);
+            double beta = x0, tk = 0.0, sc = 0.0;
+            if (sigma > 0.0) {
+                const double nrm = sqrt(x0 * x0 + sigma);
+                beta = x0 >= 0.0 ? -nrm : nrm;
+                tk = (beta - x0) / beta;
+                sc = 1.0 / (x0 - beta);
+            }
+            for (int i = k + 1 + tid; i < n; i += kEigBlock) {
+                const double vi = (i == k + 1) ? 1.0 : col[i] * sc;
+                vs[i] = vi;
+                col[i] = vi;
+            }
+            if (tid == 0) {
+                d[k] = col[k];
+                e[k] = beta;
+                tau[k] = tk;
+            }
+            __syncthreads();
+            double *wj = W + (int64_t)j * ld;
+            any = any || tk != 0.0;                   // the same in every lane
+            if (tk != 0.0) {
+                // W[:, q]^T v and V[:, q]^T v over rows k + 1 .., one wave per product
+                for (int q = wave; q < 2 * j; q += kEigBlock / 64) {
+                    const double *src = q < j ? W + (int64_t)q * ld : V + (int64_t)(q - j) * ld;
+                    double s = 0.0;
+                    for (int i = k + 1 + lane; i < n; i += 64) s += src[i] * vs[i];
+                    s = wave_sum0(s);
+                    if (lane == 0) dots[q] = s;
+                }
+                __syncthreads();
+                // p = tau (A_s v - V (W^T v) - W (V^T v)).  A_s v: the lanes of a
+                // row slot read consecutive rows of a column (coalesced); while the
+                // trailing block has at most 1024 rows, the columns are split into
+                // kEigBlock / (rows rounded up to 64) parts so every lane streams,
+                // and the parts' sums are added in order
+                const int R = n - k - 1;
+                if (R <= kEigBlock) {
+                    const int RS = (R + 63) & ~63, P = kEigBlock / RS;
+                    const int sl = tid % RS, part = tid / RS;
+                    if (part < P) {
+                        double acc = 0.0;
+                        if (sl < R) {
+                            const int i = k + 1 + sl, cl = (R + P - 1) / P;
+                            const int jb = k + 1 + part * cl, je = min(n, jb + cl);
+                            acc = row_dot(A + i, ld, vs, jb, je);
+                        }
+                        psum[part * RS + sl] = acc;
+                    }
+                    __syncthreads();
+                    for (int sl2 = tid; sl2 < R; sl2 += kEigBlock) {
+                        double s = 0.0;
+                        for (int pp = 0; pp < P; pp++) s += psum[pp * RS + sl2];
+                        const int i = k + 1 + sl2;
+                        for (int q = 0; q < j; q++)
+                            s -= V[i + (int64_t)q * ld] * dots[q] + W[i + (int64_t)q * ld] * dots[j + q];
+                        ws[i] = tk * s;
+                    }
+                } else {
+                    for (int i = k + 1 + tid; i < n; i += kEigBlock) {
+                        double s = row_dot(A + i, ld, vs, k + 1, n);
+                        for (int q = 0; q < j; q++)
+                            s -= V[i + (int64_t)q * ld] * dots[q] + W[i + (int64_t)q * ld] * dots[j + q];
+                        ws[i] = tk * s;
+                    }
+                }
+                __syncthreads();
+                double pv = 0.0;
+                for (int i = k + 1 + tid; i < n; i += kEigBlock) pv += ws[i] * vs[i];
+                const double kk = -0.5 * tk * block_sum(pv, red);
+                for (int i = k + 1 + tid; i < n; i += kEigBlock) wj[i] = ws[i] + kk * vs[i];
+            } else {
+                for (int i = k + 1 + tid; i < n; i += kEigBlock) wj[i] = 0.0;
+            }
+            __syncthreads();
+        }
+        // trailing block (rows and columns from k1 on): A -= V W^T + W V^T over the panel
+        const int k1 = kp + nb;
+        for (int c0 = k1; any && c0 < n; c0 += kTrailCols) {
+            const int ncol = min(kTrailCols, n - c0);
+            __syncthreads();
+            for (int u = tid; u < kTrailCols * 2 * kPanel; u += kEigBlock) {
+                const int cl = u / (2 * kPanel), q = u % (2 * kPanel);
+                const int qq = q % kPanel;
+                double v = 0.0;
+                if (cl < ncol && qq < nb) v = (q < kPanel ? V : W)[c0 + cl + (int64_t)qq * ld];
+                vwc[cl][q] = v;
+            }
+            __syncthreads();
+            for (int r = k1 + tid; r < n; r += kEigBlock) {
+                double vr[kPanel], wr[kPanel];
+#pragma unroll
+                for (int q = 0; q < kPanel; q++) {
+                    vr[q] = q < nb ? V[r + (int64_t)q * ld] : 0.0;
+                    wr[q] = q < nb ? W[r + (int64_t)q * ld] : 0.0;
+                }
+                for (int cl = 0; cl < ncol; cl++) {
+                    double *ac = A + r + (int64_t)(c0 + cl) * ld;
+                    double s = *ac;
+#pragma unroll
+                    for (int q = 0; q < kPanel; q++) s -= vr[q] * vwc[cl][kPanel + q] + wr[q] * vwc[cl][q];
+                    *ac = s;
+                }
             }
         }
         __syncthreads();
@@ -584,10 +702,10 @@ void n_reduce_kernel(int ng, int nmu, const double *__restrict__ part, double *_
 }  // namespace
 
 hipError_t launch_eig_tridiag(hipStream_t st, int g0, int ngroups, const GroupDesc *groups, double *a,
-                              const EigVecs &ev)
+                              double *wpanel, const EigVecs &ev)
 {
     if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tridiag_kernel, dim3((unsigned)ngroups), dim3(kEigBlock), 0, st, groups, g0, a, ev);
+    hipLaunchKernelGGL(tridiag_kernel, dim3((unsigned)ngroups), dim3(kEigBlock), 0, st, groups, g0, a, wpanel, ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(split_kernel, dim3((unsigned)((ngroups + 63) / 64)), dim3(64), 0, st, groups, g0, ngroups, ev);

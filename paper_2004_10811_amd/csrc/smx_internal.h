@@ -264,8 +264,9 @@ struct EigVecs {
 
 // Householder reduction of each group's slab (A_g - mu0 I, column-major) to
 // tridiagonal form, reflectors left below the subdiagonal; then the split.
+// wpanel: a second slab (n_pad x 16 of each group's place used as panel work).
 hipError_t launch_eig_tridiag(hipStream_t st, int g0, int ngroups, const GroupDesc *groups, double *a,
-                              const EigVecs &ev);
+                              double *wpanel, const EigVecs &ev);
 // Eigenvalues (bisection) and eigenvectors (twisted factorisations, then
 // Gram-Schmidt inside tight clusters) of T: s[i * n_pad + l] = component i of
 // eigenvector l; scratch: one more slab.
