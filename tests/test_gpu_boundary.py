@@ -142,3 +142,26 @@ def test_history_matches_oracle(smx, oracle_lib, precision):
             assert t[-1] <= 1e-3 < t[-2]
         print(f"{precision} group {g}: {n} steps, resid {r[0]:.3e} -> {r[-1]:.3e}"
               + ("" if precision == "fp64" else f", tau {h['tau'][g, 0]:.3e} -> {h['tau'][g, n - 1]:.3e}"))
+
+
+@pytest.mark.parametrize("precision,npairs", [("fp64", 1), ("fp16x2", 3), ("bf16x3", 6)])
+def test_launch_issued_flops_accounting(smx, precision, npairs):
+    """smx_get_launch_issued on one group of n = 368 (n_pad = 384, three 128-row
+    tiles): every launch that works on the group issues 21 live 64 x 64 wave tiles
+    (3 x 3 in the diagonal tiles, 3 x 4 below them) of 2 x 64 x 64 x n_pad flops,
+    times the word products per algorithmic product; the others issue nothing."""
+    s = water_config("water16")
+    one = s.with_groups([list(range(s.nblk))])
+    ctx = smx.Context(0).load(one).configure(precision=precision)
+    ctx.evaluate()
+    ms, algo, kind = ctx.launch_profile()
+    issued = smx.smx_get_launch_issued(ctx.handle)
+    ctx.close()
+    assert len(issued) == len(algo) > 0
+    n, npad = 368, 384
+    per = 21 * 2.0 * 64 * 64 * npad * npairs
+    for a, q in zip(algo, issued):
+        if a > 0:
+            assert a == 2.0 * n ** 3 and q == per
+        else:
+            assert q == 0.0

@@ -159,11 +159,15 @@ def test_error_paths(smx):
         smx.smx_evaluate(ctx.handle)
     assert e.value.code == smx.SMX_E_STATE
     ctx.load(s)
-    # finite temperature is not implemented on the GPU
+    # finite temperature diagonalises in FP64; a reduced-precision mode is refused
     smx.smx_set_temperature(ctx.handle, 0.01)
+    smx.smx_set_precision(ctx.handle, smx.SMX_FP16_2W)
     with pytest.raises(smx.SmxError) as e:
         smx.smx_evaluate(ctx.handle)
     assert e.value.code == smx.SMX_E_UNSUPPORTED
+    smx.smx_set_precision(ctx.handle, smx.SMX_FP64)
+    r = ctx.evaluate()
+    assert r.status == smx.SMX_OK and np.all(np.isfinite(r.d_values))
     smx.smx_set_temperature(ctx.handle, 0.0)
     # bad groups
     with pytest.raises(smx.SmxError) as e:
