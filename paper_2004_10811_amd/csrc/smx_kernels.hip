@@ -317,8 +317,8 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
 // consecutive rows of one column per word (one 16-B load each; eight values
 // per 16 B for FP32 reads two) and the wave's output rows need no LDS for
 // X.  Wave w of a workgroup owns output rows 32 w .. + 31 of the workgroup's
-// 128 (two 16-row blocks b) and 32 output columns per pass (two 16-column
-// blocks), 4 accumulators of 16 x 16.  Per K step of 32: lane l supplies, for
+// 128 (two 16-row blocks b) and 16 CB output columns per pass (CB 16-column
+// blocks: one when every group owns at most 16 columns, else two).  Per K step of 32: lane l supplies, for
 // product t (0 .. 7), A[i][kk] = X[r0 + 16 b + l % 16, k0 + 8 kk + t] with
 // kk = l / 16 and B[kk][j] = Z[k0 + 8 kk + t, 16 cb + l % 16] from LDS, so the
 // eight products of a block cover its 32 K values once.  Z goes to LDS 128
@@ -356,7 +356,7 @@ __device__ inline double tm_value(const u4 *raw, int t)
     }
 }
 
-template <int MODE, int K>
+template <int MODE, int K, int CB>
 __global__ __launch_bounds__(256)
 void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const double *__restrict__ z,
                       const double *__restrict__ o, double *__restrict__ y, int g0)
@@ -389,12 +389,12 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
     };
     constexpr double zscale = x_word_scale<K>();
     const int nk = npad / 32;
-    for (int c0 = 0; c0 < gd.m_own; c0 += 32) {
-        f64x4 acc[RB][2];
+    for (int c0 = 0; c0 < gd.m_own; c0 += 16 * CB) {
+        f64x4 acc[RB][CB];
 #pragma unroll
         for (int b = 0; b < RB; b++)
 #pragma unroll
-            for (int cb = 0; cb < 2; cb++) acc[b][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int cb = 0; cb < CB; cb++) acc[b][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
         u4 ra[RB][NL], rb[RB][NL];
         if (live) {
 #pragma unroll
@@ -424,12 +424,15 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
             const double *zr = zs + ((kt % (KC / 32)) * 32 + 8 * q) * ZS + li;
 #pragma unroll
             for (int t = 0; t < 8; t++) {
-                const double b0 = zr[t * ZS], b1 = zr[t * ZS + 16];
+                double bz[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; cb++) bz[cb] = zr[t * ZS + 16 * cb];
 #pragma unroll
                 for (int b = 0; b < RB; b++) {
                     const double a = tm_value<K>(rc[b], t);
-                    acc[b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[b][0], 0, 0, 0);
-                    acc[b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[b][1], 0, 0, 0);
+#pragma unroll
+                    for (int cb = 0; cb < CB; cb++)
+                        acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz[cb], acc[b][cb], 0, 0, 0);
                 }
             }
         };
@@ -442,7 +445,7 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
 #pragma unroll
             for (int b = 0; b < RB; b++)
 #pragma unroll
-                for (int cb = 0; cb < 2; cb++) {
+                for (int cb = 0; cb < CB; cb++) {
                     const int col = c0 + 16 * cb + li;
                     if (col >= gd.m_own) continue;
 #pragma unroll
@@ -541,17 +544,16 @@ void count_flags_kernel(int ngroups, const int32_t *__restrict__ flags, int32_t 
 }
 
 // Fixed-order sum of the per-block partials (one workgroup): deterministic.
+// Lane t adds the entries t, t + 1024, t + 2048, ... in that order (a wave
+// reads 512 consecutive bytes per step), then a fixed tree.
 __global__ __launch_bounds__(1024)
 void reduce_kernel(int64_t n, const double *__restrict__ pe, const double *__restrict__ pn,
                    double *__restrict__ out2)
 {
     __shared__ double se[16], sn[16];
     const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t lo = t * per;
-    const int64_t hi = (lo + per < n) ? lo + per : n;
     double e = 0.0, tr = 0.0;
-    for (int64_t i = lo; i < hi; i++) {
+    for (int64_t i = t; i < n; i += 1024) {
         e += pe[i];
         tr += pn[i];
     }
@@ -750,13 +752,21 @@ hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int ma
     // the bulk's words (or FP32 values) go through the matrix cores; an FP64
     // slab through the vector units
     const dim3 grid_m((unsigned)((max_npad + kThinRows - 1) / kThinRows), (unsigned)ngroups);
-#define SMX_TMM(KK)                                                                                          \
-    do {                                                                                                     \
-        if (mode == 0)                                                                                       \
-            hipLaunchKernelGGL((thin_mfma_kernel<0, KK>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
-        else                                                                                                 \
-            hipLaunchKernelGGL((thin_mfma_kernel<1, KK>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
-        return hipGetLastError();                                                                            \
+    // one 16-column block per pass when every group owns at most 16 columns
+#define SMX_TMM(KK)                                                                                             \
+    do {                                                                                                        \
+        if (max_own <= 16) {                                                                                    \
+            if (mode == 0)                                                                                      \
+                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+            else                                                                                                \
+                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+        } else {                                                                                                \
+            if (mode == 0)                                                                                      \
+                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+            else                                                                                                \
+                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+        }                                                                                                       \
+        return hipGetLastError();                                                                               \
     } while (0)
     switch (x_kind(xs)) {
     case X_F64: return thin_mul_k<X_F64>(st, mode, mw, grid, g0, groups, xs, z, o, y);
