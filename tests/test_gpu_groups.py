@@ -52,3 +52,20 @@ def test_kmeans_groups_match_oracle(smx, oracle_lib, precision):
           f"{smx.group_speedup(base)[1] / work:.3f}, {ms:.2f} ms (molecules {ms_mol:.2f} ms); "
           f"max|dD| on {pick} = {err:.2e}")
     assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("kT", [0.0, 0.02])
+def test_kmeans_groups_diagonalisation(smx, oracle_lib, kT):
+    """k-means groups of water16 (8 clusters) through the diagonalisation path
+    against the oracle on every group."""
+    base = water_config("water16")
+    gp, gb = smx.group_kmeans(base.coords, 8, box=base.meta["box"], seed=4)
+    s = regroup(base, gp, gb)
+    ref = oracle_lib.submatrix(s, kT=kT)
+    ctx = smx.Context(0).load(s).configure(precision="fp64", kT=kT, solver="eig")
+    r = ctx.evaluate()
+    ctx.close()
+    err = float(np.abs(r.d_values - ref.d_values).max())
+    print(f"water16 k-means 8 groups, kT = {kT}: max|dD| = {err:.2e}")
+    assert err <= TOL["fp64"]
+    assert abs(r.n_elec - ref.n_elec) <= 1e-9

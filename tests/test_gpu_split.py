@@ -110,3 +110,20 @@ def test_water256e_sampled_and_timed(smx, oracle_lib):
           f"molecule groups {ms_blk:.2f} ms; sum n^3 ratio (molecules / split) {work_blk / r['work']:.3f}; "
           f"max|dD| vs oracle on groups {pick} = {err:.2e}")
     assert err <= TOL["fp16x2"]
+
+
+def test_split_at_finite_temperature(smx, oracle_lib):
+    """The split problem through the diagonalisation path (kT = 0.05): the oracle's
+    split method with the Fermi function, element by element."""
+    s = water_config("water16e")
+    kT = 0.05
+    ref = oracle_lib.split_submatrix(s, EPS, kT=kT)
+    sp = smx.split_columns(s, EPS, merge=True)
+    ctx = smx.Context(0).load(sp).configure(precision="fp64", kT=kT)
+    r = ctx.evaluate()
+    d = smx.smx_get_d_expanded(ctx.handle, sp.src, len(s.values))
+    ctx.close()
+    err = float(np.abs(d - ref.d_values).max())
+    print(f"water16e split kT = {kT}: max|dD| = {err:.2e}, dN = {r.n_elec - ref.n_elec:.1e}")
+    assert err <= TOL["fp64"]
+    assert abs(r.n_elec - ref.n_elec) <= 1e-9 and abs(r.energy - ref.energy) <= 1e-9
