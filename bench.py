@@ -253,8 +253,8 @@ def main():
                          "done by default up to 8000 basis functions)")
     ap.add_argument("--backward", action="store_true",
                     help="also time the adjoint (dE/dK through the frozen map of the timed evaluation)")
-    ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1],
-                    help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch)")
+    ap.add_argument("--kernel-variant", type=int, default=0, choices=[0, 1, 2],
+                    help="operand stream of the word products (0: global_load_lds per K step, 1: register prefetch, 2: persistent launch over per-XCD work lists)")
     ap.add_argument("--kT", type=float, default=0.0,
                     help="electronic temperature in Hartree; kT > 0 times the diagonalisation path (Fermi D, FP64)")
     ap.add_argument("--iteration", default="ns2", choices=["ns2", "pade3"],

@@ -235,7 +235,11 @@ int32_t smx_set_tile_order(smx_ctx ctx, int32_t order);
  * Operand stream of the reduced-precision word products: 0 (default) loads
  * each K step of both operand panels straight into LDS and waits for it;
  * 1 loads the next K step into registers while the matrix cores work on the
- * current one from LDS (groups with 3 n_pad^2 >= 2^31 words fall back to 0).
+ * current one from LDS (groups with 3 n_pad^2 >= 2^31 words fall back to 0);
+ * 2 launches the Newton-Schulz products of 2-word FP16 and 1-word BF16 on the
+ * 128 x 128 bucket persistently: as many workgroups as the CUs hold, taking
+ * tiles from one work list per XCD through atomic counters (each starts with
+ * its own XCD's list, read from the hardware, then takes what the others left).
  * Results are bitwise the same.
  */
 int32_t smx_set_kernel_variant(smx_ctx ctx, int32_t variant);

@@ -119,6 +119,11 @@ struct Plan {
     std::vector<TileDesc> tiles_s, tiles_b;
     std::vector<int64_t> tiles_s_beg, tiles_b_beg;
     std::vector<double> wtiles2;       // live 16 x 16 blocks of one product on 256 x 256 tiles, per group
+    // per-XCD work lists of the 128 x 128 bucket for the persistent word products:
+    // wave w's lists start at tiles_sx[sx_wbeg[w]], list x at + xbeg[9 w + x]
+    std::vector<TileDesc> tiles_sx;
+    std::vector<int64_t> sx_wbeg;
+    std::vector<int32_t> xbeg;
     std::vector<int64_t> chunk_beg;    // wave w's gather chunks (chunks are in group order)
     std::vector<int64_t> plist;        // stored blocks of the own columns of each wave (more than one wave)
     std::vector<int64_t> plist_beg;
@@ -134,6 +139,8 @@ struct Plan {
 struct DevView {
     const GroupDesc *gd = nullptr;
     const TileDesc *tiles = nullptr, *tiles_s = nullptr, *tiles_b = nullptr;
+    const TileDesc *tiles_sx = nullptr;     // per-XCD lists of the persistent word products (context buffers only)
+    const int32_t *xbeg = nullptr;
     const int2 *chunks = nullptr;
     const RowInfo *rinfo = nullptr;
     const int32_t *bmap = nullptr, *boffs = nullptr, *own = nullptr;
@@ -198,7 +205,8 @@ struct smx_context {
     DevBuf<int32_t> d_brow, d_bcol;
     // device: plan
     DevBuf<GroupDesc> d_gd;
-    DevBuf<TileDesc> d_tiles, d_tiles_s, d_tiles_b;
+    DevBuf<TileDesc> d_tiles, d_tiles_s, d_tiles_b, d_tiles_sx;
+    DevBuf<int32_t> d_xbeg, d_tq;           // per-XCD list offsets, counters of the persistent word products
     DevBuf<int2> d_chunks;
     DevBuf<RowInfo> d_rinfo;
     DevBuf<int32_t> d_bmap, d_boffs;
@@ -213,6 +221,7 @@ struct smx_context {
                                             // 0: enqueue all max_iter steps, no host synchronisation
     int32_t tile_order = 0;                 // 0: XCD-aware launch order, 1: group by group
     int32_t kernel_variant = 0;             // operand stream of the word products (smx_set_kernel_variant)
+    int32_t pers_nwg = 0;                   // workgroups of a persistent word-product launch (0: not yet known)
     int32_t big_min_npad = kDefaultBigMinNpad;   // 256 x 256 tiles from this n_pad on (smx_set_tile_shape)
     DevBuf<unsigned long long> d_scale, d_resid;
     DevBuf<int32_t> d_done, d_kfinal, d_flags, d_ndone;
@@ -344,7 +353,9 @@ double *slab(smx_ctx c, int i) { return arena_base(c) + (size_t)i * (size_t)c->p
 // fetched into one L2 and shared by its tiles; groups are dealt to XCDs
 // greedily by work (n_pad x tiles), largest first.  Slot s of XCD x becomes
 // workgroup 8 s + x; short lists are padded with idle tiles (group -1).
-void xcd_order(const Plan &P, int32_t g0, int32_t g1, std::vector<TileDesc> &tiles)
+// The tiles of groups g0 .. g1 - 1 dealt to the 8 XCDs: all tiles of a group
+// to one XCD, groups largest first to the XCD with the least work so far.
+std::vector<std::vector<TileDesc>> xcd_deal(const Plan &P, int32_t g0, int32_t g1, const std::vector<TileDesc> &tiles)
 {
     constexpr int kXcd = 8;
     const int32_t ng = g1 - g0;
@@ -361,6 +372,13 @@ void xcd_order(const Plan &P, int32_t g0, int32_t g1, std::vector<TileDesc> &til
         load[best] += (double)P.gd[g].npad * per_group[g - g0].size();
         for (const TileDesc &t : per_group[g - g0]) lists[best].push_back(t);
     }
+    return lists;
+}
+
+void xcd_order(const Plan &P, int32_t g0, int32_t g1, std::vector<TileDesc> &tiles)
+{
+    constexpr int kXcd = 8;
+    const auto lists = xcd_deal(P, g0, g1, tiles);
     size_t len = 0;
     for (const auto &l : lists) len = std::max(len, l.size());
     tiles.assign(len * kXcd, TileDesc{-1, 0});
@@ -519,6 +537,9 @@ int32_t partition_waves(smx_ctx c, Plan &P, int64_t budget)
     P.tiles_b.clear();
     P.tiles_s_beg.assign(1, 0);
     P.tiles_b_beg.assign(1, 0);
+    P.tiles_sx.clear();
+    P.sx_wbeg.assign(1, 0);
+    P.xbeg.clear();
     P.big.assign((size_t)ng, 0);
     for (int32_t g = 0; g < ng; g++) P.big[g] = c->big_min_npad > 0 && P.gd[g].npad >= c->big_min_npad;
     P.chunk_beg.assign(1, 0);
@@ -548,6 +569,17 @@ int32_t partition_waves(smx_ctx c, Plan &P, int64_t budget)
         }
         P.work_elems = std::max(P.work_elems, e);
         P.thin_elems = std::max(P.thin_elems, t);
+        {
+            const auto lists = xcd_deal(P, P.wave_g[w], P.wave_g[w + 1], ts);
+            int32_t off = 0;
+            for (const auto &l : lists) {
+                P.xbeg.push_back(off);
+                P.tiles_sx.insert(P.tiles_sx.end(), l.begin(), l.end());
+                off += (int32_t)l.size();
+            }
+            P.xbeg.push_back(off);
+            P.sx_wbeg.push_back((int64_t)P.tiles_sx.size());
+        }
         if (c->tile_order == 0) {
             xcd_order(P, P.wave_g[w], P.wave_g[w + 1], tl);
             if (!ts.empty()) xcd_order(P, P.wave_g[w], P.wave_g[w + 1], ts);
@@ -726,6 +758,8 @@ int32_t ensure_plan(smx_ctx c)
     HIP_TRY(c, upload(c->d_tiles, P.tiles, c->stream));
     HIP_TRY(c, upload(c->d_tiles_s, P.tiles_s, c->stream));
     HIP_TRY(c, upload(c->d_tiles_b, P.tiles_b, c->stream));
+    HIP_TRY(c, upload(c->d_tiles_sx, P.tiles_sx, c->stream));
+    HIP_TRY(c, upload(c->d_xbeg, P.xbeg, c->stream));
     HIP_TRY(c, upload(c->d_tiles_full, P.tiles_full, c->stream));
     HIP_TRY(c, upload(c->d_plist, P.plist, c->stream));
     c->contrib_ready = false;
@@ -953,6 +987,9 @@ int32_t smx_destroy(smx_ctx c)
     c->d_gd.release();
     c->d_tiles.release();
     c->d_tiles_s.release();
+    c->d_tiles_sx.release();
+    c->d_xbeg.release();
+    c->d_tq.release();
     c->d_tiles_b.release();
     c->d_chunks.release();
     c->d_rinfo.release();
@@ -1194,7 +1231,7 @@ int32_t smx_set_debug_checks(smx_ctx c, int32_t on)
 int32_t smx_set_kernel_variant(smx_ctx c, int32_t variant)
 {
     if (!c) return SMX_E_INVALID;
-    if (variant != 0 && variant != 1) return fail(c, SMX_E_INVALID, "variant must be 0 or 1");
+    if (variant < 0 || variant > 2) return fail(c, SMX_E_INVALID, "variant must be 0, 1 or 2");
     if (variant != c->kernel_variant) drop_graphs(c);
     c->kernel_variant = variant;
     return SMX_OK;
@@ -1487,6 +1524,8 @@ DevView ctx_view(smx_ctx c)
     v.tiles = c->d_tiles.p;
     v.tiles_s = c->d_tiles_s.p;
     v.tiles_b = c->d_tiles_b.p;
+    v.tiles_sx = c->d_tiles_sx.p;
+    v.xbeg = c->d_xbeg.p;
     v.chunks = c->d_chunks.p;
     v.rinfo = c->d_rinfo.p;
     v.bmap = c->d_bmap.p;
@@ -1581,6 +1620,20 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
     // the register-prefetch stream indexes a group's words with 32-bit offsets
     const int32_t variant =
         (c->kernel_variant == 1 && (int64_t)std::max(nw, 1) * P.max_npad * P.max_npad < (int64_t)INT32_MAX) ? 1 : 0;
+    // persistent word products (variant 2): Newton-Schulz, 2-word FP16 or
+    // 1-word BF16, the 128 x 128 bucket, context buffers (not the static array)
+    const bool persistent = c->kernel_variant == 2 && mixed && !pade && !tangent && V.tiles_sx &&
+                            ((fmt == 0 && nw == 2) || (fmt == 1 && nw == 1));
+    int32_t pers_nwg = 0;
+    if (persistent) {
+        if (c->pers_nwg <= 0) {
+            hipDeviceProp_t prop;
+            HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+            c->pers_nwg = prop.multiProcessorCount * words_persistent_blocks_per_cu(fmt, nw);
+        }
+        pers_nwg = c->pers_nwg;
+        HIP_TRY(c, c->d_tq.ensure((size_t)(kmax + 1) * 16));
+    }
     if (use_graphs) {
         // replayable step graphs: valid while everything baked into their
         // launches (plan, buffers, mode and convergence settings) is unchanged
@@ -1613,6 +1666,8 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
         tr.push("smx gather");
         if (events) HIP_TRY(c, hipEventRecord(c->ev_wave[4 * wave], st));
         HIP_TRY(c, hipMemsetAsync(it.ndone, 0, sizeof(int32_t), st));
+        if (persistent)                         // the step launches (or their graphs) take fresh counters
+            HIP_TRY(c, hipMemsetAsync(c->d_tq.p, 0, sizeof(int32_t) * (size_t)(kmax + 1) * 16, st));
         const int nch = (int)(P.chunk_beg[wave + 1] - P.chunk_beg[wave]);
         const int2 *chs = V.chunks + P.chunk_beg[wave];
         if (!mixed) {
@@ -1674,6 +1729,12 @@ int32_t eval_enqueue(smx_ctx c, const EvalMode &m, const Plan &P, const DevView 
                     if (b.big)
                         r = run(kind256, [&] { return launch_ns_words256(s, fmt, nw, mode, b.n, b.tl, V.gd, x, y, o, it,
                                                                          k, c->switch_tol, kmax); });
+                    else if (persistent && mode <= 1)
+                        r = run(kind128, [&] {
+                            return launch_ns_words_persistent(s, fmt, nw, mode, pers_nwg, V.tiles_sx + P.sx_wbeg[wave],
+                                                              V.xbeg + 9 * wave, c->d_tq.p + ((size_t)k * 2 + mode) * 8,
+                                                              V.gd, x, y, o, it, k, c->switch_tol, kmax);
+                        });
                     else
                         r = run(kind128, [&] { return launch_ns_words(s, fmt, nw, mode, mode <= 1 ? variant : 0, b.n,
                                                                       b.tl, V.gd, x, y, o, it, k, c->switch_tol, kmax); });

@@ -152,6 +152,17 @@ __host__ __device__ inline int64_t word_pos(int nw, int ld, int r, int c)
     return (int64_t)c * ld * nw + (int64_t)(r >> 5) * (32 * nw) + (r & 31);
 }
 
+// Persistent form of the 128 x 128 word products (Newton-Schulz square and
+// update; 2-word FP16 and 1-word BF16): nwg workgroups take the tiles from
+// eight per-XCD lists tiles_x[xbeg[x] .. xbeg[x + 1]) through the counters
+// cnt[0 .. 8), which must be zero at launch.
+hipError_t launch_ns_words_persistent(hipStream_t st, int fmt, int nw, int mode, int nwg, const TileDesc *tiles_x,
+                                      const int32_t *xbeg, int32_t *cnt, const GroupDesc *groups,
+                                      const unsigned short *x, const unsigned short *b, unsigned short *out,
+                                      const IterState &it, int k, double switch_tol, int kmax);
+// Workgroups of the persistent word products one CU holds at once.
+int words_persistent_blocks_per_cu(int fmt, int nw);
+
 // Reduced-precision bulk products (fmt 0 = FP16, 1 = BF16; nw words per value;
 // fmt 2 = one FP32 value per element, column-major like the FP64 slabs).
 // mode 0: Newton-Schulz square (W = 1.5 I - 0.5 X^2, residual, 1 - T_ii);

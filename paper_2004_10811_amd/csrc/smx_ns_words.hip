@@ -297,17 +297,16 @@ __host__ __device__ constexpr int words_lds_bytes()
 // 128-B lines, eight lanes per column) while the matrix cores work on the
 // current one from LDS, then written to LDS in the same swizzled layout.
 template <int FMT, int NW, int MODE, int RP>
-__global__ __launch_bounds__(256, 2)
-void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
-                     const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
-                     unsigned short *__restrict__ out, IterState it, int k,
-                     double switch_tol, int kmax)
+__device__ __forceinline__ void ns_words_tile(const TileDesc td, const GroupDesc *__restrict__ groups,
+                                              const unsigned short *__restrict__ xin,
+                                              const unsigned short *__restrict__ bin,
+                                              unsigned short *__restrict__ out, const IterState &it, int k,
+                                              double switch_tol, int kmax)
 {
     __shared__ __attribute__((aligned(16))) unsigned char smem[words_lds_bytes<NW>()];
     unsigned short *Ls = reinterpret_cast<unsigned short *>(smem);   // [2 operands][NW][BM][BK]
     float *Cs = reinterpret_cast<float *>(smem);                     // staging after the K loop
 
-    const TileDesc td = tiles[blockIdx.x];
     const int g = td.x;
     if (g < 0) return;                  // idle slot of the launch order
     if (it.done[g]) return;
@@ -629,6 +628,50 @@ void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__rest
         rm = wave_max(rm);
         if (lane == 0)
             atomicMax(it.resid_bits + (int64_t)g * it.resid_stride + k, (unsigned long long)__double_as_longlong(rm));
+    }
+}
+
+// One 128 x 128 output tile per workgroup (grid = the launch order's tiles).
+template <int FMT, int NW, int MODE, int RP>
+__global__ __launch_bounds__(256, 2)
+void ns_words_kernel(const TileDesc *__restrict__ tiles, const GroupDesc *__restrict__ groups,
+                     const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
+                     unsigned short *__restrict__ out, IterState it, int k,
+                     double switch_tol, int kmax)
+{
+    ns_words_tile<FMT, NW, MODE, RP>(tiles[blockIdx.x], groups, xin, bin, out, it, k, switch_tol, kmax);
+}
+
+// Persistent launch: as many workgroups as the CUs hold at once, each taking
+// tiles from work lists, one per XCD (tiles of a group share one list, so
+// their operand panels meet in one L2), through an atomic counter per list.
+// A workgroup starts with the list of the XCD it runs on (hardware register
+// XCC_ID) and then takes what is left in the others, so every tile is taken
+// exactly once whatever the placement.  No workgroup waits on another: each
+// list's counter only grows, and a workgroup leaves once all eight are past
+// their ends.
+template <int FMT, int NW, int MODE>
+__global__ __launch_bounds__(256, 3)
+void ns_words_persistent(const TileDesc *__restrict__ tiles_x, const int32_t *__restrict__ xbeg,
+                         int32_t *__restrict__ cnt, const GroupDesc *__restrict__ groups,
+                         const unsigned short *__restrict__ xin, const unsigned short *__restrict__ bin,
+                         unsigned short *__restrict__ out, IterState it, int k, double switch_tol, int kmax)
+{
+    __shared__ int s_q;
+    // s_getreg of HW_REG_XCC_ID (id 20, bits 3:0)
+    const int x0 = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7);
+    for (int d = 0; d < 8; d++) {
+        const int x = (x0 + d) & 7;
+        const int base = xbeg[x], len = xbeg[x + 1] - base;
+        for (;;) {
+            if (threadIdx.x == 0) s_q = atomicAdd(cnt + x, 1);
+            __syncthreads();
+            const int q = s_q;
+            __syncthreads();                    // every lane has read s_q before it is taken again
+            if (q >= len) break;
+            ns_words_tile<FMT, NW, MODE, 0>(tiles_x[base + q], groups, xin, bin, out, it, k, switch_tol, kmax);
+            __syncthreads();                    // LDS free for the next tile
+        }
     }
 }
 
@@ -1219,6 +1262,42 @@ hipError_t launch_ns_words(hipStream_t st, int fmt, int nw, int mode, int varian
     if (fmt == 1 && nw == 1) return launch_words_t<1, 1>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     if (fmt == 1 && nw == 3) return launch_words_t<1, 3>(st, mode, variant, ntiles, tiles, groups, x, b, out, it, k, switch_tol, kmax);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_ns_words_persistent(hipStream_t st, int fmt, int nw, int mode, int nwg, const TileDesc *tiles_x,
+                                      const int32_t *xbeg, int32_t *cnt, const GroupDesc *groups,
+                                      const unsigned short *x, const unsigned short *b, unsigned short *out,
+                                      const IterState &it, int k, double switch_tol, int kmax)
+{
+    if (nwg <= 0) return hipSuccess;
+#define SMX_WP(F, N, M) hipLaunchKernelGGL((ns_words_persistent<F, N, M>), dim3(nwg), dim3(256), 0, st, tiles_x, xbeg, \
+                                           cnt, groups, x, b, out, it, k, switch_tol, kmax)
+#define SMX_WPM(F, N) switch (mode) {                                  \
+        case 0: SMX_WP(F, N, 0); break;                                    \
+        case 1: SMX_WP(F, N, 1); break;                                    \
+        default: return hipErrorInvalidValue;                              \
+        }
+    if (fmt == 0 && nw == 2) {
+        SMX_WPM(0, 2)
+    } else if (fmt == 1 && nw == 1) {
+        SMX_WPM(1, 1)
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef SMX_WPM
+#undef SMX_WP
+    return hipGetLastError();
+}
+
+int words_persistent_blocks_per_cu(int fmt, int nw)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (fmt == 0 && nw == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_words_persistent<0, 2, 0>, 256, 0);
+    else if (fmt == 1 && nw == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ns_words_persistent<1, 1, 0>, 256, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 2;
 }
 
 hipError_t launch_ns_words256(hipStream_t st, int fmt, int nw, int mode, int ntiles, const TileDesc *tiles,

@@ -146,3 +146,21 @@ def test_autotune_word_buckets(smx, oracle_lib, tmp_path, monkeypatch):
     ctx2.close()
     refo = oracle_lib.submatrix(s)
     assert float(np.abs(res.d_values - refo.d_values).max()) <= TOL_MIXED
+
+
+@pytest.mark.parametrize("precision", ["fp16x2", "bf16"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_kernel_variants_bitwise_equal(smx, precision, variant):
+    """smx_set_kernel_variant: the register-prefetch operand stream (1) and the
+    persistent launch over per-XCD work lists (2) give bitwise the results of
+    the default launch, with direct launches and with step graphs."""
+    s = ragged_system(85)
+    ref = run(smx, s, precision, 0)
+    for graph_steps in (0, 2):
+        ctx = smx.Context(0).load(s).configure(precision=precision, graph_steps=graph_steps)
+        smx.smx_set_kernel_variant(ctx.handle, variant)
+        for _ in range(2):                        # a second evaluation reuses counters / graphs
+            r = ctx.evaluate(allow_not_converged=True)
+            assert np.array_equal(r.d_values, ref["d"]) and r.n_elec == ref["n"] and r.energy == ref["e"]
+        assert np.array_equal(ctx.group_info()["iters"], ref["info"]["iters"])
+        ctx.close()
