@@ -687,8 +687,9 @@ void ns_words_persistent(const TileDesc *__restrict__ tiles_x, const int32_t *__
 // cores work on step t.  Per output element the sequence of matrix-core
 // operations (K steps in order, word pairs least significant first) is the
 // one of the 128 x 128 kernel, so both tile shapes give the same bits.
-// Blocks of 16 x 16 that lie above the diagonal of a diagonal tile, or
-// outside the matrix, are not computed (their results are never stored).
+// A wave whose 64 x 128 part lies wholly above the diagonal of a diagonal
+// tile, or outside the matrix, does no products, and operand column groups
+// wholly outside the matrix are not loaded (no output they feed is stored).
 constexpr int BM2 = 256;
 constexpr int CST2 = 260;          // column-major staging of a 64-column quarter: 1040-B columns
 
