@@ -356,20 +356,27 @@ __device__ inline double tm_value(const u4 *raw, int t)
     }
 }
 
+// Work item w = (group w / gx, row block w % gx).  The grid is a multiple of 8
+// workgroups, which the hardware deals round-robin over the 8 XCDs; workgroup
+// L takes item (L % 8) * (grid / 8) + L / 8, so that each XCD works through
+// one contiguous range of items and the row blocks of a group share the XCD's
+// L2 for their reads of the group's Z.
 template <int MODE, int K, int CB>
 __global__ __launch_bounds__(256)
 void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const double *__restrict__ z,
-                      const double *__restrict__ o, double *__restrict__ y, int g0)
+                      const double *__restrict__ o, double *__restrict__ y, int g0, int gx, int nwork)
 {
     constexpr int KC = 128;                           // rows of Z per LDS stage
     constexpr int ZS = 33;                            // LDS row stride of the staged Z (doubles)
     constexpr int NL = tm_loads<K>();
     constexpr int RB = kThinRB;
     __shared__ double zs[KC * ZS];
-    const int g = g0 + blockIdx.y;
+    const int item = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (item >= nwork) return;                        // padding of the grid to a multiple of 8
+    const int g = g0 + item / gx;
     const GroupDesc gd = groups[g];
     const int npad = gd.npad;
-    const int row0 = blockIdx.x * (64 * RB);
+    const int row0 = (item % gx) * (64 * RB);
     if (row0 >= npad) return;                         // whole workgroup beyond this group
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -407,8 +414,11 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
             if (kt % (KC / 32) == 0) {
                 const int ks = kt * 32;
                 __syncthreads();                      // every wave is done with the previous stage
+                // consecutive lanes take consecutive rows of one column of Z
+                // (coalesced reads; the LDS writes, 33 doubles apart, are at
+                // most two-way bank conflicted)
                 for (int u = tid; u < KC * 32; u += 256) {
-                    const int kk = u >> 5, cc = u & 31, kr = ks + kk, col = c0 + cc;
+                    const int kk = u & (KC - 1), cc = u / KC, kr = ks + kk, col = c0 + cc;
                     zs[kk * ZS + cc] = (kr < gd.n && col < gd.m_own) ? z[gd.thin_off + kr + (int64_t)col * npad] * zscale
                                                                      : 0.0;
                 }
@@ -751,20 +761,22 @@ hipError_t launch_thin_mul(hipStream_t st, int mode, int g0, int ngroups, int ma
     const int mw = max_own <= 8 ? 8 : (max_own <= 16 ? 16 : (max_own <= 24 ? 24 : 32));
     // the bulk's words (or FP32 values) go through the matrix cores; an FP64
     // slab through the vector units
-    const dim3 grid_m((unsigned)((max_npad + kThinRows - 1) / kThinRows), (unsigned)ngroups);
+    const int gx = (max_npad + kThinRows - 1) / kThinRows;
+    const int nwork = gx * ngroups;
+    const dim3 grid_m((unsigned)((nwork + 7) / 8 * 8));
     // one 16-column block per pass when every group owns at most 16 columns
 #define SMX_TMM(KK)                                                                                             \
     do {                                                                                                        \
         if (max_own <= 16) {                                                                                    \
             if (mode == 0)                                                                                      \
-                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0, gx, nwork); \
             else                                                                                                \
-                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 1>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0, gx, nwork); \
         } else {                                                                                                \
             if (mode == 0)                                                                                      \
-                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+                hipLaunchKernelGGL((thin_mfma_kernel<0, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0, gx, nwork); \
             else                                                                                                \
-                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0); \
+                hipLaunchKernelGGL((thin_mfma_kernel<1, KK, 2>), grid_m, dim3(256), 0, st, groups, xs, z, o, y, g0, gx, nwork); \
         }                                                                                                       \
         return hipGetLastError();                                                                               \
     } while (0)
