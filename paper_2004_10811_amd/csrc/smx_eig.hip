@@ -6,7 +6,7 @@
 //
 // Four stages, each one launch over all groups of a wave:
 //   1. Householder reduction A_g = Q T Q^T to symmetric tridiagonal form, one
-//      1024-lane workgroup per group (the reflectors stay in the slab, below
+//      512-lane workgroup per group (the reflectors stay in the slab, below
 //      the subdiagonal, as in LAPACK's sytrd), then splitting of T where an
 //      off-diagonal entry is negligible;
 //   2. eigenvalues of T by bisection on Sturm counts, one lane per eigenvalue
@@ -27,11 +27,15 @@ namespace smx {
 
 namespace {
 
-constexpr int kEigBlock = 1024;     // lanes of the reduction workgroups
+// lanes of the reduction workgroups: two waves per SIMD, so that the
+// compiler may hold 256 registers and keep eight loads per lane in flight in
+// the row dots of A_s v (at 1024 lanes and 128 registers it issued them one
+// at a time)
+constexpr int kEigBlock = 512;
 constexpr int kReflBlock = 512;     // lanes of the reflector workgroups (two waves per SIMD: 256 registers)
 
-// Sum over a 1024-lane workgroup in a fixed order (lanes by a xor tree, lane
-// 0's value per wave, then the 16 waves in order); every lane gets the same bits.
+// Sum over a kEigBlock-lane workgroup in a fixed order (lanes by a xor tree, lane
+// 0's value per wave, then the waves in order); every lane gets the same bits.
 __device__ inline double block_sum(double v, double *red)
 {
     const int tid = threadIdx.x;
@@ -157,7 +161,7 @@ void tridiag_kernel(const GroupDesc *__restrict__ groups, int g0, double *__rest
                 __syncthreads();
                 // p = tau (A_s v - V (W^T v) - W (V^T v)).  A_s v: the lanes of a
                 // row slot read consecutive rows of a column (coalesced); while the
-                // trailing block has at most 1024 rows, the columns are split into
+                // trailing block has at most kEigBlock rows, the columns are split into
                 // kEigBlock / (rows rounded up to 64) parts so every lane streams,
                 // and the parts' sums are added in order
                 const int R = n - k - 1;
