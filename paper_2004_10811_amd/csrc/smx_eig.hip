@@ -224,12 +224,22 @@ void tridiag_kernel(const GroupDesc *__restrict__ groups, int g0, double *__rest
                     vr[q] = q < nb ? V[r + (int64_t)q * ld] : 0.0;
                     wr[q] = q < nb ? W[r + (int64_t)q * ld] : 0.0;
                 }
-                for (int cl = 0; cl < ncol; cl++) {
-                    double *ac = A + r + (int64_t)(c0 + cl) * ld;
-                    double s = *ac;
+                // eight columns' entries of the row (this lane's alone; V's columns
+                // lie left of k1) are loaded together, then updated and stored
+                for (int cb = 0; cb < ncol; cb += 8) {
+                    double av[8];
 #pragma unroll
-                    for (int q = 0; q < kPanel; q++) s -= vr[q] * vwc[cl][kPanel + q] + wr[q] * vwc[cl][q];
-                    *ac = s;
+                    for (int u = 0; u < 8; u++)
+                        av[u] = cb + u < ncol ? A[r + (int64_t)(c0 + cb + u) * ld] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        if (cb + u >= ncol) break;
+                        const int cl = cb + u;
+                        double s = av[u];
+#pragma unroll
+                        for (int q = 0; q < kPanel; q++) s -= vr[q] * vwc[cl][kPanel + q] + wr[q] * vwc[cl][q];
+                        A[r + (int64_t)(c0 + cl) * ld] = s;
+                    }
                 }
             }
         }
