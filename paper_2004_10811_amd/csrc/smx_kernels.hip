@@ -362,7 +362,7 @@ __device__ inline double tm_value(const u4 *raw, int t)
 // one contiguous range of items and the row blocks of a group share the XCD's
 // L2 for their reads of the group's Z.
 template <int MODE, int K, int CB>
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__(256, 3)
 void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const double *__restrict__ z,
                       const double *__restrict__ o, double *__restrict__ y, int g0, int gx, int nwork)
 {
@@ -416,11 +416,29 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
                 __syncthreads();                      // every wave is done with the previous stage
                 // consecutive lanes take consecutive rows of one column of Z
                 // (coalesced reads; the LDS writes, 33 doubles apart, are at
-                // most two-way bank conflicted)
-                for (int u = tid; u < KC * 32; u += 256) {
-                    const int kk = u & (KC - 1), cc = u / KC, kr = ks + kk, col = c0 + cc;
-                    zs[kk * ZS + cc] = (kr < gd.n && col < gd.m_own) ? z[gd.thin_off + kr + (int64_t)col * npad] * zscale
-                                                                     : 0.0;
+                // most two-way bank conflicted).  A lane keeps one row kk of Z
+                // and takes columns tid / KC + 2 m; its loads go out ZB at a time,
+                // all in flight before their LDS writes (every lane loads: rows
+                // and columns outside Z read its last row or column, and the
+                // value is replaced by zero afterwards)
+                constexpr int ZU = KC * 32 / 256, ZB = 8;
+                const int kk = tid & (KC - 1), kr = ks + kk;
+                const double *zr = z + gd.thin_off + min(kr, gd.n - 1);
+#pragma unroll
+                for (int m0 = 0; m0 < ZU; m0 += ZB) {
+                    double zv[ZB];
+#pragma unroll
+                    for (int m = 0; m < ZB; m++) {
+                        const int col = c0 + tid / KC + 2 * (m0 + m);
+                        zv[m] = zr[(int64_t)min(col, gd.m_own - 1) * npad];
+                    }
+#pragma unroll
+                    for (int m = 0; m < ZB; m++) {
+                        const int col = c0 + tid / KC + 2 * (m0 + m);
+                        if (!(kr < gd.n && col < gd.m_own)) zv[m] = 0.0;
+                    }
+#pragma unroll
+                    for (int m = 0; m < ZB; m++) zs[kk * ZS + tid / KC + 2 * (m0 + m)] = zv[m] * zscale;
                 }
                 __syncthreads();
             }
