@@ -195,9 +195,9 @@ PEAK_BY_KERNEL = {"ns_f64_kernel": ("fp64", 78.6), "ns_words_kernel": ("fp16/bf1
 # The same runs give the matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES
 # over 1024 SIMDs x 2.4 GHz x kernel time).
 TRAFFIC = {
-    ("water1024", "ns_words_kernel"): (8.164e9, ("smx_ns_words.hip", "smx_internal.h"), "f1997adf317ed1f7",
+    ("water1024", "ns_words_kernel"): (8.164e9, ("smx_ns_words.hip", "smx_internal.h"), "9cfd87bdfd482aeb",
                                        "profiles/ns_words_kernel_water1024_fp16x2.md", 0.300),
-    ("water1024", "ns_f64_kernel"): (19.29e9, ("smx_ns_f64.hip", "smx_internal.h"), "d2687816b438a676",
+    ("water1024", "ns_f64_kernel"): (19.29e9, ("smx_ns_f64.hip", "smx_internal.h"), "7739624ee052bcd3",
                                      "profiles/ns_f64_kernel_water1024_fp64.md", 0.684),
 }
 

@@ -84,13 +84,28 @@ __device__ inline double gather_row(const GroupDesc &gd, int r, const RowInfo *_
         const int c0 = bo[cb];
         const int bc = bo[cb + 1] - c0;
         const int32_t p = real ? map_row[(int64_t)gd.m * cb] : -1;
-        const double *src = (p >= 0) ? kvals + valoff[p] + rr : nullptr;
-        for (int cc = 0; cc < bc; cc++) {
-            const int c = c0 + cc;
-            double v = (p >= 0) ? src[(int64_t)cc * br] : 0.0;
-            if (r == c) v -= mu;
-            rowsum += fabs(v);
-            emit(c, v);
+        // Every lane loads (an unstored block or a padding row reads K's first
+        // value and uses zero), eight columns of the block row at a time, so
+        // that the loads are in flight together rather than one by one.
+        const double *src = kvals + ((p >= 0) ? valoff[p] + rr : 0);
+        const int64_t stride = (p >= 0) ? br : 0;
+        for (int cc0 = 0; cc0 < bc; cc0 += 8) {
+            double vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) vb[u] = src[(int64_t)min(cc0 + u, bc - 1) * stride];
+            // an empty statement that takes all eight values keeps the compiler
+            // from sinking each load to its (conditional) use
+#pragma unroll
+            for (int u = 0; u < 8; u++) asm volatile("" ::"v"(vb[u]));
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (cc0 + u >= bc) break;
+                const int c = c0 + cc0 + u;
+                double v = (p >= 0) ? vb[u] : 0.0;
+                if (r == c) v -= mu;
+                rowsum += fabs(v);
+                emit(c, v);
+            }
         }
     }
     return real ? rowsum : 0.0;
