@@ -246,7 +246,8 @@ def main():
     ap.add_argument("--workload", default="water1024", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp16x2", choices=sorted(DTYPES))
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="groups in the CPU oracle sample (default: one per thread)")
+                    help="groups in the CPU oracle sample (default: two per thread, about 15 s on 16 host threads "
+                         "for water1024)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--full-sign", action="store_true",
                     help="also report the error against the exact sign of the whole K (dense eigendecomposition; "
@@ -464,9 +465,10 @@ def main():
         out["literal_bf16_water16"] = lit
     if not args.no_cpu_baseline:
         nth = min(16, os.cpu_count() or 1)
-        progress(f"CPU oracle on a sample of {args.cpu_sample or nth} submatrices, {nth} threads")
+        nsamp = args.cpu_sample or 2 * nth
+        progress(f"CPU oracle on a sample of {nsamp} submatrices, {nth} threads")
         base, err, pick = cpu_baseline(system, d_out.cpu().numpy(), r64["info"]["iters"], r64["info"]["n"],
-                                       nth, args.cpu_sample or nth, kT=args.kT)
+                                       nth, nsamp, kT=args.kT)
         out["cpu_baseline"] = base
         out["max_abs_dD_vs_oracle_on_sample"] = err
         if "literal_bf16_water16" in out:
