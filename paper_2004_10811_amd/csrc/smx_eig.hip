@@ -294,14 +294,14 @@ __global__ void split_kernel(const GroupDesc *__restrict__ groups, int g0, int n
 
 // Number of eigenvalues of the block T[s:t, s:t] below x (Sylvester inertia of
 // T - x I from its LDL^T pivots); pivots smaller than pivmin are replaced by
-// -pivmin.
-__device__ inline int sturm_count(const double *d, const double *e, int s, int t, double x, double pivmin)
+// -pivmin.  e2[i] = e[i]^2 (d and e2 staged in LDS by the caller).
+__device__ inline int sturm_count(const double *d, const double *e2, int s, int t, double x, double pivmin)
 {
     double q = d[s] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
     for (int i = s + 1; i < t; i++) {
-        q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+        q = (d[i] - x) - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
     }
@@ -311,15 +311,25 @@ __device__ inline int sturm_count(const double *d, const double *e, int s, int t
 // ---- 2. eigenvalues by bisection --------------------------------------------
 // Lane l of group g finds the (l - s)-th smallest eigenvalue of its block
 // [s, t) (ascending within each block), inside the block's Gershgorin
-// interval, to the width of a few units in the last place.
+// interval, to the width of a few units in the last place.  The workgroup
+// first stages d and e^2 of its group in LDS: every Sturm count then reads
+// them there (the lanes of a wave mostly at the same index: broadcasts)
+// instead of waiting on a global load per recurrence step.
 __global__ __launch_bounds__(256)
 void bisect_kernel(const GroupDesc *__restrict__ groups, int g0, EigVecs ev)
 {
+    __shared__ double ds[kEigMaxN], e2s[kEigMaxN];
     const int g = g0 + blockIdx.y;
     const GroupDesc gd = groups[g];
     const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= gd.n) return;
+    if (blockIdx.x * 256 >= gd.n) return;             // whole workgroup beyond this group
     const double *d = ev.d + gd.rinfo_off, *e = ev.e + gd.rinfo_off;
+    for (int i = threadIdx.x; i < gd.n; i += 256) {
+        ds[i] = d[i];
+        e2s[i] = e[i] * e[i];
+    }
+    __syncthreads();
+    if (l >= gd.n) return;
     const int s = ev.bs[gd.rinfo_off + l], t = ev.be[gd.rinfo_off + l], m = l - s;
     double lo = 1.7976931348623157e308, hi = -1.7976931348623157e308, tn = 0.0, emax = 0.0;
     for (int i = s; i < t; i++) {
@@ -338,7 +348,7 @@ void bisect_kernel(const GroupDesc *__restrict__ groups, int g0, EigVecs ev)
         const double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
         if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + 2.220446049250313e-16 * tn + pivmin) break;
-        if (sturm_count(d, e, s, t, mid, pivmin) > m) hi = mid;
+        if (sturm_count(ds, e2s, s, t, mid, pivmin) > m) hi = mid;
         else lo = mid;
     }
     ev.lam[gd.rinfo_off + l] = 0.5 * (lo + hi);
