@@ -54,6 +54,19 @@ __device__ inline double wave_sum0(double v)
     return __shfl(v, 0, 64);
 }
 
+// Workgroup barrier for an exchange through LDS only: waits for this wave's
+// LDS accesses, not for its global loads (__syncthreads() also waits for
+// every outstanding global load, which would void a prefetch issued before
+// it); the empty asm statements keep the compiler from moving LDS accesses
+// across it.
+__device__ inline void lds_only_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0), vmcnt and expcnt left at their maxima
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // ---- 1. Householder tridiagonalisation --------------------------------------
 // Step k (0 <= k < n - 2): x = A[k+1:, k]; the reflector H_k = I - tau v v^T
 // (v_0 = 1) maps x to beta e_1 (beta = -sign(x_0) ||x||, tau = (beta - x_0) /
@@ -547,29 +560,43 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
 #pragma unroll
         for (int c = 0; c < kReflCols; c++) yr[q][c] = (i < n && c < nc) ? yb[i + (int64_t)c * ld] : 0.0;
     }
-    for (int step = 0; step + 2 < n; step++) {
+    // The next step's reflector and tau are loaded while this step's dot
+    // products are reduced (the reflectors do not change); two register sets
+    // take turns, so that no step waits on a memory round trip before its
+    // products.
+    // (every lane loads, rows beyond n reading row n - 1, so that the loads
+    // sit outside any branch; rows outside the reflector are masked to zero
+    // where they are used)
+    auto load_v = [&](int step, double (&dst)[R], double &tdst) {
         const int k = FORWARD ? step : n - 3 - step;
-        const double t = tau[k];
-        if (t == 0.0) continue;
         const double *v = A + (int64_t)k * ld;
+        tdst = tau[k];
+#pragma unroll
+        for (int q = 0; q < R; q++) dst[q] = v[min(tid + kReflBlock * q, n - 1)];
+    };
+    auto apply = [&](int step, const double (&vl)[R], double t) {
+        if (t == 0.0) return;
+        const int k = FORWARD ? step : n - 3 - step;
         double vr[R];
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const int i = tid + kReflBlock * q;
+            vr[q] = (i > k && i < n) ? vl[q] : 0.0;
+        }
         double part[kReflCols];
 #pragma unroll
         for (int c = 0; c < kReflCols; c++) part[c] = 0.0;
 #pragma unroll
-        for (int q = 0; q < R; q++) {
-            const int i = tid + kReflBlock * q;
-            vr[q] = (i > k && i < n) ? v[i] : 0.0;
+        for (int q = 0; q < R; q++)
 #pragma unroll
             for (int c = 0; c < kReflCols; c++) part[c] += vr[q] * yr[q][c];
-        }
 #pragma unroll
         for (int c = 0; c < kReflCols; c++) {
             double s = part[c];
             for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
             if (lane == 0) red[wave][c] = s;
         }
-        __syncthreads();
+        lds_only_barrier();
         double sv[kReflCols];
 #pragma unroll
         for (int c = 0; c < kReflCols; c++) {
@@ -577,11 +604,23 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
             for (int w = 0; w < NWV; w++) s += red[w][c];
             sv[c] = t * s;
         }
-        __syncthreads();
+        lds_only_barrier();
 #pragma unroll
         for (int q = 0; q < R; q++)
 #pragma unroll
             for (int c = 0; c < kReflCols; c++) yr[q][c] -= sv[c] * vr[q];
+    };
+    const int nsteps = n - 2;
+    double va[R], vb[R], ta = 0.0, tb = 0.0;
+    if (nsteps > 0) load_v(0, va, ta);
+    // (the loads are unconditional, the last step's reflector read again at
+    // the end, so that the wait counts stay exact across the loop)
+    for (int st = 0; st < nsteps; st += 2) {
+        load_v(min(st + 1, nsteps - 1), vb, tb);
+        apply(st, va, ta);
+        if (st + 1 >= nsteps) break;
+        load_v(min(st + 2, nsteps - 1), va, ta);
+        apply(st + 1, vb, tb);
     }
 #pragma unroll
     for (int q = 0; q < R; q++) {
