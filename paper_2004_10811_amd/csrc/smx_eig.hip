@@ -54,19 +54,6 @@ __device__ inline double wave_sum0(double v)
     return __shfl(v, 0, 64);
 }
 
-// Workgroup barrier for an exchange through LDS only: waits for this wave's
-// LDS accesses, not for its global loads (__syncthreads() also waits for
-// every outstanding global load, which would void a prefetch issued before
-// it); the empty asm statements keep the compiler from moving LDS accesses
-// across it.
-__device__ inline void lds_only_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0), vmcnt and expcnt left at their maxima
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
 // ---- 1. Householder tridiagonalisation --------------------------------------
 // Step k (0 <= k < n - 2): x = A[k+1:, k]; the reflector H_k = I - tau v v^T
 // (v_0 = 1) maps x to beta e_1 (beta = -sign(x_0) ||x||, tau = (beta - x_0) /
@@ -563,7 +550,8 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
     // The next step's reflector and tau are loaded while this step's dot
     // products are reduced (the reflectors do not change); two register sets
     // take turns, so that no step waits on a memory round trip before its
-    // products.
+    // products (the barriers of a step wait for LDS accesses, not for these
+    // loads).
     // (every lane loads, rows beyond n reading row n - 1, so that the loads
     // sit outside any branch; rows outside the reflector are masked to zero
     // where they are used)
@@ -596,7 +584,7 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
             for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
             if (lane == 0) red[wave][c] = s;
         }
-        lds_only_barrier();
+        __syncthreads();
         double sv[kReflCols];
 #pragma unroll
         for (int c = 0; c < kReflCols; c++) {
@@ -604,7 +592,7 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
             for (int w = 0; w < NWV; w++) s += red[w][c];
             sv[c] = t * s;
         }
-        lds_only_barrier();
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < R; q++)
 #pragma unroll
@@ -614,7 +602,8 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
     double va[R], vb[R], ta = 0.0, tb = 0.0;
     if (nsteps > 0) load_v(0, va, ta);
     // (the loads are unconditional, the last step's reflector read again at
-    // the end, so that the wait counts stay exact across the loop)
+    // the end: loads issued under a branch made the compiler wait for every
+    // outstanding load where the paths join)
     for (int st = 0; st < nsteps; st += 2) {
         load_v(min(st + 1, nsteps - 1), vb, tb);
         apply(st, va, ta);
