@@ -443,11 +443,15 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
                 __syncthreads();
             }
             if (!live) return;
-            if (kt + 1 < nk) {
+            // the next step's words (unconditionally: the last step reloads its
+            // own, so that no load sits under a branch, where the compiler would
+            // wait for it at once)
+            {
+                const int kn = min(kt + 1, nk - 1) * 32;
 #pragma unroll
                 for (int b = 0; b < RB; b++)
 #pragma unroll
-                    for (int w = 0; w < NL; w++) rn[b][w] = *src(b, (kt + 1) * 32, w);
+                    for (int w = 0; w < NL; w++) rn[b][w] = *src(b, kn, w);
             }
             const double *zr = zs + ((kt % (KC / 32)) * 32 + 8 * q) * ZS + li;
 #pragma unroll
