@@ -224,22 +224,34 @@ void tridiag_kernel(const GroupDesc *__restrict__ groups, int g0, double *__rest
                     vr[q] = q < nb ? V[r + (int64_t)q * ld] : 0.0;
                     wr[q] = q < nb ? W[r + (int64_t)q * ld] : 0.0;
                 }
-                // eight columns' entries of the row (this lane's alone; V's columns
-                // lie left of k1) are loaded together, then updated and stored
-                for (int cb = 0; cb < ncol; cb += 8) {
-                    double av[8];
+                // Eight columns' entries of the row at a time (the row is this
+                // lane's alone, and V's columns lie left of k1); the next eight
+                // are loaded, unconditionally (columns past the chunk read its last
+                // one), before this batch is updated and stored, into two
+                // register sets in turn, so no load waits behind the stores.
+                auto load8 = [&](int cb, double (&dst)[8]) {
 #pragma unroll
-                    for (int u = 0; u < 8; u++)
-                        av[u] = cb + u < ncol ? A[r + (int64_t)(c0 + cb + u) * ld] : 0.0;
+                    for (int u = 0; u < 8; u++) dst[u] = A[r + (int64_t)(c0 + min(cb + u, ncol - 1)) * ld];
+                };
+                auto update8 = [&](int cb, const double (&src)[8]) {
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
                         if (cb + u >= ncol) break;
                         const int cl = cb + u;
-                        double s = av[u];
+                        double s = src[u];
 #pragma unroll
                         for (int q = 0; q < kPanel; q++) s -= vr[q] * vwc[cl][kPanel + q] + wr[q] * vwc[cl][q];
                         A[r + (int64_t)(c0 + cl) * ld] = s;
                     }
+                };
+                double ba[8], bb[8];
+                load8(0, ba);
+                for (int cb = 0; cb < ncol; cb += 16) {
+                    load8(cb + 8, bb);
+                    update8(cb, ba);
+                    if (cb + 8 >= ncol) break;
+                    load8(cb + 16, ba);
+                    update8(cb + 8, bb);
                 }
             }
         }
