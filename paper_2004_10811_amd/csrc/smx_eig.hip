@@ -563,10 +563,9 @@ void reflect_kernel(const GroupDesc *__restrict__ groups, int g0, const double *
     // products are reduced (the reflectors do not change); two register sets
     // take turns, so that no step waits on a memory round trip before its
     // products (the barriers of a step wait for LDS accesses, not for these
-    // loads).
-    // (every lane loads, rows beyond n reading row n - 1, so that the loads
-    // sit outside any branch; rows outside the reflector are masked to zero
-    // where they are used)
+    // loads).  Every lane loads, rows beyond n reading row n - 1, so that the
+    // loads sit outside any branch; rows outside the reflector are masked to
+    // zero where they are used.
     auto load_v = [&](int step, double (&dst)[R], double &tdst) {
         const int k = FORWARD ? step : n - 3 - step;
         const double *v = A + (int64_t)k * ld;

@@ -421,6 +421,7 @@ void thin_mfma_kernel(const GroupDesc *__restrict__ groups, XSource xs, const do
                 // all in flight before their LDS writes (every lane loads: rows
                 // and columns outside Z read its last row or column, and the
                 // value is replaced by zero afterwards)
+                static_assert(256 == 2 * KC, "a lane's row kk = tid % KC, its first column tid / KC in {0, 1}");
                 constexpr int ZU = KC * 32 / 256, ZB = 8;
                 const int kk = tid & (KC - 1), kr = ks + kk;
                 const double *zr = z + gd.thin_off + min(kr, gd.n - 1);
