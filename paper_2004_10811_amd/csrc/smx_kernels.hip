@@ -330,7 +330,8 @@ void thin_mul_kernel(const GroupDesc *__restrict__ groups, XSource xs,
 template <int K>
 __device__ constexpr int tm_loads() { return K == X_F32 ? 2 : x_nw<K>(); }
 // 16-row blocks per wave: two keep the kernel at three waves per SIMD (four
-// took two waves per SIMD and ran 0.9% slower per D on water1024)
+// took two waves per SIMD and ran 0.9% slower per D on water1024; one, at four
+// waves per SIMD, 5% slower per launch)
 constexpr int kThinRB = 2;
 constexpr int kThinRows = 64 * kThinRB;                // output rows per workgroup
 
